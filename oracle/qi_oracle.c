@@ -1,0 +1,371 @@
+/*
+ * qi_oracle.c -- plain FP64 CPU oracle for the synchronous quantum-inspired
+ * (QI) low-energy search (Ueda, Otsuka, Yunoki, arXiv:2010.00180).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may call this code:
+ * only the tests, the smoke check and the benchmark's CPU-baseline leg use it.
+ * It shares no code, header, table or helper with the HIP library.
+ *
+ * What it computes, in the paper's terms:
+ *   - energy  E(x) = sum_{i<j} J_ij s_i s_j + sum_i h_i s_i          (Eq. 1)
+ *     with s_i = +1 for sigma_i = 0 and s_i = -1 for sigma_i = 1, and the
+ *     state integer psi = sum_i 2^i sigma_i                             (Eq. 15)
+ *   - spin flips by XOR of the state integer with sum_k 2^{i_k}         (Alg. 1)
+ *   - the neighbourhood of x: x itself, all N single flips and all
+ *     N(N-1)/2 pair flips (i<j), i.e. the states reached by H_tot with the
+ *     one- and two-body sigma^x terms of H1                              (Eq. 9, Eq. 16)
+ *   - the energy of a flipped state from its parent's energy in O(N), using
+ *     only the couplings of the flipped sites                            (Sec. III, cost paragraph)
+ *   - one synchronous step: keep the M lowest distinct states of the union
+ *     of the neighbourhoods of the kept states; in the infinitesimal-lambda
+ *     limit the p_{M',k} selection reduces to this energy order       (Sec. II, Eqs. 9-14)
+ *   - repeat until the kept set no longer changes                        (Sec. II)
+ *   - independent searches from L initial states merged into the M lowest
+ *     distinct states of the union of their kept sets                    (Alg. 4)
+ *
+ * Readings where the paper leaves a choice open:
+ *   - ties in energy are broken by the state integer psi (smaller first), so
+ *     the kept set is unique; the paper keeps arrival order;
+ *   - a state already in the kept set never enters twice (distinctness);
+ *   - "literal" mode expands every kept state each step; "frontier" mode
+ *     expands only states that entered in the previous step.  Both give the
+ *     same sets (children of an old member were already offered one step
+ *     earlier and either entered or ranked behind the whole kept set).
+ *
+ * Exactness: inputs on the 2^-24 grid with modest magnitudes make every sum
+ * here exact in FP64, so the result does not depend on summation order.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static int words_of(int N) { return (N + 63) / 64; }
+
+static int spin_of(const uint64_t *x, int i)
+{
+    return ((x[i >> 6] >> (i & 63)) & 1u) ? -1 : +1;
+}
+
+/* Eq. 1 written out: pairs i<j, then the field term. */
+double qo_energy(int N, const double *J, const double *h, const uint64_t *x)
+{
+    double e = 0.0;
+    for (int i = 0; i < N; ++i) {
+        int si = spin_of(x, i);
+        for (int j = i + 1; j < N; ++j)
+            e += J[(size_t)i * N + j] * (double)(si * spin_of(x, j));
+    }
+    for (int i = 0; i < N; ++i)
+        e += h[i] * (double)spin_of(x, i);
+    return e;
+}
+
+static int in_sites(int l, int nflip, const int *sites)
+{
+    for (int a = 0; a < nflip; ++a)
+        if (sites[a] == l) return 1;
+    return 0;
+}
+
+/*
+ * E(x') - E(x) for x' = x with the spins in `sites` flipped (distinct sites).
+ * Only the terms of Eq. 1 that touch a flipped site change: h_k s_k for a
+ * flipped k, and J_kl s_k s_l with exactly one of k, l flipped (a pair with
+ * both flipped keeps its sign).  Each such term changes by -2 times itself.
+ */
+double qo_flip_change(int N, const double *J, const double *h, const uint64_t *x,
+                      int nflip, const int *sites)
+{
+    double d = 0.0;
+    for (int a = 0; a < nflip; ++a) {
+        int k = sites[a];
+        double sk = (double)spin_of(x, k);
+        double field = h[k];
+        for (int l = 0; l < N; ++l) {
+            if (in_sites(l, nflip, sites)) continue;
+            field += J[(size_t)k * N + l] * (double)spin_of(x, l);
+        }
+        d += -2.0 * sk * field;
+    }
+    return d;
+}
+
+/* Total order: energy first, then the state integer psi (highest word first). */
+static int order_cmp(double Ea, const uint64_t *a, double Eb, const uint64_t *b, int W)
+{
+    if (Ea < Eb) return -1;
+    if (Ea > Eb) return 1;
+    for (int w = W - 1; w >= 0; --w) {
+        if (a[w] < b[w]) return -1;
+        if (a[w] > b[w]) return 1;
+    }
+    return 0;
+}
+
+/* A list of at most `cap` distinct states sorted by the total order. */
+typedef struct {
+    int cap, n, W;
+    double *E;
+    uint64_t *bits;
+    uint8_t *flag;
+} klist;
+
+static int klist_init(klist *L, int cap, int W)
+{
+    L->cap = cap; L->n = 0; L->W = W;
+    L->E = (double *)malloc(sizeof(double) * (size_t)(cap + 1));
+    L->bits = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(cap + 1) * W);
+    L->flag = (uint8_t *)malloc((size_t)(cap + 1));
+    return (L->E && L->bits && L->flag) ? 0 : -1;
+}
+
+static void klist_free(klist *L)
+{
+    free(L->E); free(L->bits); free(L->flag);
+    L->E = NULL; L->bits = NULL; L->flag = NULL;
+}
+
+/* Offer one state; it enters if it is new and ranks among the `cap` best. */
+static int klist_offer(klist *L, double E, const uint64_t *x, uint8_t flag)
+{
+    int W = L->W;
+    if (L->n == L->cap && order_cmp(E, x, L->E[L->n - 1], L->bits + (size_t)(L->n - 1) * W, W) >= 0)
+        return 0;
+    for (int k = 0; k < L->n; ++k)
+        if (memcmp(L->bits + (size_t)k * W, x, sizeof(uint64_t) * W) == 0)
+            return 0;
+    int pos = L->n;
+    while (pos > 0 && order_cmp(E, x, L->E[pos - 1], L->bits + (size_t)(pos - 1) * W, W) < 0)
+        --pos;
+    for (int k = L->n; k > pos; --k) {
+        L->E[k] = L->E[k - 1];
+        L->flag[k] = L->flag[k - 1];
+        memcpy(L->bits + (size_t)k * W, L->bits + (size_t)(k - 1) * W, sizeof(uint64_t) * W);
+    }
+    L->E[pos] = E;
+    L->flag[pos] = flag;
+    memcpy(L->bits + (size_t)pos * W, x, sizeof(uint64_t) * W);
+    if (L->n < L->cap) L->n++;
+    return 1;
+}
+
+/* Offer the neighbourhood of parent x (energy Ex): single flips, then pairs i<j. */
+static void offer_children(klist *L, int N, const double *J, const double *h,
+                           const uint64_t *x, double Ex, uint64_t *child)
+{
+    int W = words_of(N);
+    int sites[2];
+    for (int i = 0; i < N; ++i) {
+        memcpy(child, x, sizeof(uint64_t) * W);
+        child[i >> 6] ^= (uint64_t)1 << (i & 63);
+        sites[0] = i;
+        klist_offer(L, Ex + qo_flip_change(N, J, h, x, 1, sites), child, 1);
+    }
+    for (int i = 0; i < N; ++i) {
+        for (int j = i + 1; j < N; ++j) {
+            memcpy(child, x, sizeof(uint64_t) * W);
+            child[i >> 6] ^= (uint64_t)1 << (i & 63);
+            child[j >> 6] ^= (uint64_t)1 << (j & 63);
+            sites[0] = i; sites[1] = j;
+            klist_offer(L, Ex + qo_flip_change(N, J, h, x, 2, sites), child, 1);
+        }
+    }
+}
+
+/*
+ * One synchronous step.  Input: the kept set S_t (n_in states, energies in_E
+ * or NULL to evaluate Eq. 1, and in_front = 1 for states that entered in the
+ * previous step).  Output: S_{t+1}, the M lowest distinct states of
+ * S_t united with the neighbourhoods of the expanded states, sorted, with
+ * out_front = 1 for states not in S_t.  literal != 0 expands every state of
+ * S_t; otherwise only those with in_front set.  Returns the number of new
+ * states (0 means the set is stable), or -1 on allocation failure.
+ */
+int qo_step(int N, const double *J, const double *h, int M, int literal,
+            int n_in, const uint64_t *in_bits, const double *in_E, const uint8_t *in_front,
+            uint64_t *out_bits, double *out_E, uint8_t *out_front, int *n_out)
+{
+    int W = words_of(N);
+    double *E_in = (double *)malloc(sizeof(double) * (size_t)(n_in > 0 ? n_in : 1));
+    if (!E_in) return -1;
+    for (int k = 0; k < n_in; ++k)
+        E_in[k] = in_E ? in_E[k] : qo_energy(N, J, h, in_bits + (size_t)k * W);
+
+    int nthreads = 1;
+#ifdef _OPENMP
+    nthreads = omp_get_max_threads();
+#endif
+    klist *part = (klist *)calloc((size_t)nthreads, sizeof(klist));
+    int fail = (part == NULL);
+    for (int t = 0; t < nthreads && !fail; ++t)
+        fail |= klist_init(&part[t], M, W);
+
+    if (!fail) {
+#pragma omp parallel num_threads(nthreads)
+        {
+            int tid = 0;
+#ifdef _OPENMP
+            tid = omp_get_thread_num();
+#endif
+            uint64_t *child = (uint64_t *)malloc(sizeof(uint64_t) * W);
+#pragma omp for schedule(dynamic, 1)
+            for (int k = 0; k < n_in; ++k) {
+                if (!literal && !in_front[k]) continue;
+                offer_children(&part[tid], N, J, h, in_bits + (size_t)k * W, E_in[k], child);
+            }
+            free(child);
+        }
+    }
+
+    int n_new = -1;
+    klist R;
+    if (!fail && klist_init(&R, M, W) == 0) {
+        /* S_t first, so a child equal to a kept state keeps the kept flag. */
+        for (int k = 0; k < n_in; ++k)
+            klist_offer(&R, E_in[k], in_bits + (size_t)k * W, 0);
+        for (int t = 0; t < nthreads; ++t)
+            for (int k = 0; k < part[t].n; ++k)
+                klist_offer(&R, part[t].E[k], part[t].bits + (size_t)k * W, 1);
+        n_new = 0;
+        for (int k = 0; k < R.n; ++k) {
+            out_E[k] = R.E[k];
+            out_front[k] = R.flag[k];
+            memcpy(out_bits + (size_t)k * W, R.bits + (size_t)k * W, sizeof(uint64_t) * W);
+            n_new += R.flag[k];
+        }
+        *n_out = R.n;
+        klist_free(&R);
+    }
+    if (part) {
+        for (int t = 0; t < nthreads; ++t) klist_free(&part[t]);
+        free(part);
+    }
+    free(E_in);
+    return n_new;
+}
+
+/*
+ * One search from initial state x0 (S_0 = {x0}); steps until the set is
+ * stable or max_iters steps were taken.  *iters counts the steps evaluated,
+ * including the last one that found no new state.  Returns 1 if stable, 0 if
+ * the cap was reached first, -1 on failure.
+ */
+int qo_search(int N, const double *J, const double *h, int M, int max_iters, int literal,
+              const uint64_t *x0, uint64_t *out_bits, double *out_E, int *n_out, int *iters)
+{
+    int W = words_of(N);
+    size_t cap = (size_t)M;
+    uint64_t *cb = (uint64_t *)malloc(sizeof(uint64_t) * cap * W);
+    uint64_t *nb = (uint64_t *)malloc(sizeof(uint64_t) * cap * W);
+    double *cE = (double *)malloc(sizeof(double) * cap);
+    double *nE = (double *)malloc(sizeof(double) * cap);
+    uint8_t *cf = (uint8_t *)malloc(cap);
+    uint8_t *nf = (uint8_t *)malloc(cap);
+    int rc = -1;
+    if (cb && nb && cE && nE && cf && nf) {
+        int n = 1;
+        memcpy(cb, x0, sizeof(uint64_t) * W);
+        cE[0] = qo_energy(N, J, h, x0);
+        cf[0] = 1;
+        int t = 0, stable = 0;
+        while (t < max_iters) {
+            int nn = 0;
+            int n_new = qo_step(N, J, h, M, literal, n, cb, cE, cf, nb, nE, nf, &nn);
+            if (n_new < 0) { t = -1; break; }
+            ++t;
+            if (n_new == 0) { stable = 1; break; }
+            uint64_t *tb = cb; cb = nb; nb = tb;
+            double *tE = cE; cE = nE; nE = tE;
+            uint8_t *tf = cf; cf = nf; nf = tf;
+            n = nn;
+        }
+        if (t >= 0) {
+            memcpy(out_bits, cb, sizeof(uint64_t) * (size_t)n * W);
+            memcpy(out_E, cE, sizeof(double) * (size_t)n);
+            *n_out = n;
+            *iters = t;
+            rc = stable;
+        }
+    }
+    free(cb); free(nb); free(cE); free(nE); free(cf); free(nf);
+    return rc;
+}
+
+/* Alg. 4 merge: the M lowest distinct states of the union of several lists. */
+int qo_merge(int N, int M, int n_lists, const int *counts, const uint64_t *bits, const double *E,
+             uint64_t *out_bits, double *out_E, int *n_out)
+{
+    int W = words_of(N);
+    klist R;
+    if (klist_init(&R, M, W) != 0) return -1;
+    size_t off = 0;
+    for (int l = 0; l < n_lists; ++l) {
+        for (int k = 0; k < counts[l]; ++k, ++off)
+            klist_offer(&R, E[off], bits + off * W, 0);
+    }
+    for (int k = 0; k < R.n; ++k) {
+        out_E[k] = R.E[k];
+        memcpy(out_bits + (size_t)k * W, R.bits + (size_t)k * W, sizeof(uint64_t) * W);
+    }
+    *n_out = R.n;
+    klist_free(&R);
+    return 0;
+}
+
+/*
+ * Exhaustive search over all 2^N states (the paper's brute-force reference,
+ * N small): the K lowest states under the total order.  States are visited
+ * in Gray-code order; flipping spin i changes E by -2 s_i f_i with
+ * f_i = h_i + sum_l J_il s_l, and then every f_k moves by -2 s_i J_ki.
+ */
+int qo_brute_lowest(int N, const double *J, const double *h, int K,
+                    uint64_t *out_bits, double *out_E, int *n_out)
+{
+    if (N < 1 || N > 40) return -1;
+    int W = words_of(N);
+    klist R;
+    if (klist_init(&R, K, W) != 0) return -1;
+    double *f = (double *)malloc(sizeof(double) * N);
+    int *s = (int *)malloc(sizeof(int) * N);
+    uint64_t *x = (uint64_t *)calloc((size_t)W, sizeof(uint64_t));
+    if (!f || !s || !x) { free(f); free(s); free(x); klist_free(&R); return -1; }
+    for (int i = 0; i < N; ++i) s[i] = 1;
+    for (int i = 0; i < N; ++i) {
+        f[i] = h[i];
+        for (int l = 0; l < N; ++l) f[i] += J[(size_t)i * N + l];
+    }
+    double E = qo_energy(N, J, h, x);
+    klist_offer(&R, E, x, 0);
+    uint64_t total = (uint64_t)1 << N;
+    for (uint64_t g = 1; g < total; ++g) {
+        int i = __builtin_ctzll(g);
+        E += -2.0 * s[i] * f[i];
+        for (int k = 0; k < N; ++k)
+            f[k] += -2.0 * s[i] * J[(size_t)k * N + i];
+        s[i] = -s[i];
+        x[i >> 6] ^= (uint64_t)1 << (i & 63);
+        if (R.n < R.cap || E <= R.E[R.n - 1])
+            klist_offer(&R, E, x, 0);
+    }
+    for (int k = 0; k < R.n; ++k) {
+        out_E[k] = R.E[k];
+        memcpy(out_bits + (size_t)k * W, R.bits + (size_t)k * W, sizeof(uint64_t) * W);
+    }
+    *n_out = R.n;
+    free(f); free(s); free(x);
+    klist_free(&R);
+    return 0;
+}
+
+int qo_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
