@@ -1,0 +1,162 @@
+/*
+ * ising_search.h -- C ABI of the MI355X (gfx950) library for the synchronous
+ * quantum-inspired (QI) low-energy search of classical Ising Hamiltonians
+ * (Ueda, Otsuka, Yunoki, arXiv:2010.00180).
+ *
+ * Problem (Sec. I, Eq. 1): H0 = sum_{i<j} J_ij s_i s_j + sum_i h_i s_i on a fully
+ * connected graph of N spins.  A state is the integer psi = sum_i 2^i sigma_i
+ * with sigma_i = 0 <=> s_i = +1 and sigma_i = 1 <=> s_i = -1 (Sec. III, Eq. 15).
+ * Bit layout everywhere: W = ceil(N/64) little-endian uint64 words per state;
+ * bit i of word i>>6 is sigma_i; bits at positions >= N must be zero.
+ *
+ * Method (Sec. II, Eqs. 9-14 in the infinitesimal-lambda limit, with the
+ * one- and two-spin flip terms of H1, Eq. 16): every search keeps a set of at
+ * most M distinct states.  One step replaces the set by the M lowest distinct
+ * states of the union of the neighbourhoods (the state, its N single flips and
+ * its N(N-1)/2 pair flips) of its states; the search is stable when a step
+ * brings no new state.  Searches start from one initial state each; the L
+ * searches of one instance are merged at the end into the M lowest distinct
+ * states of their union (Alg. 4).  Ties in energy are broken by psi (smaller
+ * first), which makes every kept set unique.
+ *
+ * Exact arithmetic: J_ij and h_i must be integer multiples of 2^-24 and
+ * sum_{i<j} |J_ij| + sum_i |h_i| <= 2^24.  All energies, local fields and
+ * energy changes are then exact in FP64 and independent of summation order.
+ *
+ * Errors: every call returns an ising_status_t; negative values are errors and
+ * leave a message for ising_search_last_error().  No call aborts the process.
+ * Calls on one handle must not overlap; different handles are independent.
+ */
+#ifndef ISING_SEARCH_H
+#define ISING_SEARCH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ising_search ising_search_t; /* opaque; owns all of its device memory */
+
+typedef enum {
+    ISING_OK = 0,
+    ISING_NOT_CONVERGED = 1,   /* run() hit its step cap; the state is valid and can be continued */
+    ISING_ERR_INVALID_ARG = -1,
+    ISING_ERR_NO_DEVICE = -2,
+    ISING_ERR_OUT_OF_MEMORY = -3,
+    ISING_ERR_HIP = -4,
+    ISING_ERR_BAD_STATE = -5,  /* NULL or destroyed handle, or a handle after a device error */
+    ISING_ERR_CAPACITY = -6    /* a search produced more tied candidates than its buffer holds */
+} ising_status_t;
+
+typedef enum {
+    ISING_FORM_PLAIN = 0,      /* FP64 local fields, FP64 energy-change scan */
+    ISING_FORM_SPLIT_BF16 = 1, /* initial local fields from J = hi + lo (bf16) on MFMA with FP32
+                                  accumulation, FP32 scan with a proven error slack, FP64 re-score */
+    ISING_FORM_LEARNED = 2     /* pair flips ranked by a small MLP; only the top K are scored exactly */
+} ising_form_t;
+
+typedef struct {
+    int32_t M;                 /* states kept per search, >= 1 */
+    int32_t max_iters;         /* default step cap used by ising_search_run when its cap is <= 0 */
+    int32_t form;              /* ising_form_t */
+    int32_t states_per_item;   /* scan tile: frontier states per work item; 0 = tuned default */
+    int32_t topk_factor;       /* learned form: K = topk_factor * N pairs per state (default 8) */
+    int32_t persistent;        /* 1 = capture one step into a hipGraph and replay it in run() */
+    int32_t reserved[2];       /* must be zero */
+} ising_config_t;
+
+typedef struct {
+    uint64_t steps;            /* steps executed (all searches advance together) */
+    uint64_t pair_evals;       /* pair-flip energy changes evaluated by the scan */
+    uint64_t single_evals;     /* single-flip energy changes evaluated */
+    uint64_t frontier_states;  /* states expanded, summed over steps */
+    uint64_t survivors;        /* candidates that passed the scan's cut, summed over steps */
+    uint64_t retries;          /* re-scans of a search after its candidate buffer filled */
+    uint64_t fallbacks;        /* split form: states re-scanned in FP64; learned form: full scans */
+    uint64_t reserved[5];
+} ising_stats_t;
+
+/*
+ * Create a handle and run the first part of the method: copy the instances to
+ * the device, compute the local fields F = h + J s of every initial state
+ * (FP64 MFMA GEMM, one per instance) and their energies (Eq. 1 through
+ * E = (1/2) sum_i s_i (F_i + h_i)), and seed every search with S_0 = {x0}.
+ *
+ *   out        receives the handle (set to NULL on failure)
+ *   cfg        configuration (see ising_config_t)
+ *   n_inst     number of instances B >= 1
+ *   N          [B] spins per instance, 1 <= N[b] <= 4096
+ *   J          [B] host pointers to N[b]*N[b] row-major FP64 couplings; exactly
+ *              symmetric, zero diagonal (Eq. 1 sums i<j, so an upper-triangle
+ *              caller must mirror first)
+ *   h          [B] host pointers to N[b] FP64 fields
+ *   L          searches (initial states) per instance, >= 1
+ *   init_bits  [B] host pointers to L*W[b] uint64 words (L initial states)
+ *   stream     hipStream_t to order all device work on, or NULL for the
+ *              default stream
+ * Host inputs are copied; the caller keeps ownership.  Errors: INVALID_ARG
+ * (sizes, asymmetry, nonzero diagonal, non-finite or off-grid values, stray
+ * bits), NO_DEVICE, OUT_OF_MEMORY, HIP.
+ */
+int ising_search_init(ising_search_t **out, const ising_config_t *cfg, int32_t n_inst,
+                      const int32_t *N, const double *const *J, const double *const *h,
+                      int32_t L, const uint64_t *const *init_bits, void *stream);
+
+/*
+ * One synchronous step of every search still running (Sec. II): expand the
+ * states that entered in the previous step by all single and pair flips,
+ * evaluate their energies from local fields, and keep the M lowest distinct
+ * states of the union with the current set.  States already kept never need
+ * re-expansion: their neighbours were offered one step earlier.
+ * n_active (may be NULL) receives the number of searches whose set changed.
+ */
+int ising_search_step(ising_search_t *s, int32_t *n_active);
+
+/*
+ * Step until every search is stable or max_iters steps were taken
+ * (max_iters <= 0 uses cfg->max_iters).  iters_done (may be NULL) receives
+ * the steps taken by this call, including the final one that found no new
+ * state.  Returns ISING_OK when all searches are stable, ISING_NOT_CONVERGED
+ * when the cap was reached first.
+ */
+int ising_search_run(ising_search_t *s, int32_t max_iters, int32_t *iters_done);
+
+/*
+ * Result of one instance (Alg. 4): the M lowest distinct states of the union
+ * of its L kept sets, sorted by (E, psi).  bits_out: caller buffer of M*W
+ * words; E_out: M doubles; count receives the number written (<= M).
+ */
+int ising_search_get_states(ising_search_t *s, int32_t instance, uint64_t *bits_out,
+                            double *E_out, int32_t *count);
+
+/*
+ * The current kept set of one search (search = instance*L + l), sorted by
+ * (E, psi), with front[k] = 1 for states that entered in the last step.
+ * bits_out: M*W words; E_out: M doubles; front_out: M bytes (may be NULL).
+ */
+int ising_search_get_search(ising_search_t *s, int32_t search, uint64_t *bits_out,
+                            double *E_out, uint8_t *front_out, int32_t *count);
+
+/*
+ * Replace the kept set of one search (checkpoint restore, or a test that
+ * starts a step from a given set).  Up to M distinct states; energies and
+ * local fields are recomputed on the device; front[k] marks states to expand
+ * in the next step (NULL = all).  The search becomes active.
+ */
+int ising_search_set_search(ising_search_t *s, int32_t search, const uint64_t *bits,
+                            const uint8_t *front, int32_t count);
+
+int ising_search_get_stats(ising_search_t *s, ising_stats_t *out);
+
+/* Frees all device memory of the handle.  NULL is accepted. */
+void ising_search_destroy(ising_search_t *s);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *ising_search_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISING_SEARCH_H */

@@ -1,0 +1,550 @@
+// Host side of the C ABI declared in include/ising_search.h: argument
+// validation, device allocation, the per-step launch sequence and result
+// copies.  Every device computation happens in the kernels of k_init.hip and
+// k_step.hip; this file only moves data and orders launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "../../include/ising_search.h"
+#include "common.h"
+
+using namespace qi;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+constexpr uint32_t MAGIC = 0x51495331u;   // "QIS1"
+
+// Live handles; a destroyed or foreign pointer is rejected without being read.
+std::mutex g_live_mu;
+std::set<const void*> g_live;
+
+}  // namespace
+
+struct ising_search {
+    uint32_t magic = MAGIC;
+    bool broken = false;
+    ising_config_t cfg{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    Layout lay{};
+    std::vector<int> N;
+    std::vector<int> Npad;
+    int scan_grid = 0;
+    bool final_dirty = true;
+    std::vector<void*> allocs;
+    // host mirrors of small device buffers
+    int flags_h[8]{};
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            return fail(ISING_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+        }                                                                                 \
+    } while (0)
+
+template <class T>
+int dalloc(ising_search* h, T** p, size_t count)
+{
+    void* v = nullptr;
+    size_t bytes = count * sizeof(T);
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(&v, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ISING_ERR_OUT_OF_MEMORY, "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    }
+    h->allocs.push_back(v);
+    *p = static_cast<T*>(v);
+    return ISING_OK;
+}
+
+void free_all(ising_search* h)
+{
+    for (void* p : h->allocs) (void)hipFree(p);
+    h->allocs.clear();
+}
+
+uint64_t splitmix64(uint64_t& x)
+{
+    uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+bool on_grid(double v)
+{
+    if (!std::isfinite(v)) return false;
+    const double s = v * 16777216.0;   // 2^24
+    if (std::fabs(s) > 9.0e15) return false;
+    return s == std::nearbyint(s);
+}
+
+int check_handle(ising_search_t* s)
+{
+    if (!s) return fail(ISING_ERR_BAD_STATE, "NULL handle");
+    {
+        std::lock_guard<std::mutex> g(g_live_mu);
+        if (!g_live.count(s)) return fail(ISING_ERR_BAD_STATE, "handle is not live (destroyed or never created)");
+    }
+    if (s->magic != MAGIC) return fail(ISING_ERR_BAD_STATE, "handle is corrupt");
+    if (s->broken) return fail(ISING_ERR_BAD_STATE, "handle is unusable after an earlier device error");
+    return ISING_OK;
+}
+
+int sync_flags(ising_search* h)
+{
+    HIP_TRY(hipMemcpyAsync(h->flags_h, h->lay.flags, sizeof(h->flags_h), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return ISING_OK;
+}
+
+}  // namespace
+
+extern "C" const char* ising_search_last_error(void) { return g_err.c_str(); }
+
+extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg, int32_t n_inst,
+                                 const int32_t* N, const double* const* J, const double* const* h,
+                                 int32_t L, const uint64_t* const* init_bits, void* stream)
+{
+    g_err.clear();
+    if (!out) return fail(ISING_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!cfg) return fail(ISING_ERR_INVALID_ARG, "cfg is NULL");
+    if (cfg->M < 1 || cfg->M > 1024) return fail(ISING_ERR_INVALID_ARG, "M=%d outside [1, 1024]", cfg->M);
+    if (cfg->form != ISING_FORM_PLAIN)
+        return fail(ISING_ERR_INVALID_ARG, "form %d is not available in this build", cfg->form);
+    if (cfg->reserved[0] || cfg->reserved[1]) return fail(ISING_ERR_INVALID_ARG, "reserved fields must be zero");
+    if (cfg->states_per_item < 0 || cfg->states_per_item > 4096)
+        return fail(ISING_ERR_INVALID_ARG, "states_per_item=%d outside [0, 4096]", cfg->states_per_item);
+    if (n_inst < 1) return fail(ISING_ERR_INVALID_ARG, "n_inst=%d < 1", n_inst);
+    if (L < 1) return fail(ISING_ERR_INVALID_ARG, "L=%d < 1", L);
+    if (!N || !J || !h || !init_bits) return fail(ISING_ERR_INVALID_ARG, "NULL array argument");
+    if ((long long)n_inst * L > (1 << 24)) return fail(ISING_ERR_INVALID_ARG, "too many searches");
+
+    int Nmax = 0;
+    for (int b = 0; b < n_inst; ++b) {
+        if (N[b] < 1 || N[b] > MAX_N) return fail(ISING_ERR_INVALID_ARG, "N[%d]=%d outside [1, %d]", b, N[b], MAX_N);
+        if (!J[b] || !h[b] || !init_bits[b]) return fail(ISING_ERR_INVALID_ARG, "NULL pointer for instance %d", b);
+        if (N[b] > Nmax) Nmax = N[b];
+        const int n = N[b];
+        double bound = 0.0;
+        for (int i = 0; i < n; ++i) {
+            if (!on_grid(h[b][i]))
+                return fail(ISING_ERR_INVALID_ARG, "h[%d][%d]=%g is not a finite multiple of 2^-24", b, i, h[b][i]);
+            bound += std::fabs(h[b][i]);
+            if (J[b][(size_t)i * n + i] != 0.0)
+                return fail(ISING_ERR_INVALID_ARG, "J[%d] has a nonzero diagonal at %d", b, i);
+            for (int j = i + 1; j < n; ++j) {
+                const double v = J[b][(size_t)i * n + j];
+                if (!on_grid(v))
+                    return fail(ISING_ERR_INVALID_ARG, "J[%d][%d,%d]=%g is not a finite multiple of 2^-24", b, i, j, v);
+                if (v != J[b][(size_t)j * n + i])
+                    return fail(ISING_ERR_INVALID_ARG, "J[%d] is not symmetric at (%d,%d)", b, i, j);
+                bound += std::fabs(v);
+            }
+        }
+        if (bound > 16777216.0)
+            return fail(ISING_ERR_INVALID_ARG, "instance %d: sum |J_ij| + sum |h_i| = %g exceeds 2^24", b, bound);
+        const int W = words_of(n);
+        for (int l = 0; l < L; ++l) {
+            const uint64_t* x = init_bits[b] + (size_t)l * W;
+            const int tail = n & 63;
+            if (tail && (x[W - 1] >> tail))
+                return fail(ISING_ERR_INVALID_ARG, "initial state %d of instance %d has bits at positions >= N", l, b);
+        }
+    }
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        return fail(ISING_ERR_NO_DEVICE, "no HIP device available");
+    }
+
+    ising_search* hd = new ising_search();
+    hd->cfg = *cfg;
+    if (hd->cfg.max_iters <= 0) hd->cfg.max_iters = 4 * Nmax + 16;
+    hd->stream = static_cast<hipStream_t>(stream);
+    if (hipGetDevice(&hd->device) != hipSuccess) {
+        delete hd;
+        return fail(ISING_ERR_HIP, "hipGetDevice failed");
+    }
+    Layout& lay = hd->lay;
+    lay.B = n_inst;
+    lay.L = L;
+    lay.M = cfg->M;
+    lay.S = n_inst * L;
+    lay.Wmax = words_of(Nmax);
+    lay.Npmax = pad_of(Nmax);
+    lay.fmax = L * cfg->M;
+    lay.cap_surv = 32768;
+    lay.sc = cfg->states_per_item > 0 ? cfg->states_per_item : 64;
+    hd->N.assign(N, N + n_inst);
+    hd->Npad.resize(n_inst);
+    std::vector<long long> joff(n_inst);
+    long long jtot = 0;
+    for (int b = 0; b < n_inst; ++b) {
+        hd->Npad[b] = pad_of(N[b]);
+        joff[b] = jtot;
+        jtot += (long long)hd->Npad[b] * hd->Npad[b];
+    }
+
+    int rc = ISING_OK;
+    int *dN = nullptr, *dNpad = nullptr;
+    long long* djoff = nullptr;
+    double *dJ4 = nullptr, *dh = nullptr;
+    uint64_t *dz = nullptr, *dx0 = nullptr;
+    const size_t S = lay.S, M2 = 2 * (size_t)lay.M;
+#define ALLOC(p, n) \
+    if (rc == ISING_OK) rc = dalloc(hd, &(p), (n))
+    ALLOC(dN, n_inst);
+    ALLOC(dNpad, n_inst);
+    ALLOC(djoff, n_inst);
+    ALLOC(dJ4, (size_t)jtot);
+    ALLOC(dh, (size_t)n_inst * lay.Npmax);
+    ALLOC(dz, (size_t)MAX_N);
+    ALLOC(dx0, S * lay.Wmax);
+    ALLOC(lay.bits, S * M2 * lay.Wmax);
+    ALLOC(lay.E, S * M2);
+    ALLOC(lay.zob, S * M2);
+    ALLOC(lay.F, S * M2 * lay.Npmax);
+    ALLOC(lay.fresh, S * M2);
+    ALLOC(lay.kept, S * lay.M);
+    ALLOC(lay.nkept, S);
+    ALLOC(lay.active, S);
+    ALLOC(lay.retry, S);
+    ALLOC(lay.cut, S);
+    ALLOC(lay.fr_count, n_inst);
+    ALLOC(lay.fr_list, (size_t)n_inst * lay.fmax);
+    ALLOC(lay.A, (size_t)n_inst * lay.fmax * lay.Npmax);
+    ALLOC(lay.T, (size_t)n_inst * lay.fmax);
+    ALLOC(lay.surv_count, S);
+    ALLOC(lay.surv, S * lay.cap_surv);
+    ALLOC(lay.item_prefix, 2 * ((size_t)n_inst + 1));
+    ALLOC(lay.ctr, 16);
+    ALLOC(lay.flags, 8);
+    ALLOC(lay.out_bits, (size_t)n_inst * lay.M * lay.Wmax);
+    ALLOC(lay.out_E, (size_t)n_inst * lay.M);
+    ALLOC(lay.out_count, n_inst);
+#undef ALLOC
+    if (rc != ISING_OK) {
+        free_all(hd);
+        delete hd;
+        return rc;
+    }
+    lay.N = dN;
+    lay.Npad = dNpad;
+    lay.joff = djoff;
+    lay.J4 = dJ4;
+    lay.h = dh;
+    lay.zkey = dz;
+
+    // host staging of padded 4J and h
+    auto bail = [&](int code) {
+        free_all(hd);
+        delete hd;
+        return code;
+    };
+    {
+        std::vector<double> J4h((size_t)jtot, 0.0);
+        std::vector<double> hh((size_t)n_inst * lay.Npmax, 0.0);
+        std::vector<uint64_t> x0((size_t)S * lay.Wmax, 0);
+        for (int b = 0; b < n_inst; ++b) {
+            const int n = N[b], np = hd->Npad[b];
+            double* dst = J4h.data() + joff[b];
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) dst[(size_t)i * np + j] = 4.0 * J[b][(size_t)i * n + j];
+            for (int i = 0; i < n; ++i) hh[(size_t)b * lay.Npmax + i] = h[b][i];
+            const int W = words_of(n);
+            for (int l = 0; l < L; ++l)
+                for (int w = 0; w < W; ++w)
+                    x0[((size_t)b * L + l) * lay.Wmax + w] = init_bits[b][(size_t)l * W + w];
+        }
+        std::vector<uint64_t> zk(MAX_N);
+        uint64_t st = 0x2010001800000001ull;
+        for (auto& z : zk) z = splitmix64(st);
+        const hipStream_t sm = hd->stream;
+        int r2 = ISING_OK;
+        auto cp = [&](void* d, const void* src, size_t bytes) {
+            if (r2 != ISING_OK) return;
+            hipError_t e = hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, sm);
+            if (e != hipSuccess) r2 = fail(ISING_ERR_HIP, "host-to-device copy failed: %s", hipGetErrorString(e));
+        };
+        cp(dN, N, sizeof(int) * n_inst);
+        cp(dNpad, hd->Npad.data(), sizeof(int) * n_inst);
+        cp(djoff, joff.data(), sizeof(long long) * n_inst);
+        cp(dJ4, J4h.data(), sizeof(double) * J4h.size());
+        cp(dh, hh.data(), sizeof(double) * hh.size());
+        cp(dz, zk.data(), sizeof(uint64_t) * zk.size());
+        cp(dx0, x0.data(), sizeof(uint64_t) * x0.size());
+        if (r2 == ISING_OK) {
+            hipError_t e = hipMemsetAsync(lay.ctr, 0, 16 * sizeof(unsigned long long), sm);
+            if (e == hipSuccess) e = hipMemsetAsync(lay.flags, 0, 8 * sizeof(int), sm);
+            if (e == hipSuccess) e = launch_init_fields(lay, dx0, sm);
+            if (e == hipSuccess) e = hipStreamSynchronize(sm);
+            if (e != hipSuccess) r2 = fail(ISING_ERR_HIP, "initialisation kernels failed: %s", hipGetErrorString(e));
+        }
+        if (r2 != ISING_OK) return bail(r2);
+    }
+    int cus = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hd->device) == hipSuccess && prop.multiProcessorCount > 0)
+        cus = prop.multiProcessorCount;
+    hd->scan_grid = cus * 16;
+    {
+        std::lock_guard<std::mutex> g(g_live_mu);
+        g_live.insert(hd);
+    }
+    *out = hd;
+    return ISING_OK;
+}
+
+static int do_step(ising_search* h, int32_t* n_active)
+{
+    const Layout& lay = h->lay;
+    hipError_t e = launch_step_begin(lay, false, h->stream);
+    if (e == hipSuccess) e = launch_step(lay, h->scan_grid, false, h->stream);
+    if (e != hipSuccess) {
+        h->broken = true;
+        return fail(ISING_ERR_HIP, "step launch failed: %s", hipGetErrorString(e));
+    }
+    int rc = sync_flags(h);
+    if (rc != ISING_OK) {
+        h->broken = true;
+        return rc;
+    }
+    int guard = 0;
+    while (h->flags_h[FLAG_OVERFLOW] > 0) {
+        if (h->flags_h[FLAG_STUCK] > 0 || ++guard > 64)
+            return fail(ISING_ERR_CAPACITY,
+                        "a search has more tied candidates at its cut than its buffer holds (%d records)",
+                        lay.cap_surv);
+        e = launch_step_begin(lay, true, h->stream);
+        if (e == hipSuccess) e = launch_step(lay, h->scan_grid, true, h->stream);
+        if (e != hipSuccess) {
+            h->broken = true;
+            return fail(ISING_ERR_HIP, "retry launch failed: %s", hipGetErrorString(e));
+        }
+        rc = sync_flags(h);
+        if (rc != ISING_OK) {
+            h->broken = true;
+            return rc;
+        }
+    }
+    h->final_dirty = true;
+    if (n_active) *n_active = h->flags_h[FLAG_ACTIVE];
+    return ISING_OK;
+}
+
+extern "C" int ising_search_step(ising_search_t* s, int32_t* n_active)
+{
+    g_err.clear();
+    int rc = check_handle(s);
+    if (rc != ISING_OK) return rc;
+    return do_step(s, n_active);
+}
+
+extern "C" int ising_search_run(ising_search_t* s, int32_t max_iters, int32_t* iters_done)
+{
+    g_err.clear();
+    int rc = check_handle(s);
+    if (rc != ISING_OK) return rc;
+    const int cap = max_iters > 0 ? max_iters : s->cfg.max_iters;
+    int it = 0;
+    int active = 1;
+    while (it < cap && active > 0) {
+        rc = do_step(s, &active);
+        if (rc != ISING_OK) {
+            if (iters_done) *iters_done = it;
+            return rc;
+        }
+        ++it;
+    }
+    if (iters_done) *iters_done = it;
+    return active > 0 ? ISING_NOT_CONVERGED : ISING_OK;
+}
+
+extern "C" int ising_search_get_states(ising_search_t* s, int32_t instance, uint64_t* bits_out, double* E_out,
+                                       int32_t* count)
+{
+    g_err.clear();
+    int rc = check_handle(s);
+    if (rc != ISING_OK) return rc;
+    if (instance < 0 || instance >= s->lay.B)
+        return fail(ISING_ERR_INVALID_ARG, "instance %d outside [0, %d)", instance, s->lay.B);
+    if (!bits_out || !E_out || !count) return fail(ISING_ERR_INVALID_ARG, "NULL output pointer");
+    const Layout& lay = s->lay;
+    if (s->final_dirty) {
+        hipError_t e = launch_final(lay, s->stream);
+        if (e != hipSuccess) {
+            s->broken = true;
+            return fail(ISING_ERR_HIP, "merge launch failed: %s", hipGetErrorString(e));
+        }
+        s->final_dirty = false;
+    }
+    int n = 0;
+    const int W = words_of(s->N[instance]);
+    std::vector<uint64_t> tmp((size_t)lay.M * lay.Wmax);
+    HIP_TRY(hipMemcpyAsync(&n, lay.out_count + instance, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(tmp.data(), lay.out_bits + (size_t)instance * lay.M * lay.Wmax,
+                           tmp.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(E_out, lay.out_E + (size_t)instance * lay.M, sizeof(double) * lay.M,
+                           hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (int k = 0; k < n; ++k)
+        for (int w = 0; w < W; ++w) bits_out[(size_t)k * W + w] = tmp[(size_t)k * lay.Wmax + w];
+    *count = n;
+    return ISING_OK;
+}
+
+extern "C" int ising_search_get_search(ising_search_t* s, int32_t search, uint64_t* bits_out, double* E_out,
+                                       uint8_t* front_out, int32_t* count)
+{
+    g_err.clear();
+    int rc = check_handle(s);
+    if (rc != ISING_OK) return rc;
+    const Layout& lay = s->lay;
+    if (search < 0 || search >= lay.S) return fail(ISING_ERR_INVALID_ARG, "search %d outside [0, %d)", search, lay.S);
+    if (!bits_out || !E_out || !count) return fail(ISING_ERR_INVALID_ARG, "NULL output pointer");
+    const int M = lay.M;
+    const size_t M2 = 2 * (size_t)M;
+    int nk = 0;
+    std::vector<int> kept(M);
+    std::vector<uint64_t> bits(M2 * lay.Wmax);
+    std::vector<double> E(M2);
+    std::vector<uint8_t> fr(M2);
+    HIP_TRY(hipMemcpyAsync(&nk, lay.nkept + search, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(kept.data(), lay.kept + (size_t)search * M, sizeof(int) * M, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(bits.data(), lay.bits + (size_t)search * M2 * lay.Wmax, sizeof(uint64_t) * bits.size(),
+                           hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(E.data(), lay.E + (size_t)search * M2, sizeof(double) * M2, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(fr.data(), lay.fresh + (size_t)search * M2, M2, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    const int W = words_of(s->N[search / lay.L]);
+    for (int k = 0; k < nk; ++k) {
+        const int slot = kept[k];
+        for (int w = 0; w < W; ++w) bits_out[(size_t)k * W + w] = bits[(size_t)slot * lay.Wmax + w];
+        E_out[k] = E[slot];
+        if (front_out) front_out[k] = fr[slot];
+    }
+    *count = nk;
+    return ISING_OK;
+}
+
+extern "C" int ising_search_set_search(ising_search_t* s, int32_t search, const uint64_t* bits,
+                                       const uint8_t* front, int32_t count)
+{
+    g_err.clear();
+    int rc = check_handle(s);
+    if (rc != ISING_OK) return rc;
+    const Layout& lay = s->lay;
+    if (search < 0 || search >= lay.S) return fail(ISING_ERR_INVALID_ARG, "search %d outside [0, %d)", search, lay.S);
+    if (count < 1 || count > lay.M) return fail(ISING_ERR_INVALID_ARG, "count %d outside [1, M]", count);
+    if (!bits) return fail(ISING_ERR_INVALID_ARG, "bits is NULL");
+    const int n = s->N[search / lay.L];
+    const int W = words_of(n);
+    const int tail = n & 63;
+    for (int k = 0; k < count; ++k) {
+        if (tail && (bits[(size_t)k * W + W - 1] >> tail))
+            return fail(ISING_ERR_INVALID_ARG, "state %d has bits at positions >= N", k);
+        for (int q = 0; q < k; ++q)
+            if (std::memcmp(bits + (size_t)k * W, bits + (size_t)q * W, W * sizeof(uint64_t)) == 0)
+                return fail(ISING_ERR_INVALID_ARG, "states %d and %d are equal", q, k);
+    }
+    const int M = lay.M;
+    const size_t M2 = 2 * (size_t)M;
+    std::vector<uint64_t> hb((size_t)count * lay.Wmax, 0);
+    for (int k = 0; k < count; ++k)
+        for (int w = 0; w < W; ++w) hb[(size_t)k * lay.Wmax + w] = bits[(size_t)k * W + w];
+    std::vector<uint8_t> hf(M2, 0);
+    for (int k = 0; k < count; ++k) hf[k] = front ? (front[k] ? 1 : 0) : 1;
+    HIP_TRY(hipMemcpyAsync(lay.bits + (size_t)search * M2 * lay.Wmax, hb.data(), hb.size() * sizeof(uint64_t),
+                           hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(lay.fresh + (size_t)search * M2, hf.data(), M2, hipMemcpyHostToDevice, s->stream));
+    hipError_t e = launch_fields_for(lay, search, count, s->stream);
+    if (e != hipSuccess) return fail(ISING_ERR_HIP, "field kernel failed: %s", hipGetErrorString(e));
+    // order the kept list by (E, psi) on the host from the computed energies
+    std::vector<double> E(count);
+    HIP_TRY(hipMemcpyAsync(E.data(), lay.E + (size_t)search * M2, sizeof(double) * count, hipMemcpyDeviceToHost,
+                           s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    std::vector<int> order(count);
+    for (int k = 0; k < count; ++k) order[k] = k;
+    auto less = [&](int a, int b) {
+        if (E[a] != E[b]) return E[a] < E[b];
+        for (int w = W - 1; w >= 0; --w) {
+            const uint64_t x = bits[(size_t)a * W + w], y = bits[(size_t)b * W + w];
+            if (x != y) return x < y;
+        }
+        return false;
+    };
+    for (int i = 1; i < count; ++i)
+        for (int j = i; j > 0 && less(order[j], order[j - 1]); --j) std::swap(order[j], order[j - 1]);
+    const int one = 1, zero = 0;
+    HIP_TRY(hipMemcpyAsync(lay.kept + (size_t)search * M, order.data(), sizeof(int) * count, hipMemcpyHostToDevice,
+                           s->stream));
+    HIP_TRY(hipMemcpyAsync(lay.nkept + search, &count, sizeof(int), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(lay.active + search, &one, sizeof(int), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(lay.retry + search, &zero, sizeof(int), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->final_dirty = true;
+    return ISING_OK;
+}
+
+extern "C" int ising_search_get_stats(ising_search_t* s, ising_stats_t* out)
+{
+    g_err.clear();
+    int rc = check_handle(s);
+    if (rc != ISING_OK) return rc;
+    if (!out) return fail(ISING_ERR_INVALID_ARG, "out is NULL");
+    unsigned long long c[16];
+    HIP_TRY(hipMemcpyAsync(c, s->lay.ctr, sizeof c, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    std::memset(out, 0, sizeof *out);
+    out->steps = c[CTR_STEPS];
+    out->pair_evals = c[CTR_PAIRS];
+    out->single_evals = c[CTR_SINGLES];
+    out->frontier_states = c[CTR_FRONTIER];
+    out->survivors = c[CTR_SURV];
+    out->retries = c[CTR_RETRY];
+    out->fallbacks = c[CTR_FALLBACK];
+    return ISING_OK;
+}
+
+extern "C" void ising_search_destroy(ising_search_t* s)
+{
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> g(g_live_mu);
+        if (!g_live.erase(s)) return;
+    }
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    else (void)hipDeviceSynchronize();
+    free_all(s);
+    delete s;
+}

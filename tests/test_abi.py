@@ -1,0 +1,112 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point that include/ising_search.h declares, and rejects bad arguments and bad
+handles with the documented status codes (validation runs before any device
+call)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2010_00180_amd import binding, workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    out = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if fn.endswith(".h"):
+            src = open(os.path.join(inc, fn)).read()
+            out |= set(re.findall(r"\b(ising_search_[a-z_]+)\s*\(", src))
+    return out
+
+
+def test_library_exports_every_declared_symbol():
+    L = binding.load()
+    syms = declared_symbols()
+    assert syms == set(binding.EXPORTED)
+    for name in syms:
+        assert hasattr(L, name), name
+
+
+def _init(cfg, Ns, Js, hs, L, xs):
+    lib = binding.load()
+    B = len(Ns)
+    vp = ctypes.c_void_p
+    Jp = (vp * B)(*[J.ctypes.data for J in Js])
+    hp = (vp * B)(*[h.ctypes.data for h in hs])
+    xp = (vp * B)(*[x.ctypes.data for x in xs])
+    h = vp()
+    rc = lib.ising_search_init(ctypes.byref(h), ctypes.byref(cfg), B, (ctypes.c_int32 * B)(*Ns), Jp, hp, L, xp, None)
+    return rc, h
+
+
+def _good(N=10, L=2):
+    inst = workloads.make_instance(N, 42, L)
+    return inst
+
+
+@pytest.mark.parametrize("case", ["M0", "Mbig", "form", "reserved", "L0", "N0", "Nbig", "asym", "diag",
+                                  "nan", "offgrid", "stray", "bound"])
+def test_init_rejects_invalid_arguments(case):
+    inst = _good()
+    J, h, x = inst.J.copy(), inst.h.copy(), inst.init_bits.copy()
+    N, L = inst.N, 2
+    cfg = binding.IsingConfig(M=8)
+    if case == "M0":
+        cfg.M = 0
+    elif case == "Mbig":
+        cfg.M = 5000
+    elif case == "form":
+        cfg.form = 7
+    elif case == "reserved":
+        cfg.reserved[0] = 1
+    elif case == "L0":
+        L = 0
+    elif case == "N0":
+        N = 0
+    elif case == "Nbig":
+        N = 100000
+    elif case == "asym":
+        J[1, 2] += 2.0 ** -24
+    elif case == "diag":
+        J[3, 3] = 1.0
+    elif case == "nan":
+        h[0] = np.nan
+    elif case == "offgrid":
+        J[0, 1] = J[1, 0] = 0.1
+    elif case == "stray":
+        x[0, 0] |= np.uint64(1) << np.uint64(40)
+    elif case == "bound":
+        J[:] = 0.0
+        J[0, 1] = J[1, 0] = 2.0 ** 25
+    rc, hnd = _init(cfg, [N], [J], [h], L, [x])
+    assert rc == binding.ISING_ERR_INVALID_ARG, (case, rc, binding.last_error())
+    assert hnd.value is None
+    assert binding.last_error()
+
+
+def test_bad_handles_are_rejected():
+    lib = binding.load()
+    n = ctypes.c_int32(0)
+    assert lib.ising_search_step(None, ctypes.byref(n)) == binding.ISING_ERR_BAD_STATE
+    bogus = ctypes.create_string_buffer(256)
+    assert lib.ising_search_step(ctypes.cast(bogus, ctypes.c_void_p), ctypes.byref(n)) == binding.ISING_ERR_BAD_STATE
+    assert lib.ising_search_run(None, 1, None) == binding.ISING_ERR_BAD_STATE
+    lib.ising_search_destroy(None)
+    lib.ising_search_destroy(ctypes.cast(bogus, ctypes.c_void_p))  # ignored, never freed
+
+
+def test_init_without_device_reports_no_device():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except Exception:
+        pass
+    inst = _good()
+    rc, hnd = _init(binding.IsingConfig(M=8), [inst.N], [inst.J], [inst.h], 2, [inst.init_bits])
+    assert rc == binding.ISING_ERR_NO_DEVICE, binding.last_error()

@@ -1,0 +1,182 @@
+"""Parity of the HIP path with the CPU oracle, through the C ABI.
+
+Every comparison is exact: with J and h on the 2^-24 grid all energies are
+exact in FP64, so kept bitstrings, their order and their energies must be
+identical (this is stricter than the 1e-9 relative energy tolerance asked of
+the method).  Small cases are compared at every step; the full-size workload
+is compared on sampled searches and on properties that hold at any size.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2010_00180_amd import binding, workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    binding.load()
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_trajectory(inst, M, x0, max_steps=10000):
+    """Kept sets after each step, from the oracle's own step function."""
+    bits = np.asarray(x0, np.uint64).reshape(1, -1)
+    E, front = None, np.ones(1, np.uint8)
+    traj = []
+    for _ in range(max_steps):
+        ob, oE, of, n_new = oracle.step(inst.J, inst.h, M, bits, E, front)
+        traj.append((ob, oE, of))
+        if n_new == 0:
+            break
+        bits, E, front = ob, oE, of
+    return traj
+
+
+def assert_same_set(g, o, what):
+    gb, gE, gf = g
+    ob, oE, of = o
+    assert gb.shape == ob.shape, f"{what}: count {gb.shape} vs {ob.shape}"
+    assert np.array_equal(gb, ob), f"{what}: bitstrings differ"
+    assert np.array_equal(gE, oE), f"{what}: energies differ (max {np.max(np.abs(gE - oE))})"
+    assert np.array_equal(gf.astype(bool), of.astype(bool)), f"{what}: new-state flags differ"
+
+
+def stepwise_parity(w, tag, **kw):
+    note(f"[{tag}] Ns={[i.N for i in w.instances]} L={w.L} M={w.M} {kw}")
+    s = binding.IsingSearch.from_workload(w, **kw)
+    trajs = {}
+    for b, inst in enumerate(w.instances):
+        for l in range(w.L):
+            trajs[b * w.L + l] = oracle_trajectory(inst, w.M, inst.init_bits[l])
+    nsteps = max(len(t) for t in trajs.values())
+    for t in range(nsteps):
+        active = s.step()
+        for sid, traj in trajs.items():
+            o = traj[min(t, len(traj) - 1)]
+            assert_same_set(s.get_search(sid), o if t < len(traj) else (o[0], o[1], np.zeros_like(o[2])),
+                            f"{tag} search {sid} step {t + 1}")
+        want_active = sum(1 for traj in trajs.values() if t + 1 < len(traj))
+        assert active == want_active, f"{tag} step {t + 1}: {active} active, oracle {want_active}"
+    assert s.step() == 0
+    for b, inst in enumerate(w.instances):
+        lists = [(trajs[b * w.L + l][-1][0], trajs[b * w.L + l][-1][1]) for l in range(w.L)]
+        mb, mE = oracle.merge(inst.N, w.M, lists)
+        gb, gE = s.get_states(b)
+        assert np.array_equal(gb, mb) and np.array_equal(gE, mE), f"{tag} instance {b} merge"
+    st = s.stats()
+    s.destroy()
+    return st
+
+
+def test_c1_n24_stepwise_and_brute_force():
+    w = wl.c1_n24()
+    st = stepwise_parity(w, "c1")
+    assert st["pair_evals"] > 0
+    inst = w.instances[0]
+    bb, bE = oracle.brute_lowest(inst.J, inst.h, w.M)
+    s = binding.IsingSearch.from_workload(w)
+    s.run()
+    gb, gE = s.get_states(0)
+    # the search never reports an energy below the true k-th lowest
+    assert np.all(gE >= bE[: len(gE)])
+    note(f"c1: found ground state {gE[0] == bE[0]}; lowest kept {gE[:3]}, exact {bE[:3]}")
+    s.destroy()
+
+
+@pytest.mark.parametrize("N,M,L", [(1, 1, 2), (2, 3, 2), (3, 8, 2), (5, 40, 2), (24, 1, 3), (63, 7, 2),
+                                   (64, 40, 2), (65, 120, 2), (100, 17, 2), (130, 60, 1), (200, 120, 1)])
+def test_sizes_stepwise(N, M, L):
+    w = wl.custom([N], L=L, M=M, config=11, seed_offset=N * 7 + M)
+    stepwise_parity(w, f"size N={N} M={M}")
+
+
+@pytest.mark.parametrize("dist", ["pmj", "sk_h0", "uniform"])
+def test_ties_and_symmetry_stepwise(dist):
+    w = wl.custom([40, 70], L=2, M=50, config=12, dist=dist)
+    stepwise_parity(w, f"ties {dist}")
+
+
+def test_uneven_sizes_one_handle():
+    w = wl.custom([5, 64, 65, 100, 129], L=2, M=30, config=13)
+    stepwise_parity(w, "uneven")
+
+
+@pytest.mark.parametrize("sc", [1, 7, 64, 200])
+def test_tile_configuration_does_not_change_results(sc):
+    w = wl.custom([90, 150], L=3, M=40, config=14)
+    stepwise_parity(w, f"sc={sc}", states_per_item=sc)
+
+
+def test_checkpoint_restore_continues_identically():
+    w = wl.custom([80, 120], L=3, M=30, config=15)
+    note("[checkpoint]")
+    a = binding.IsingSearch.from_workload(w)
+    for _ in range(3):
+        a.step()
+    b = binding.IsingSearch.from_workload(w)
+    for sid in range(a.B * a.L):
+        bits, E, fr = a.get_search(sid)
+        b.set_search(sid, bits, fr)
+        gb, gE, gf = b.get_search(sid)
+        assert np.array_equal(gb, bits) and np.array_equal(gE, E) and np.array_equal(gf, fr)
+    a.run()
+    b.run()
+    for sid in range(a.B * a.L):
+        assert_same_set(b.get_search(sid), a.get_search(sid), f"restored search {sid}")
+    a.destroy()
+    b.destroy()
+
+
+def test_iteration_cap_reports_not_converged():
+    w = wl.custom([150], L=2, M=60, config=16)
+    s = binding.IsingSearch.from_workload(w)
+    it, stable = s.run(max_iters=2)
+    assert it == 2 and not stable
+    it2, stable2 = s.run()
+    assert stable2
+    trajs = [oracle_trajectory(w.instances[0], w.M, x) for x in w.instances[0].init_bits]
+    assert it + it2 == max(len(t) for t in trajs)
+    for l in range(2):
+        assert_same_set(s.get_search(l), (trajs[l][-1][0], trajs[l][-1][1], np.zeros_like(trajs[l][-1][2])),
+                        f"cap search {l}")
+    s.destroy()
+
+
+def test_c2_full_size_sampled():
+    """120 instances, N=200, L=16, M=120, as the benchmark runs them."""
+    w = wl.c2_n200()
+    note("[c2] full workload")
+    s = binding.IsingSearch.from_workload(w)
+    it, stable = s.run()
+    assert stable
+    note(f"[c2] steps={it} stats={s.stats()}")
+    rng = np.random.default_rng(2)
+    for sid in rng.choice(w.n_searches, 2, replace=False):
+        b, l = divmod(int(sid), w.L)
+        inst = w.instances[b]
+        ob, oE, oit, ostable = oracle.search(inst.J, inst.h, w.M, inst.init_bits[l])
+        gb, gE, gf = s.get_search(int(sid))
+        assert np.array_equal(gb, ob) and np.array_equal(gE, oE), f"c2 search {sid}"
+        assert oit <= it
+    for b in rng.choice(len(w.instances), 4, replace=False):
+        inst = w.instances[b]
+        gb, gE = s.get_states(int(b))
+        assert len(gE) == w.M
+        assert np.all(np.diff(gE) >= 0)
+        assert len({tuple(r) for r in gb}) == len(gb)
+        for k in rng.choice(len(gE), 5, replace=False):
+            assert oracle.energy(inst.J, inst.h, gb[k]) == gE[k]
+    s.destroy()
