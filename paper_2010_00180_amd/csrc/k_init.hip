@@ -12,7 +12,7 @@ namespace qi {
 // Operand layout of v_mfma_f64_16x16x4_f64 (per lane l):
 //   A[i][k]: i = l % 16, k = l / 16        (J4 rows = sites, k = summed site)
 //   B[k][j]: j = l % 16, k = l / 16        (spins of search j at site k)
-//   D[i][j]: 4 values, i = 4*(l/16) + r, j = l % 16
+//   D[i][j]: 4 values, i = l/16 + 4*r, j = l % 16   (register r of lane l)
 __global__ __launch_bounds__(64) void k_init_fields(Layout lay, const double* __restrict__ J4,
                                                     const uint64_t* __restrict__ x0)
 {
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(64) void k_init_fields(Layout lay, const double* __
     const double* h = lay.h + (size_t)b * lay.Npmax;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int site = row0 + 4 * (lane >> 4) + r;
+        const int site = row0 + (lane >> 4) + 4 * r;
         if (site < Np) F[site] = site < N ? h[site] + 0.25 * acc[r] : 0.0;
     }
 }
