@@ -1,0 +1,209 @@
+"""Benchmark of the synchronous quantum-inspired search on one MI355X.
+
+One benchmark step is one complete pass of the method over the whole batch:
+restart every search from its initial state (local fields on the matrix cores,
+energies), step all searches until every kept set is stable, and merge the L
+searches of each instance (Alg. 4).  The inputs are resident in HBM before the
+timed region starts.
+
+Workload: 120 instances, N = 600, J_ij ~ N(0,1)/sqrt(N), h_i ~ N(0,1) (both on
+the 2^-24 grid), M = 120 kept states, 64 initial states per instance, plain
+FP64 form.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pair-flip ΔE evals/s + time-to-solution/instance at N=600,M=120 vs plain"
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz; FP64 add/compare and 32-bit
+# integer VALU ops each issue at this lane rate (78.6 TFLOP/s FP64 counts an FMA as 2).
+VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
+OPS_PER_PAIR = 3          # sign applied to 4J_ij, add a_j, compare with T - a_i
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for rel in ("paper_2010_00180_amd/csrc/k_step.hip", "paper_2010_00180_amd/csrc/common.h"):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(digest):
+    """Per-launch HBM bytes of the scan from the committed counter summary, if it
+    was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "k_scan_c3_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_digest") != digest:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(w, budget_s):
+    """The CPU oracle on a bounded sample of the same workload: one synchronous
+    step of search 0 of instance 0 from its first kept set, expanding as many
+    new states as fit the time budget."""
+    import numpy as np
+    import oracle
+    inst = w.instances[0]
+    N, M = inst.N, w.M
+    pairs = N * (N - 1) // 2
+    t0 = time.time()
+    b1, E1, f1, _ = oracle.step(inst.J, inst.h, M, inst.init_bits[:1])
+    t1 = time.time()
+    per_state = max(t1 - t0, 1e-3)
+    k = int(max(1, min(len(E1), (budget_s - (t1 - t0)) / per_state)))
+    front = np.zeros(len(E1), np.uint8)
+    front[:k] = 1
+    t2 = time.time()
+    oracle.step(inst.J, inst.h, M, b1, E1, front)
+    t3 = time.time()
+    evals = pairs * (1 + k)
+    secs = (t1 - t0) + (t3 - t2)
+    return {
+        "value": evals / secs,
+        "unit": "pair-flip dE evals/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"instance 0 search 0 of the same workload: the first step from x0 (1 state) and one "
+                   f"step from S_1 expanding {k} of its new states; {evals} pair flips, "
+                   f"O(N) flipped-site energy change each, {secs:.1f} s"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--instances", type=int, default=120)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="after the timed region, copy this many GiB with torch (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              f"(the searches shard by instance with no exchange; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2010_00180_amd import binding, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = workloads.c3_n600(n_instances=args.instances)
+    log(f"workload {w.name}: {len(w.instances)} instances, L={w.L}, M={w.M}")
+    s = binding.IsingSearch.from_workload(w, timing=1)
+    torch.cuda.synchronize()
+
+    def one_pass():
+        s.reset()
+        it, stable = s.run()
+        s.get_states(0)
+        return it, stable
+
+    for k in range(args.warmup):
+        it, stable = one_pass()
+        log(f"warmup {k}: {it} iterations, stable={stable}")
+    st0 = s.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    for k in range(args.steps):
+        it, stable = one_pass()
+        iters.append(it)
+        log(f"step {k}: {it} iterations, stable={stable}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st1 = s.stats()
+    wall = t1 - t0
+    d = {k: st1[k] - st0[k] for k in st1}
+    pairs = d["pair_evals"]
+    value = pairs / wall
+    scan_s = d["scan_ms"] / 1e3
+    launches = max(d["scan_launches"], 1)
+    ops_per_s = OPS_PER_PAIR * pairs / scan_s if scan_s > 0 else 0.0
+    digest = source_digest()
+    traffic = load_traffic(digest)
+
+    E1 = [float(s.get_states(b)[1][0]) for b in range(len(w.instances))]
+    per_inst = wall / args.steps / len(w.instances)
+
+    if args.copy_gib > 0:
+        n = int(args.copy_gib * (1 << 30)) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {n * 8} bytes read, {n * 8} bytes written")
+
+    cpu = None
+    if not args.no_cpu:
+        log("timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(w, args.cpu_seconds)
+    s.destroy()
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pair-flip dE evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{w.name}: {len(w.instances)} instances N=600 J~N(0,1)/sqrt(N) h~N(0,1) on the 2^-24 grid, "
+                        f"M={w.M} kept, L={w.L} initial states each, plain FP64 form, run to stable",
+            "instances": len(w.instances), "N": 600, "M": w.M, "L": w.L, "form": "plain",
+        },
+        "time_per_instance_s": per_inst,
+        "tts_per_instance_s": per_inst,
+        "tts_note": "p1 = 1 against the best energy this run finds (no certified reference at N=600), so TTS = t",
+        "iterations": iters,
+        "mean_E1": sum(E1) / len(E1),
+        "scan_kernel_evals_per_s": pairs / scan_s if scan_s > 0 else None,
+        "kernel_ms_per_step": {k: d[k + "_ms"] / args.steps for k in ("scan", "merge", "frontier", "prep", "init")},
+        "survivors": d["survivors"],
+        "retries": d["retries"],
+        "roofline": {
+            "kernel": "k_scan",
+            "bound": "alu",
+            "achieved": ops_per_s / 1e12,
+            "peak": VALU_LANE_OPS_PER_S / 1e12,
+            "unit": "Tops/s",
+            "frac": ops_per_s / VALU_LANE_OPS_PER_S,
+            "traffic": traffic,
+            "avg_launch_ms": d["scan_ms"] / launches,
+            "ops_per_pair": OPS_PER_PAIR,
+            "source_digest": digest,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -63,7 +63,8 @@ typedef struct {
     int32_t states_per_item;   /* scan tile: frontier states per work item; 0 = tuned default */
     int32_t topk_factor;       /* learned form: K = topk_factor * N pairs per state (default 8) */
     int32_t persistent;        /* 1 = capture one step into a hipGraph and replay it in run() */
-    int32_t reserved[2];       /* must be zero */
+    int32_t timing;            /* 1 = time every kernel family with hipEvents on the handle's stream */
+    int32_t reserved;          /* must be zero */
 } ising_config_t;
 
 typedef struct {
@@ -74,7 +75,13 @@ typedef struct {
     uint64_t survivors;        /* candidates that passed the scan's cut, summed over steps */
     uint64_t retries;          /* re-scans of a search after its candidate buffer filled */
     uint64_t fallbacks;        /* split form: states re-scanned in FP64; learned form: full scans */
-    uint64_t reserved[5];
+    uint64_t scan_launches;    /* launches of the pair-scan kernel */
+    double scan_ms;            /* device time of the pair-scan kernel (cfg.timing = 1), summed */
+    double merge_ms;           /* device time of the per-search merge, summed */
+    double frontier_ms;        /* device time of frontier listing, pilot cut and planning, summed */
+    double prep_ms;            /* device time of the per-state preparation, summed */
+    double init_ms;            /* device time of local fields and seeding (init and reset), summed */
+    uint64_t reserved[2];
 } ising_stats_t;
 
 /*
@@ -102,6 +109,14 @@ typedef struct {
 int ising_search_init(ising_search_t **out, const ising_config_t *cfg, int32_t n_inst,
                       const int32_t *N, const double *const *J, const double *const *h,
                       int32_t L, const uint64_t *const *init_bits, void *stream);
+
+/*
+ * Restart every search from its initial state (the L states given to init,
+ * kept on the device): local fields by the FP64 MFMA GEMM, energies, and
+ * S_0 = {x0}.  Statistics counters are kept.  Lets a caller repeat a search
+ * without copying the instances again.
+ */
+int ising_search_reset(ising_search_t *s);
 
 /*
  * One synchronous step of every search still running (Sec. II): expand the

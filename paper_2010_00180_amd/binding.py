@@ -31,6 +31,7 @@ FORM_LEARNED = 2
 
 EXPORTED = (
     "ising_search_init",
+    "ising_search_reset",
     "ising_search_step",
     "ising_search_run",
     "ising_search_get_states",
@@ -50,7 +51,8 @@ class IsingConfig(ctypes.Structure):
         ("states_per_item", ctypes.c_int32),
         ("topk_factor", ctypes.c_int32),
         ("persistent", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("timing", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -63,11 +65,17 @@ class IsingStats(ctypes.Structure):
         ("survivors", ctypes.c_uint64),
         ("retries", ctypes.c_uint64),
         ("fallbacks", ctypes.c_uint64),
-        ("reserved", ctypes.c_uint64 * 5),
+        ("scan_launches", ctypes.c_uint64),
+        ("scan_ms", ctypes.c_double),
+        ("merge_ms", ctypes.c_double),
+        ("frontier_ms", ctypes.c_double),
+        ("prep_ms", ctypes.c_double),
+        ("init_ms", ctypes.c_double),
+        ("reserved", ctypes.c_uint64 * 2),
     ]
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class IsingError(RuntimeError):
@@ -92,6 +100,8 @@ def load(path: str = LIB_PATH):
     L.ising_search_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(IsingConfig), ctypes.c_int32,
                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                     ctypes.c_int32, ctypes.POINTER(vp), vp]
+    L.ising_search_reset.restype = ctypes.c_int
+    L.ising_search_reset.argtypes = [vp]
     L.ising_search_step.restype = ctypes.c_int
     L.ising_search_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.ising_search_run.restype = ctypes.c_int
@@ -142,7 +152,7 @@ class IsingSearch:
 
     def __init__(self, Ns: Sequence[int], Js, hs, init_bits, M: int, form: int = FORM_PLAIN,
                  max_iters: int = 0, states_per_item: int = 0, topk_factor: int = 8,
-                 persistent: int = 0, stream: Optional[int] = None):
+                 persistent: int = 0, timing: int = 0, stream: Optional[int] = None):
         L = load()
         self.Ns = [int(n) for n in Ns]
         self.B = len(self.Ns)
@@ -170,7 +180,7 @@ class IsingSearch:
         Narr = (ctypes.c_int32 * self.B)(*self.Ns)
         cfg = IsingConfig(M=self.M, max_iters=int(max_iters), form=int(form),
                           states_per_item=int(states_per_item), topk_factor=int(topk_factor),
-                          persistent=int(persistent))
+                          persistent=int(persistent), timing=int(timing))
         if stream is None:
             stream = current_stream_handle()
         h = ctypes.c_void_p()
@@ -187,6 +197,9 @@ class IsingSearch:
     @property
     def handle(self):
         return self._h
+
+    def reset(self):
+        _check(load().ising_search_reset(self._h))
 
     def step(self) -> int:
         n = ctypes.c_int32(0)

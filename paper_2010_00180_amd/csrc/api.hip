@@ -53,8 +53,14 @@ struct ising_search {
     int scan_grid = 0;
     bool final_dirty = true;
     std::vector<void*> allocs;
+    uint64_t* x0 = nullptr;      // initial states, kept for reset
     // host mirrors of small device buffers
     int flags_h[8]{};
+    // timing (cfg.timing): events around each kernel family of a step
+    bool timing = false;
+    hipEvent_t ev[6]{};
+    double t_scan = 0, t_merge = 0, t_frontier = 0, t_prep = 0, t_init = 0;
+    uint64_t scan_launches = 0;
 };
 
 namespace {
@@ -87,6 +93,20 @@ void free_all(ising_search* h)
 {
     for (void* p : h->allocs) (void)hipFree(p);
     h->allocs.clear();
+    for (hipEvent_t& e : h->ev) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+    }
+}
+
+float elapsed_ms(hipEvent_t a, hipEvent_t b)
+{
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0.f;
+    }
+    return ms;
 }
 
 uint64_t splitmix64(uint64_t& x)
@@ -139,7 +159,7 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     if (cfg->M < 1 || cfg->M > 1024) return fail(ISING_ERR_INVALID_ARG, "M=%d outside [1, 1024]", cfg->M);
     if (cfg->form != ISING_FORM_PLAIN)
         return fail(ISING_ERR_INVALID_ARG, "form %d is not available in this build", cfg->form);
-    if (cfg->reserved[0] || cfg->reserved[1]) return fail(ISING_ERR_INVALID_ARG, "reserved fields must be zero");
+    if (cfg->reserved) return fail(ISING_ERR_INVALID_ARG, "reserved fields must be zero");
     if (cfg->states_per_item < 0 || cfg->states_per_item > 4096)
         return fail(ISING_ERR_INVALID_ARG, "states_per_item=%d outside [0, 4096]", cfg->states_per_item);
     if (n_inst < 1) return fail(ISING_ERR_INVALID_ARG, "n_inst=%d < 1", n_inst);
@@ -242,7 +262,8 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     ALLOC(lay.fr_count, n_inst);
     ALLOC(lay.fr_list, (size_t)n_inst * lay.fmax);
     ALLOC(lay.A, (size_t)n_inst * lay.fmax * lay.Npmax);
-    ALLOC(lay.T, (size_t)n_inst * lay.fmax);
+    ALLOC(lay.rec, (size_t)n_inst * lay.fmax);
+    ALLOC(lay.fbits, (size_t)n_inst * lay.fmax * lay.Wmax);
     ALLOC(lay.surv_count, S);
     ALLOC(lay.surv, S * lay.cap_surv);
     ALLOC(lay.item_prefix, 2 * ((size_t)n_inst + 1));
@@ -263,6 +284,17 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     lay.J4 = dJ4;
     lay.h = dh;
     lay.zkey = dz;
+    hd->x0 = dx0;
+    hd->timing = cfg->timing != 0;
+    if (hd->timing) {
+        for (hipEvent_t& e : hd->ev) {
+            if (hipEventCreate(&e) != hipSuccess) {
+                free_all(hd);
+                delete hd;
+                return fail(ISING_ERR_HIP, "hipEventCreate failed");
+            }
+        }
+    }
 
     // host staging of padded 4J and h
     auto bail = [&](int code) {
@@ -305,8 +337,11 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
         if (r2 == ISING_OK) {
             hipError_t e = hipMemsetAsync(lay.ctr, 0, 16 * sizeof(unsigned long long), sm);
             if (e == hipSuccess) e = hipMemsetAsync(lay.flags, 0, 8 * sizeof(int), sm);
+            if (e == hipSuccess && hd->timing) e = hipEventRecord(hd->ev[0], sm);
             if (e == hipSuccess) e = launch_init_fields(lay, dx0, sm);
+            if (e == hipSuccess && hd->timing) e = hipEventRecord(hd->ev[1], sm);
             if (e == hipSuccess) e = hipStreamSynchronize(sm);
+            if (e == hipSuccess && hd->timing) hd->t_init += elapsed_ms(hd->ev[0], hd->ev[1]);
             if (e != hipSuccess) r2 = fail(ISING_ERR_HIP, "initialisation kernels failed: %s", hipGetErrorString(e));
         }
         if (r2 != ISING_OK) return bail(r2);
@@ -324,11 +359,44 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     return ISING_OK;
 }
 
+// One pass of the step kernels; with timing on, events bracket each family.
+static hipError_t launch_pass(ising_search* h, bool retry_mode)
+{
+    const Layout& lay = h->lay;
+    hipStream_t st = h->stream;
+    hipEvent_t* ev = h->ev;
+    const bool tm = h->timing;
+    hipError_t e = hipSuccess;
+    auto rec = [&](int k) {
+        if (tm && e == hipSuccess) e = hipEventRecord(ev[k], st);
+    };
+    rec(0);
+    if (e == hipSuccess) e = launch_step_begin(lay, retry_mode, st);
+    if (e == hipSuccess && !retry_mode) e = launch_frontier_plan(lay, st);
+    rec(1);
+    if (e == hipSuccess) e = launch_prep(lay, st);
+    rec(2);
+    if (e == hipSuccess) e = launch_scan(lay, h->scan_grid, st);
+    rec(3);
+    if (e == hipSuccess) e = launch_merge(lay, st);
+    rec(4);
+    if (e == hipSuccess) ++h->scan_launches;
+    return e;
+}
+
+static void collect_times(ising_search* h)
+{
+    if (!h->timing) return;
+    h->t_frontier += elapsed_ms(h->ev[0], h->ev[1]);
+    h->t_prep += elapsed_ms(h->ev[1], h->ev[2]);
+    h->t_scan += elapsed_ms(h->ev[2], h->ev[3]);
+    h->t_merge += elapsed_ms(h->ev[3], h->ev[4]);
+}
+
 static int do_step(ising_search* h, int32_t* n_active)
 {
     const Layout& lay = h->lay;
-    hipError_t e = launch_step_begin(lay, false, h->stream);
-    if (e == hipSuccess) e = launch_step(lay, h->scan_grid, false, h->stream);
+    hipError_t e = launch_pass(h, false);
     if (e != hipSuccess) {
         h->broken = true;
         return fail(ISING_ERR_HIP, "step launch failed: %s", hipGetErrorString(e));
@@ -338,14 +406,14 @@ static int do_step(ising_search* h, int32_t* n_active)
         h->broken = true;
         return rc;
     }
+    collect_times(h);
     int guard = 0;
     while (h->flags_h[FLAG_OVERFLOW] > 0) {
         if (h->flags_h[FLAG_STUCK] > 0 || ++guard > 64)
             return fail(ISING_ERR_CAPACITY,
                         "a search has more tied candidates at its cut than its buffer holds (%d records)",
                         lay.cap_surv);
-        e = launch_step_begin(lay, true, h->stream);
-        if (e == hipSuccess) e = launch_step(lay, h->scan_grid, true, h->stream);
+        e = launch_pass(h, true);
         if (e != hipSuccess) {
             h->broken = true;
             return fail(ISING_ERR_HIP, "retry launch failed: %s", hipGetErrorString(e));
@@ -355,9 +423,29 @@ static int do_step(ising_search* h, int32_t* n_active)
             h->broken = true;
             return rc;
         }
+        collect_times(h);
     }
     h->final_dirty = true;
     if (n_active) *n_active = h->flags_h[FLAG_ACTIVE];
+    return ISING_OK;
+}
+
+extern "C" int ising_search_reset(ising_search_t* s)
+{
+    g_err.clear();
+    int rc = check_handle(s);
+    if (rc != ISING_OK) return rc;
+    hipError_t e = hipSuccess;
+    if (s->timing) e = hipEventRecord(s->ev[0], s->stream);
+    if (e == hipSuccess) e = launch_init_fields(s->lay, s->x0, s->stream);
+    if (e == hipSuccess && s->timing) e = hipEventRecord(s->ev[1], s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        s->broken = true;
+        return fail(ISING_ERR_HIP, "reset kernels failed: %s", hipGetErrorString(e));
+    }
+    if (s->timing) s->t_init += elapsed_ms(s->ev[0], s->ev[1]);
+    s->final_dirty = true;
     return ISING_OK;
 }
 
@@ -533,6 +621,12 @@ extern "C" int ising_search_get_stats(ising_search_t* s, ising_stats_t* out)
     out->survivors = c[CTR_SURV];
     out->retries = c[CTR_RETRY];
     out->fallbacks = c[CTR_FALLBACK];
+    out->scan_launches = s->scan_launches;
+    out->scan_ms = s->t_scan;
+    out->merge_ms = s->t_merge;
+    out->frontier_ms = s->t_frontier;
+    out->prep_ms = s->t_prep;
+    out->init_ms = s->t_init;
     return ISING_OK;
 }
 

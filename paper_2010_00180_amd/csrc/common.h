@@ -10,27 +10,37 @@
 //   kept   per search: up to M slot ids sorted by (E, psi).
 //   front  per instance: list of (search, slot) of states to expand.
 //   A      per frontier entry: a_i = -2 s_i F_i (the single-flip change).
-//   surv   per search: candidate records {E_child, frontier entry, i | j<<16}.
+//   surv   per search: candidate records {E_child, parent slot, i | j<<16}.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace qi {
 
-constexpr int TILE = 64;            // rows/cols of one J tile (one row per lane)
+constexpr int TILE = 64;            // rows of one J tile (one row per lane)
+constexpr int TCOL = 32;            // columns of one J tile held in registers
 constexpr int MAX_N = 4096;         // pair indices are packed into 16 bits
 constexpr int PILOT_K = 48;         // lightest sites used for the per-search pilot cut
 constexpr int MERGE_CH = 4096;      // candidates sorted per merge pass (LDS)
-constexpr int STAGE = 512;          // wave-private survivor staging (records)
+constexpr int STAGE = 256;          // wave-private survivor staging (records)
 constexpr uint32_t SINGLE = 0xFFFFu;   // j field of a single-flip record
 constexpr uint32_t REF_SURV = 0x80000000u;
 
 struct Surv {
     double E;        // energy of the child
-    uint32_t f;      // frontier entry (index within its instance's list)
+    uint32_t code;   // pool slot of the parent: search * 2M + slot
     uint32_t pair;   // i | j << 16, j = SINGLE for a single flip
 };
 static_assert(sizeof(Surv) == 16, "record layout");
+
+// What the scan needs of one frontier state besides its a_i values.
+struct FrRec {
+    double T;        // cut - E: a pair survives iff a_i + a_j + 4 s_i s_j J_ij <= T
+    double E;        // energy of the state
+    int s;           // search
+    int code;        // s * 2M + slot
+};
+static_assert(sizeof(FrRec) == 24, "record layout");
 
 // Everything the kernels need, passed by value.
 struct Layout {
@@ -60,7 +70,8 @@ struct Layout {
     int* fr_count;           // [B]
     int* fr_list;            // [B][fmax] : s * 2M + slot
     double* A;               // [B][fmax][Npmax]
-    double* T;               // [B][fmax] : cut[s] - E (scan threshold on a_i + a_j + sJ)
+    FrRec* rec;              // [B][fmax]
+    uint64_t* fbits;         // [B][fmax][Wmax] : copy of the state's words
     // survivors
     int* surv_count;         // [S]
     Surv* surv;              // [S][cap_surv]
@@ -80,15 +91,20 @@ enum { FLAG_ACTIVE = 0, FLAG_OVERFLOW = 1, FLAG_STUCK = 2, FLAG_RETRY_MODE = 3 }
 
 __host__ __device__ inline int words_of(int N) { return (N + 63) >> 6; }
 __host__ __device__ inline int pad_of(int N) { return (N + TILE - 1) / TILE * TILE; }
+// Tiles of 64 rows x 32 columns that hold pairs i < j: row block bi meets
+// column blocks bc >= 2*bi of the nc = Npad/32 column blocks.
 __host__ __device__ inline long long tiles_of(int N) {
-    long long nb = (N + TILE - 1) / TILE;
-    return nb * (nb + 1) / 2;
+    const long long nb = (N + TILE - 1) / TILE, nc = 2 * nb;
+    return nb * nc - nb * (nb - 1);
 }
 
 // Host launchers (defined next to their kernels).
 hipError_t launch_init_fields(const Layout& lay, const uint64_t* d_x0, hipStream_t st);
 hipError_t launch_fields_for(const Layout& lay, int search, int count, hipStream_t st);
-hipError_t launch_step(const Layout& lay, int scan_grid, bool retry_mode, hipStream_t st);
+hipError_t launch_frontier_plan(const Layout& lay, hipStream_t st);
+hipError_t launch_prep(const Layout& lay, hipStream_t st);
+hipError_t launch_scan(const Layout& lay, int scan_grid, hipStream_t st);
+hipError_t launch_merge(const Layout& lay, hipStream_t st);
 hipError_t launch_step_begin(const Layout& lay, bool retry_mode, hipStream_t st);
 hipError_t launch_final(const Layout& lay, hipStream_t st);
 

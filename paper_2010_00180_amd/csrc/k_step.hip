@@ -13,7 +13,7 @@
 //                 the lightest sites of its lowest new state)
 //   k_plan        per-instance work prefix sums for the scan and the prep
 //   k_prep        per frontier state: a_i, the scan threshold, single flips
-//   k_scan        per (instance, chunk of states, 64x64 tile of pairs): every
+//   k_scan        per (instance, chunk of states, 64x32 tile of pairs): every
 //                 pair energy change, filtered by the cut, survivors recorded
 //   k_merge       per search: sort kept + survivors by (E, psi), drop
 //                 duplicates, keep M, write new states and their local fields
@@ -106,17 +106,36 @@ __device__ inline int pow2_at_least(int n)
 // only ones whose neighbourhoods can hold anything new), and sets the cut on
 // child energies.  The cut starts at the M-th kept energy (a child above it
 // ranks behind the whole kept set, the paper's "E < E_{K+1}" acceptance test).
-// The pilot tightens it: the M lowest of any M distinct children of one state
-// bound the M-th lowest distinct state of the union from above, so
-//   cut = min(E_M, E_p + theta),  theta = M-th smallest energy change among
-// the single flips of the K lightest sites of the lowest new state p and the
-// pair flips among them (exact values; only their selection is heuristic).
+// Pilots tighten it: any M distinct members of the union bound its M-th
+// lowest distinct energy from above.  The pilots are the NPILOT lowest new
+// states; each offers its single flips and pair flips among its PILOT_K
+// lightest sites (lowest a_i), with exact energies.  Two such children of
+// pilots p, q are the same state iff x_p xor x_q equals the symmetric
+// difference of their flip sets, which is checked exactly from the pilots'
+// words, so the pool's M-th distinct energy is a valid cut.
+constexpr int NPILOT = 4;
+constexpr int PK = 32;                       // lightest sites per pilot
+constexpr int PCAND = PK * (PK + 1) / 2;     // candidates per pilot
+
+__device__ inline void cand_sites(uint32_t id, int* out, int& n)
+{
+    // id = pilot << 26 | single << 25 | i << 12 | j
+    n = 0;
+    out[n++] = (int)((id >> 12) & 0xFFFu);
+    if (!((id >> 25) & 1u)) out[n++] = (int)(id & 0xFFFu);
+}
+
 __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __restrict__ J4)
 {
     __shared__ double key[MAX_N];
     __shared__ uint32_t idx[MAX_N];
+    __shared__ double pE[NPILOT * PCAND];
+    __shared__ uint32_t pid[NPILOT * PCAND];
     __shared__ int tmp[256];
-    __shared__ int s_pilot;
+    __shared__ int pslot[NPILOT];
+    __shared__ int dsites[NPILOT][NPILOT][5];   // [0] = count (5 = farther than 4 flips)
+    __shared__ double aK[PK];
+    __shared__ int iK[PK];
     const int s = blockIdx.x;
     const int b = s / lay.L;
     const int M = lay.M;
@@ -129,29 +148,22 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
     const size_t q0 = (size_t)s * 2 * M;
 
     // rank the new states in kept (energy) order
-    int base_rank = 0;
-    if (threadIdx.x == 0) s_pilot = -1;
-    __syncthreads();
-    int fr_base = 0;
+    int nfresh = 0;
     for (int c0 = 0; c0 < nk; c0 += 256) {
         const int k = c0 + threadIdx.x;
         const int slot = k < nk ? kept[k] : 0;
         const int isnew = (k < nk && lay.fresh[q0 + slot]) ? 1 : 0;
         int excl;
         const int tot = block_exclusive_scan(isnew, tmp, excl);
-        if (isnew) idx[base_rank + excl] = (uint32_t)slot;   // temporary list of new slots
-        base_rank += tot;
+        if (isnew) idx[nfresh + excl] = (uint32_t)slot;   // new slots, lowest energy first
+        nfresh += tot;
     }
     __syncthreads();
-    const int nfresh = base_rank;
-    if (threadIdx.x == 0 && nfresh > 0) {
-        fr_base = atomicAdd(&lay.fr_count[b], nfresh);
-        s_pilot = (int)idx[0];
-        tmp[0] = fr_base;
-    }
+    if (threadIdx.x == 0 && nfresh > 0) tmp[0] = atomicAdd(&lay.fr_count[b], nfresh);
+    if ((int)threadIdx.x < NPILOT) pslot[threadIdx.x] = (int)threadIdx.x < nfresh ? (int)idx[threadIdx.x] : -1;
     __syncthreads();
     if (nfresh > 0) {
-        fr_base = tmp[0];
+        const int fr_base = tmp[0];
         for (int r = threadIdx.x; r < nfresh; r += blockDim.x)
             lay.fr_list[(size_t)b * lay.fmax + fr_base + r] = (int)(s * 2 * M + idx[r]);
     }
@@ -161,58 +173,129 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
         if (threadIdx.x == 0) lay.cut[s] = ecut;
         return;
     }
-
-    // pilot: lowest new state p (first new one in energy order)
     const int N = lay.N[b], Np = lay.Npad[b];
-    const int ps = s_pilot;
-    const uint64_t* xp = lay.bits + (q0 + ps) * lay.Wmax;
-    const double* Fp = lay.F + (q0 + ps) * lay.Npmax;
-    const double Ep = lay.E[q0 + ps];
-    const int n2 = pow2_at_least(N);
-    for (int i = threadIdx.x; i < n2; i += blockDim.x) {
-        key[i] = i < N ? -2.0 * spin_of(xp, i) * Fp[i] : INFINITY;
-        idx[i] = (uint32_t)i;
-    }
-    __syncthreads();
-    bitonic_sort(key, idx, n2, PlainLess());
-    const int K = N < PILOT_K ? N : PILOT_K;
+    const int W = words_of(N);
+    const int K = N < PK ? N : PK;
     const int nc = K * (K + 1) / 2;
-    double theta = INFINITY;
-    if (nc >= M) {
-        // candidates: K singles and K(K-1)/2 pairs, written behind the sorted prefix
-        __shared__ double aK[PILOT_K];
-        __shared__ int iK[PILOT_K];
-        if (threadIdx.x < K) {
+    const int np = nfresh < NPILOT ? nfresh : NPILOT;
+    if (nc * np < M) {   // too few candidates to bound anything
+        if (threadIdx.x == 0) lay.cut[s] = ecut;
+        return;
+    }
+    // sites where two pilots differ (when at most 4)
+    if ((int)threadIdx.x < np * np) {
+        const int p = threadIdx.x / np, q = threadIdx.x % np;
+        const uint64_t* xp = lay.bits + (q0 + pslot[p]) * lay.Wmax;
+        const uint64_t* xq = lay.bits + (q0 + pslot[q]) * lay.Wmax;
+        int n = 0;
+        for (int w = 0; w < W && n <= 4; ++w) {
+            uint64_t d = xp[w] ^ xq[w];
+            while (d && n <= 4) {
+                const int bit = __builtin_ctzll(d);
+                if (n < 4) dsites[p][q][1 + n] = w * 64 + bit;
+                ++n;
+                d &= d - 1;
+            }
+        }
+        dsites[p][q][0] = n;
+    }
+    const double* Jb = J4 + lay.joff[b];
+    const int n2 = pow2_at_least(N);
+    for (int p = 0; p < np; ++p) {
+        const uint64_t* xp = lay.bits + (q0 + pslot[p]) * lay.Wmax;
+        const double* Fp = lay.F + (q0 + pslot[p]) * lay.Npmax;
+        const double Ep = lay.E[q0 + pslot[p]];
+        for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+            key[i] = i < N ? -2.0 * spin_of(xp, i) * Fp[i] : INFINITY;
+            idx[i] = (uint32_t)i;
+        }
+        __syncthreads();
+        bitonic_sort(key, idx, n2, PlainLess());
+        if ((int)threadIdx.x < K) {
             aK[threadIdx.x] = key[threadIdx.x];
             iK[threadIdx.x] = (int)idx[threadIdx.x];
         }
         __syncthreads();
-        const double* Jb = J4 + lay.joff[b];
-        const int n2c = pow2_at_least(nc);
-        for (int t = threadIdx.x; t < n2c; t += blockDim.x) {
-            double v = INFINITY;
+        for (int t = threadIdx.x; t < nc; t += blockDim.x) {
+            double v;
+            uint32_t id;
             if (t < K) {
                 v = aK[t];
-            } else if (t < nc) {
-                // t - K enumerates pairs (p, r), p < r < K
-                int u = t - K, p = 0;
-                while (u >= K - 1 - p) { u -= K - 1 - p; ++p; }
-                const int r = p + 1 + u;
-                const int i = iK[p], j = iK[r];
+                id = (1u << 25) | ((uint32_t)iK[t] << 12);
+            } else {
+                int u = t - K, a = 0;   // pairs (a, c), a < c < K
+                while (u >= K - 1 - a) { u -= K - 1 - a; ++a; }
+                const int c = a + 1 + u;
+                int i = iK[a], j = iK[c];
+                if (i > j) { const int x = i; i = j; j = x; }
                 const double sij = spin_of(xp, i) * spin_of(xp, j);
-                v = aK[p] + aK[r] + sij * Jb[(size_t)i * Np + j];
+                v = aK[a] + aK[c] + sij * Jb[(size_t)i * Np + j];
+                id = ((uint32_t)i << 12) | (uint32_t)j;
             }
-            key[t] = v;
-            idx[t] = (uint32_t)t;
+            pE[p * nc + t] = Ep + v;
+            pid[p * nc + t] = ((uint32_t)p << 26) | id;
         }
         __syncthreads();
-        bitonic_sort(key, idx, n2c, PlainLess());
-        theta = key[M - 1];
     }
-    if (threadIdx.x == 0) {
-        const double c = Ep + theta;
-        lay.cut[s] = c < ecut ? c : ecut;
+    // pool: sort by energy, drop duplicates, take the M-th distinct
+    const int npool = np * nc;
+    const int n2p = pow2_at_least(npool);
+    for (int t = threadIdx.x; t < n2p; t += blockDim.x) {
+        key[t] = t < npool ? pE[t] : INFINITY;
+        idx[t] = t < npool ? pid[t] : 0xFFFFFFFFu;
     }
+    __syncthreads();
+    bitonic_sort(key, idx, n2p, PlainLess());
+    double theta = INFINITY;
+    int seen = 0;
+    for (int c0 = 0; c0 < npool && seen < M; c0 += 256) {
+        const int t = c0 + threadIdx.x;
+        int isnew = 0;
+        if (t < npool) {
+            isnew = 1;
+            const uint32_t id = idx[t];
+            int fa[2], na;
+            cand_sites(id, fa, na);
+            const int pa = (int)(id >> 26);
+            for (int u = t - 1; u >= 0 && key[u] == key[t] && isnew; --u) {
+                const uint32_t ib = idx[u];
+                const int pb = (int)(ib >> 26);
+                if (pb == pa) continue;   // children of one parent are distinct
+                const int nd = dsites[pa][pb][0];
+                if (nd > 4) continue;
+                int fb[2], nb2;
+                cand_sites(ib, fb, nb2);
+                // symmetric difference of the two flip sets must equal the differing sites
+                int sd[4], ns = 0;
+                for (int e = 0; e < na; ++e) {
+                    bool in = false;
+                    for (int g = 0; g < nb2; ++g) in |= fa[e] == fb[g];
+                    if (!in) sd[ns++] = fa[e];
+                }
+                for (int g = 0; g < nb2; ++g) {
+                    bool in = false;
+                    for (int e = 0; e < na; ++e) in |= fb[g] == fa[e];
+                    if (!in) sd[ns++] = fb[g];
+                }
+                if (ns != nd) continue;
+                bool same = true;
+                for (int e = 0; e < ns && same; ++e) {
+                    bool in = false;
+                    for (int g = 0; g < nd; ++g) in |= sd[e] == dsites[pa][pb][1 + g];
+                    same = in;
+                }
+                if (same) isnew = 0;
+            }
+        }
+        int excl;
+        const int tot = block_exclusive_scan(isnew, tmp, excl);
+        if (isnew && seen + excl == M - 1) tmp[0] = t;   // read after the barrier below
+        __syncthreads();
+        if (seen < M && seen + tot >= M) theta = key[tmp[0]];
+        __syncthreads();
+        seen += tot;
+    }
+    if (threadIdx.x == 0) lay.cut[s] = theta < ecut ? theta : ecut;
 }
 
 // ------------------------------------------------------------------ k_plan
@@ -285,9 +368,9 @@ __device__ inline int find_instance(const long long* prefix, int B, long long e)
 }
 
 // ------------------------------------------------------------------ k_prep
-// One wave per frontier entry: a_i = -2 s_i F_i, the scan threshold
-// T = cut - E (a pair survives iff a_i + a_j + 4 s_i s_j J_ij <= T), and the
-// single flips below the cut.
+// One wave per frontier entry: a_i = -2 s_i F_i, the per-state record the
+// scan reads (threshold T = cut - E, energy, search, slot), a copy of the
+// state's words next to it, and the single flips below the cut.
 __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __restrict__ fr_prefix)
 {
     const long long total = fr_prefix[lay.B];
@@ -297,7 +380,8 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
     for (long long e = (long long)blockIdx.x * 4 + wave; e < total; e += (long long)gridDim.x * 4) {
         const int b = find_instance(fr_prefix, lay.B, e);
         const int f = (int)(e - fr_prefix[b]);
-        const int code = lay.fr_list[(size_t)b * lay.fmax + f];
+        const size_t fe = (size_t)b * lay.fmax + f;
+        const int code = lay.fr_list[fe];
         const int s = code / (2 * lay.M);
         if (retry_mode && !lay.retry[s]) continue;
         const size_t q = (size_t)code;   // s*2M + slot
@@ -306,8 +390,16 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
         const double c = lay.cut[s];
         const uint64_t* x = lay.bits + q * lay.Wmax;
         const double* F = lay.F + q * lay.Npmax;
-        double* A = lay.A + ((size_t)b * lay.fmax + f) * lay.Npmax;
-        if (lane == 0) lay.T[(size_t)b * lay.fmax + f] = c - Em;
+        double* A = lay.A + fe * lay.Npmax;
+        if (lane == 0) {
+            FrRec r;
+            r.T = c - Em;
+            r.E = Em;
+            r.s = s;
+            r.code = code;
+            lay.rec[fe] = r;
+        }
+        if ((int)lane < lay.Wmax) lay.fbits[fe * lay.Wmax + lane] = x[lane];
         if (retry_mode && lane == 0) {
             atomicAdd(&lay.ctr[CTR_PAIRS], (unsigned long long)N * (N - 1) / 2);
             atomicAdd(&lay.ctr[CTR_SINGLES], (unsigned long long)N);
@@ -329,7 +421,7 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
                     if (pos < lay.cap_surv) {
                         Surv r;
                         r.E = Ec;
-                        r.f = (uint32_t)f;
+                        r.code = (uint32_t)code;
                         r.pair = (uint32_t)i | (SINGLE << 16);
                         lay.surv[(size_t)s * lay.cap_surv + pos] = r;
                     }
@@ -341,17 +433,18 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
 
 // ------------------------------------------------------------------ k_scan
 // One wave per work item (instance b, chunk of sc frontier states, tile of
-// 64 rows i x 64 columns j with row block <= column block).  Lane = row i;
-// the wave holds the 64 values 4J_ij of its row in registers and walks the
-// chunk's states, so each tile load serves sc states.  For state m the pair
-// (i,j) survives iff a_j + s_i s_j 4J_ij <= T_m - a_i.  The sign s_i s_j is
-// applied in place to the high word of the register copy: the stored sign
-// changes between consecutive states by (bit_i ^ bit_i') ^ (bit_j ^ bit_j'),
-// and adding 2^31 flips bit 31 exactly like xor, so (hi ^ di) + dj is a
-// single v_xad_u32.  Pairs outside the triangle or the instance hold NaN,
-// which never passes the test.  a_j is wave-uniform (scalar loads).
-// Survivors are staged in LDS and appended to the search's record buffer
-// with one atomic per flush.
+// 64 rows i x 32 columns j).  Lane = row i; the wave keeps the 32 values
+// 4J_ij of its row in registers and walks the chunk's states, so one tile
+// load serves sc states.  For state m the pair (i,j) survives iff
+//   a_j + s_i s_j 4J_ij <= T_m - a_i.
+// The sign s_i s_j is applied in place to the high word of the register copy:
+// between consecutive states it changes by (bit_i ^ bit_i') ^ (bit_j ^ bit_j'),
+// and adding 2^31 flips bit 31 exactly like xor, so (hi ^ di) + dj is a single
+// v_xad_u32; then one v_add_f64 with the wave-uniform a_j (scalar registers)
+// and one v_cmp_le_f64.  Pairs outside the triangle or the instance hold NaN,
+// which never passes.  The next state's record, words and a_i are loaded
+// while the current state is scanned.  Survivors are staged in LDS and
+// appended to the search's buffer with one atomic per flush.
 __device__ inline void flush_stage(const Layout& lay, Surv* stage, int& n, int s)
 {
     if (n == 0) return;
@@ -369,188 +462,280 @@ __device__ inline void flush_stage(const Layout& lay, Surv* stage, int& n, int s
 
 __global__ __launch_bounds__(64) void k_scan(Layout lay, const double* __restrict__ J4,
                                              const double* __restrict__ Abuf,
-                                             const double* __restrict__ Tbuf,
-                                             const int* __restrict__ frl)
+                                             const FrRec* __restrict__ recs,
+                                             const uint64_t* __restrict__ fbits)
 {
     __shared__ Surv stage[STAGE];
+    __shared__ double abuf[2][TCOL];   // a_j of the current and the next state
+    __shared__ uint32_t djb[TCOL];     // per column: 2^31 if the sign of s_j changed
     const uint32_t lane = lane_id();
     const long long total = lay.item_prefix[lay.B];
     const int retry_mode = lay.flags[FLAG_RETRY_MODE];
-    const int M2 = 2 * lay.M;
+    const int Wm = lay.Wmax;
     for (long long item = blockIdx.x; item < total; item += gridDim.x) {
         const int b = uniform_int(find_instance(lay.item_prefix, lay.B, item));
         const long long r = item - lay.item_prefix[b];
         const int N = lay.N[b], Np = lay.Npad[b];
-        const int nb = Np / TILE;
+        const int nc = 2 * (Np / TILE);
         const long long T = tiles_of(N);
         const int c = (int)(r / T);
         int t = (int)(r % T);
         int bi = 0;
-        while (t >= nb - bi) { t -= nb - bi; ++bi; }
-        const int bj = bi + t;
+        while (t >= nc - 2 * bi) { t -= nc - 2 * bi; ++bi; }
         bi = uniform_int(bi);
-        const int bjj = uniform_int(bj);
+        const int bc = uniform_int(2 * bi + t);
         const int P = lay.fr_count[b];
         const int f0 = c * lay.sc;
         const int f1 = min(f0 + lay.sc, P);
 
-        // the tile: row i = bi*64 + lane, columns j = bjj*64 + 0..63
+        // the tile: row i = bi*64 + lane, columns j = bc*32 + 0..31
         const int row = bi * TILE + (int)lane;
+        const int col0 = bc * TCOL;
         const double* Jt = J4 + lay.joff[b];
-        uint64_t Jb[TILE];
+        uint64_t Jb[TCOL];
 #pragma unroll
-        for (int j = 0; j < TILE; ++j) {
-            const int col = bjj * TILE + j;
-            double v = Jt[(size_t)col * Np + row];   // symmetric: (col,row) = (row,col)
-            const bool ok = row < N && col < N && (bi != bjj || j > (int)lane);
+        for (int j = 0; j < TCOL; ++j) {
+            const int col = col0 + j;
+            const double v = Jt[(size_t)col * Np + row];   // symmetric: (col,row) = (row,col)
+            const bool ok = row < N && col < N && col > row;
             Jb[j] = ok ? (uint64_t)__double_as_longlong(v) : 0x7ff8000000000000ull;
         }
-        uint32_t prev_i = 0;
-        uint64_t prev_wj = 0;
+        const int wrow = bi, wcol = bc >> 1, shcol = 32 * (bc & 1);
+        uint32_t prev_i = 0, prev_wj = 0;
         int nstage = 0, sstage = -1;
+        int cur = 0;
+        // the first state's data; later states are fetched one state ahead
+        size_t fe = (size_t)b * lay.fmax + f0;
+        FrRec nrec = recs[fe];
+        uint64_t nwi = fbits[fe * Wm + wrow];
+        uint64_t nwj = fbits[fe * Wm + wcol];
+        double nai = Abuf[fe * lay.Npmax + row];
+        double naj = lane < TCOL ? Abuf[fe * lay.Npmax + col0 + lane] : 0.0;
+        if (lane < TCOL) abuf[0][lane] = naj;
         for (int f = f0; f < f1; ++f) {
-            const int code = uniform_int(frl[(size_t)b * lay.fmax + f]);
-            const int s = code / M2;
-            if (retry_mode && !lay.retry[s]) continue;
-            if (s != sstage) {
-                flush_stage(lay, stage, nstage, sstage);
-                sstage = s;
+            const FrRec rc = nrec;
+            const uint64_t wi = nwi, wjw = nwj;
+            const double ai = nai;
+            if (f + 1 < f1) {
+                const size_t fn = (size_t)b * lay.fmax + f + 1;
+                nrec = recs[fn];
+                nwi = fbits[fn * Wm + wrow];
+                nwj = fbits[fn * Wm + wcol];
+                nai = Abuf[fn * lay.Npmax + row];
+                if (lane < TCOL) naj = Abuf[fn * lay.Npmax + col0 + lane];
             }
-            const uint64_t* xb = lay.bits + (size_t)code * lay.Wmax;
-            const uint64_t wi = xb[bi];
-            const uint64_t wj = xb[bjj];
-            const size_t arow = ((size_t)b * lay.fmax + f) * lay.Npmax;
-            const double tm = Tbuf[(size_t)b * lay.fmax + f];
-            const double ai = Abuf[arow + row];
-            const double Ea = lay.E[code] + ai;
-            const double rr = row < N ? tm - ai : -INFINITY;
-            const uint32_t cur_i = (uint32_t)(wi >> lane) & 1u;
-            const uint32_t di = (cur_i ^ prev_i) << 31;
-            prev_i = cur_i;
-            const uint64_t dw = wj ^ prev_wj;
-            prev_wj = wj;
-            const double* aj = Abuf + arow + (size_t)bjj * TILE;
-#pragma unroll
-            for (int g = 0; g < TILE; g += 8) {
-                uint64_t m[8];
-                double x[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int j = g + u;
-                    const uint32_t dj = (uint32_t)((dw >> j) & 1ull) << 31;
-                    const uint32_t hi = (((uint32_t)(Jb[j] >> 32)) ^ di) + dj;
-                    Jb[j] = (Jb[j] & 0xffffffffull) | ((uint64_t)hi << 32);
-                    x[u] = aj[j] + __longlong_as_double((long long)Jb[j]);
-                    m[u] = __builtin_amdgcn_ballot_w64(x[u] <= rr);
+            __syncthreads();   // abuf[cur] is complete
+            const int s = uniform_int(rc.s);
+            const bool skip = retry_mode && !lay.retry[s];
+            if (!skip) {
+                if (s != sstage) {
+                    flush_stage(lay, stage, nstage, sstage);
+                    sstage = s;
                 }
-                const uint64_t any = m[0] | m[1] | m[2] | m[3] | m[4] | m[5] | m[6] | m[7];
-                if (any) {
+                const double Ea = rc.E + ai;
+                const double rr = row < N ? rc.T - ai : -INFINITY;
+                const uint32_t cur_i = (uint32_t)(wi >> lane) & 1u;
+                const uint32_t di = (cur_i ^ prev_i) << 31;
+                prev_i = cur_i;
+                const uint32_t wj = (uint32_t)(wjw >> shcol);
+                const uint32_t dw = wj ^ prev_wj;
+                prev_wj = wj;
+                if (lane < TCOL) djb[lane] = ((dw >> lane) & 1u) << 31;
+                __syncthreads();
+                const double* aj = abuf[cur];
+#pragma unroll
+                for (int g = 0; g < TCOL; g += 8) {
+                    double a8[8];
+                    uint32_t d8[8];
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
-                        if (m[u]) {
-                            if (nstage > STAGE - 64) flush_stage(lay, stage, nstage, s);
-                            if ((m[u] >> lane) & 1ull) {
-                                Surv rec;
-                                rec.E = Ea + x[u];
-                                rec.f = (uint32_t)f;
-                                rec.pair = (uint32_t)row | ((uint32_t)(bjj * TILE + g + u) << 16);
-                                stage[nstage + (int)mbcnt64(m[u])] = rec;
+                        a8[u] = aj[g + u];
+                        d8[u] = djb[g + u];
+                    }
+                    uint64_t any = 0;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int j = g + u;
+                        const uint32_t hi = (((uint32_t)(Jb[j] >> 32)) ^ di) + d8[u];
+                        Jb[j] = (Jb[j] & 0xffffffffull) | ((uint64_t)hi << 32);
+                        const double x = a8[u] + __longlong_as_double((long long)Jb[j]);
+                        any |= __builtin_amdgcn_ballot_w64(x <= rr);
+                    }
+                    if (any) {
+                        // rare: recompute the group and record every survivor
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const double x = a8[u] + __longlong_as_double((long long)Jb[g + u]);
+                            const uint64_t m = __builtin_amdgcn_ballot_w64(x <= rr);
+                            if (m) {
+                                if (nstage > STAGE - 64) flush_stage(lay, stage, nstage, s);
+                                if ((m >> lane) & 1ull) {
+                                    // opaque to the optimiser, so the 32 record codes are formed
+                                    // here instead of being held in registers across the loop
+                                    uint32_t rowv = (uint32_t)row;
+                                    asm volatile("" : "+v"(rowv));
+                                    Surv rec;
+                                    rec.E = Ea + x;
+                                    rec.code = (uint32_t)rc.code;
+                                    rec.pair = rowv | ((uint32_t)(col0 + g + u) << 16);
+                                    stage[nstage + (int)mbcnt64(m)] = rec;
+                                }
+                                nstage += __builtin_popcountll(m);
                             }
-                            nstage += __builtin_popcountll(m[u]);
                         }
                     }
                 }
             }
+            if (f + 1 < f1 && lane < TCOL) abuf[cur ^ 1][lane] = naj;
+            cur ^= 1;
         }
         flush_stage(lay, stage, nstage, sstage);
+        __syncthreads();
     }
 }
 
 // ------------------------------------------------------------------ merge helpers
-// Candidate sources give the energy and the packed words of a candidate.
-struct SearchSrc {
-    const Layout* lay;
-    int s, b;
-    __device__ uint64_t word(uint32_t ref, int w) const
+// A candidate decoded once: the words of its parent state and up to two
+// flipped sites (j = SINGLE for a single flip, i = j = SINGLE for a state
+// taken as it is).  Comparisons of words then issue independent loads.
+struct Cand {
+    const uint64_t* base;
+    int i, j;
+    __device__ uint64_t word(int w) const
     {
-        const size_t q0 = (size_t)s * 2 * lay->M;
-        if (ref & REF_SURV) {
-            const Surv r = lay->surv[(size_t)s * lay->cap_surv + (ref & ~REF_SURV)];
-            const int code = lay->fr_list[(size_t)b * lay->fmax + r.f];
-            uint64_t v = lay->bits[(size_t)code * lay->Wmax + w];
-            const int i = (int)(r.pair & 0xFFFFu), j = (int)(r.pair >> 16);
-            if ((i >> 6) == w) v ^= 1ull << (i & 63);
-            if (j != (int)SINGLE && (j >> 6) == w) v ^= 1ull << (j & 63);
-            return v;
-        }
-        const int slot = lay->kept[(size_t)s * lay->M + ref];
-        return lay->bits[(q0 + slot) * lay->Wmax + w];
+        uint64_t v = base[w];
+        if (i != (int)SINGLE && (i >> 6) == w) v ^= 1ull << (i & 63);
+        if (j != (int)SINGLE && (j >> 6) == w) v ^= 1ull << (j & 63);
+        return v;
     }
 };
 
+// Candidates of one search: kept states (ref < REF_SURV, index into the kept
+// list) and survivor records (ref = REF_SURV | record index).
+struct SearchSrc {
+    const Layout* lay;
+    int s, b;
+    __device__ Cand decode(uint32_t ref) const
+    {
+        if (ref & REF_SURV) {
+            const Surv r = lay->surv[(size_t)s * lay->cap_surv + (ref & ~REF_SURV)];
+            return Cand{lay->bits + (size_t)r.code * lay->Wmax, (int)(r.pair & 0xFFFFu), (int)(r.pair >> 16)};
+        }
+        const int slot = lay->kept[(size_t)s * lay->M + ref];
+        return Cand{lay->bits + ((size_t)s * 2 * lay->M + slot) * lay->Wmax, (int)SINGLE, (int)SINGLE};
+    }
+};
+
+// Candidates of one instance: ref = l * M + k, the k-th kept state of search l.
 struct InstanceSrc {
     const Layout* lay;
     int b;
-    __device__ uint64_t word(uint32_t ref, int w) const
+    __device__ Cand decode(uint32_t ref) const
     {
         const int l = (int)(ref / (uint32_t)lay->M), k = (int)(ref % (uint32_t)lay->M);
         const int s = b * lay->L + l;
         const int slot = lay->kept[(size_t)s * lay->M + k];
-        return lay->bits[((size_t)s * 2 * lay->M + slot) * lay->Wmax + w];
+        return Cand{lay->bits + ((size_t)s * 2 * lay->M + slot) * lay->Wmax, (int)SINGLE, (int)SINGLE};
     }
 };
 
 constexpr uint32_t REF_PAD = 0xFFFFFFFFu;
 
-// (E, psi, ref): psi compared as an unsigned integer from the highest word.
+// Total order (E, psi, ref).  Two candidates with equal energy and equal
+// Zobrist hash are taken to be the same state and ordered by ref (a kept
+// state has a smaller ref than any survivor, so it comes first); the dedupe
+// pass confirms this on the full words and, on a hash collision, the list is
+// sorted again with strict = true, which always compares psi.
 template <class Src>
 struct StateLess {
     const Src* src;
     int W;
-    __device__ bool operator()(double a, uint32_t ia, double b, uint32_t ib) const
+    bool strict;
+    __device__ bool operator()(double a, uint32_t ia, uint64_t za, double b, uint32_t ib, uint64_t zb) const
     {
         if (a < b) return true;
         if (a > b) return false;
         if (ia == REF_PAD || ib == REF_PAD) return ia < ib;
+        if (!strict && za == zb) return ia < ib;
+        const Cand A = src->decode(ia), B = src->decode(ib);
         for (int w = W - 1; w >= 0; --w) {
-            const uint64_t x = src->word(ia, w), y = src->word(ib, w);
+            const uint64_t x = A.word(w), y = B.word(w);
             if (x != y) return x < y;
         }
         return ia < ib;
     }
 };
 
-template <class Src>
-__device__ bool same_state(const Src& src, int W, double a, uint32_t ia, double b, uint32_t ib)
+template <class Less>
+__device__ void bitonic_sort3(double* key, uint32_t* idx, uint64_t* zk, int n2, const Less& less)
 {
-    if (a != b || ia == REF_PAD || ib == REF_PAD) return false;
-    for (int w = W - 1; w >= 0; --w)
-        if (src.word(ia, w) != src.word(ib, w)) return false;
-    return true;
+    for (int k = 2; k <= n2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < (n2 >> 1); t += blockDim.x) {
+                const int i = 2 * j * (t / j) + (t % j);
+                const int l = i + j;
+                const bool up = (i & k) == 0;
+                const bool swap = up ? less(key[l], idx[l], zk[l], key[i], idx[i], zk[i])
+                                     : less(key[i], idx[i], zk[i], key[l], idx[l], zk[l]);
+                if (swap) {
+                    const double tk = key[i]; key[i] = key[l]; key[l] = tk;
+                    const uint32_t ti = idx[i]; idx[i] = idx[l]; idx[l] = ti;
+                    const uint64_t tz = zk[i]; zk[i] = zk[l]; zk[l] = tz;
+                }
+            }
+            __syncthreads();
+        }
+    }
 }
 
-// Sorts key/ref[0..n), drops duplicates (the first of equal states is kept;
-// the order puts a kept state before its copies), keeps the first M distinct
-// at the front.  Returns their count.
 template <class Src>
-__device__ int sort_dedupe_keep(const Src& src, int W, double* key, uint32_t* ref, int n, int M,
+__device__ bool same_words(const Src& src, int W, uint32_t ia, uint32_t ib)
+{
+    const Cand A = src.decode(ia), B = src.decode(ib);
+    if (A.base == B.base && A.i == B.i && A.j == B.j) return true;
+    uint64_t diff = 0;
+    for (int w = 0; w < W; ++w) diff |= A.word(w) ^ B.word(w);
+    return diff == 0;
+}
+
+// Sorts key/ref/zob[0..n), drops duplicates (the first of equal states is
+// kept; a kept state sorts before its copies) and moves the first M distinct
+// to the front.  Returns their count.
+template <class Src>
+__device__ int sort_dedupe_keep(const Src& src, int W, double* key, uint32_t* ref, uint64_t* zk, int n, int M,
                                 int* tmp, uint8_t* keep)
 {
+    __shared__ int s_collide;
     const int n2 = pow2_at_least(n < 2 ? 2 : n);
     for (int t = n + threadIdx.x; t < n2; t += blockDim.x) {
         key[t] = INFINITY;
         ref[t] = REF_PAD;
+        zk[t] = 0;
+    }
+    if (threadIdx.x == 0) s_collide = 0;
+    __syncthreads();
+    bitonic_sort3(key, ref, zk, n2, StateLess<Src>{&src, W, false});
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        int kf = 1;
+        if (t > 0 && key[t - 1] == key[t] && zk[t - 1] == zk[t]) {
+            if (same_words(src, W, ref[t - 1], ref[t])) kf = 0;
+            else s_collide = 1;
+        }
+        keep[t] = (uint8_t)kf;
     }
     __syncthreads();
-    StateLess<Src> less{&src, W};
-    bitonic_sort(key, ref, n2, less);
-    for (int t = threadIdx.x; t < n; t += blockDim.x)
-        keep[t] = (t == 0 || !same_state(src, W, key[t - 1], ref[t - 1], key[t], ref[t])) ? 1 : 0;
-    __syncthreads();
+    if (s_collide) {
+        // a 64-bit hash collision: order by the full words and compare them
+        bitonic_sort3(key, ref, zk, n2, StateLess<Src>{&src, W, true});
+        for (int t = threadIdx.x; t < n; t += blockDim.x)
+            keep[t] = (t == 0 || key[t - 1] != key[t] || !same_words(src, W, ref[t - 1], ref[t])) ? 1 : 0;
+        __syncthreads();
+    }
     // compact the first M distinct, in order, in chunks of 256
     int out = 0;
     __shared__ double ck[256];
     __shared__ uint32_t cr[256];
+    __shared__ uint64_t cz[256];
     for (int c0 = 0; c0 < n && out < M; c0 += 256) {
         const int t = c0 + threadIdx.x;
         const int kf = t < n ? keep[t] : 0;
@@ -558,17 +743,20 @@ __device__ int sort_dedupe_keep(const Src& src, int W, double* key, uint32_t* re
         const int tot = block_exclusive_scan(kf, tmp, excl);
         double kv = 0.0;
         uint32_t rv = 0;
-        if (kf) { kv = key[t]; rv = ref[t]; }
+        uint64_t zv = 0;
+        if (kf) { kv = key[t]; rv = ref[t]; zv = zk[t]; }
         __syncthreads();
         if (kf && out + excl < M) {
             ck[excl] = kv;
             cr[excl] = rv;
+            cz[excl] = zv;
         }
         __syncthreads();
         const int take = min(tot, M - out);
         if ((int)threadIdx.x < take) {
             key[out + threadIdx.x] = ck[threadIdx.x];
             ref[out + threadIdx.x] = cr[threadIdx.x];
+            zk[out + threadIdx.x] = cz[threadIdx.x];
         }
         __syncthreads();
         out += take;
@@ -588,10 +776,13 @@ __global__ __launch_bounds__(256) void k_merge(Layout lay, const double* __restr
 {
     __shared__ double key[MERGE_CH];
     __shared__ uint32_t ref[MERGE_CH];
+    __shared__ uint64_t zk[MERGE_CH];
     __shared__ uint8_t keep[MERGE_CH];
     __shared__ int tmp[256];
     __shared__ int freeslot[2048];
     __shared__ int kslot[1024];
+    __shared__ int ncode[1024];
+    __shared__ uint32_t npair[1024];
     __shared__ uint8_t used[2048];
     const int s = blockIdx.x;
     const int b = s / lay.L;
@@ -604,11 +795,14 @@ __global__ __launch_bounds__(256) void k_merge(Layout lay, const double* __restr
     const int cnt = ctot < lay.cap_surv ? ctot : lay.cap_surv;
     const size_t q0 = (size_t)s * 2 * M;
     const int W = words_of(lay.N[b]);
+    const Surv* sv = lay.surv + (size_t)s * lay.cap_surv;
     SearchSrc src{&lay, s, b};
 
     for (int k = threadIdx.x; k < nk; k += blockDim.x) {
-        key[k] = lay.E[q0 + lay.kept[(size_t)s * M + k]];
+        const int slot = lay.kept[(size_t)s * M + k];
+        key[k] = lay.E[q0 + slot];
         ref[k] = (uint32_t)k;
+        zk[k] = lay.zob[q0 + slot];
     }
     __syncthreads();
     int nrun = nk;
@@ -617,11 +811,16 @@ __global__ __launch_bounds__(256) void k_merge(Layout lay, const double* __restr
         const int room = MERGE_CH - nrun;
         const int take = min(cnt - pos, room);
         for (int t = threadIdx.x; t < take; t += blockDim.x) {
-            key[nrun + t] = lay.surv[(size_t)s * lay.cap_surv + pos + t].E;
+            const Surv r = sv[pos + t];
+            const int i = (int)(r.pair & 0xFFFFu), j = (int)(r.pair >> 16);
+            uint64_t z = lay.zob[r.code] ^ lay.zkey[i];
+            if (j != (int)SINGLE) z ^= lay.zkey[j];
+            key[nrun + t] = r.E;
             ref[nrun + t] = REF_SURV | (uint32_t)(pos + t);
+            zk[nrun + t] = z;
         }
         __syncthreads();
-        nrun = sort_dedupe_keep(src, W, key, ref, nrun + take, M, tmp, keep);
+        nrun = sort_dedupe_keep(src, W, key, ref, zk, nrun + take, M, tmp, keep);
         pos += take;
     } while (pos < cnt);
 
@@ -655,7 +854,7 @@ __global__ __launch_bounds__(256) void k_merge(Layout lay, const double* __restr
         nfree += tot;
     }
     __syncthreads();
-    // position of each new state among the new ones
+    // slot of every member; new members are numbered in list order
     int nnew = 0;
     for (int c0 = 0; c0 < nrun; c0 += 256) {
         const int k = c0 + threadIdx.x;
@@ -663,64 +862,53 @@ __global__ __launch_bounds__(256) void k_merge(Layout lay, const double* __restr
         int excl;
         const int tot = block_exclusive_scan(isnew, tmp, excl);
         if (k < nrun) {
-            int slot;
             if (isnew) {
-                slot = freeslot[nnew + excl];
+                const int m = nnew + excl;
+                const Surv r = sv[ref[k] & ~REF_SURV];
+                const int slot = freeslot[m];
+                kslot[k] = slot;
                 keep[k] = 1;
+                ncode[m] = (int)r.code;
+                npair[m] = r.pair;
+                lay.E[q0 + slot] = r.E;
+                lay.zob[q0 + slot] = zk[k];
+                lay.fresh[q0 + slot] = 1;
+                // stash the member's slot where the field update finds it
+                used[m] = 0;
             } else {
-                slot = lay.kept[(size_t)s * M + ref[k]];
+                kslot[k] = lay.kept[(size_t)s * M + ref[k]];
                 keep[k] = 0;
             }
-            kslot[k] = slot;
         }
         nnew += tot;
     }
     __syncthreads();
-    // old members that stay are no longer new
+    // old members that stay are no longer new; new member m lives in freeslot[m]
     for (int k = threadIdx.x; k < nrun; k += blockDim.x)
         if (!keep[k]) lay.fresh[q0 + kslot[k]] = 0;
-    // new members: bits, energy, hash, flag
-    const int N = lay.N[b], Np = lay.Npad[b];
-    for (int k = threadIdx.x; k < nrun; k += blockDim.x) {
-        if (!keep[k]) continue;
-        const Surv r = lay.surv[(size_t)s * lay.cap_surv + (ref[k] & ~REF_SURV)];
-        const int code = lay.fr_list[(size_t)b * lay.fmax + r.f];
-        const int slot = kslot[k];
-        const int i = (int)(r.pair & 0xFFFFu), j = (int)(r.pair >> 16);
-        const uint64_t* xp = lay.bits + (size_t)code * lay.Wmax;
-        uint64_t* xn = lay.bits + (q0 + slot) * lay.Wmax;
-        for (int w = 0; w < lay.Wmax; ++w) {
-            uint64_t v = xp[w];
-            if ((i >> 6) == w) v ^= 1ull << (i & 63);
-            if (j != (int)SINGLE && (j >> 6) == w) v ^= 1ull << (j & 63);
-            xn[w] = v;
-        }
-        uint64_t z = lay.zob[code] ^ lay.zkey[i];
-        if (j != (int)SINGLE) z ^= lay.zkey[j];
-        lay.zob[q0 + slot] = z;
-        lay.E[q0 + slot] = r.E;
-        lay.fresh[q0 + slot] = 1;
+    // bits of new members
+    for (int t = threadIdx.x; t < nnew * lay.Wmax; t += blockDim.x) {
+        const int m = t / lay.Wmax, w = t - m * lay.Wmax;
+        const uint32_t pr = npair[m];
+        const int i = (int)(pr & 0xFFFFu), j = (int)(pr >> 16);
+        uint64_t v = lay.bits[(size_t)ncode[m] * lay.Wmax + w];
+        if ((i >> 6) == w) v ^= 1ull << (i & 63);
+        if (j != (int)SINGLE && (j >> 6) == w) v ^= 1ull << (j & 63);
+        lay.bits[(q0 + freeslot[m]) * lay.Wmax + w] = v;
     }
-    // local fields of new members: one member at a time, threads over sites
+    // local fields of new members, all members and sites in parallel
+    const int N = lay.N[b], Np = lay.Npad[b];
     const double* Jb = J4 + lay.joff[b];
-    for (int k = 0; k < nrun; ++k) {
-        if (!keep[k]) continue;
-        const Surv r = lay.surv[(size_t)s * lay.cap_surv + (ref[k] & ~REF_SURV)];
-        const int code = lay.fr_list[(size_t)b * lay.fmax + r.f];
-        const int slot = kslot[k];
-        const int i = (int)(r.pair & 0xFFFFu), j = (int)(r.pair >> 16);
+    for (int t = threadIdx.x; t < nnew * Np; t += blockDim.x) {
+        const int m = t / Np, kk = t - m * Np;
+        const uint32_t pr = npair[m];
+        const int i = (int)(pr & 0xFFFFu), j = (int)(pr >> 16);
+        const int code = ncode[m];
         const uint64_t* xp = lay.bits + (size_t)code * lay.Wmax;
-        const double ci = -0.5 * spin_of(xp, i);                       // -2 s_i J = -0.5 s_i (4J)
-        const double cj = j != (int)SINGLE ? -0.5 * spin_of(xp, j) : 0.0;
         const double* Fp = lay.F + (size_t)code * lay.Npmax;
-        double* Fn = lay.F + (q0 + slot) * lay.Npmax;
-        const double* Ji = Jb + (size_t)i * Np;
-        const double* Jj = Jb + (size_t)(j != (int)SINGLE ? j : i) * Np;
-        for (int kk = threadIdx.x; kk < Np; kk += blockDim.x) {
-            double v = Fp[kk] + ci * Ji[kk];
-            if (j != (int)SINGLE) v += cj * Jj[kk];
-            Fn[kk] = kk < N ? v : 0.0;
-        }
+        double v = Fp[kk] - 0.5 * spin_of(xp, i) * Jb[(size_t)i * Np + kk];   // -2 s_i J = -0.5 s_i (4J)
+        if (j != (int)SINGLE) v -= 0.5 * spin_of(xp, j) * Jb[(size_t)j * Np + kk];
+        lay.F[(q0 + freeslot[m]) * lay.Npmax + kk] = kk < N ? v : 0.0;
     }
     for (int k = threadIdx.x; k < nrun; k += blockDim.x)
         lay.kept[(size_t)s * M + k] = kslot[k];
@@ -739,6 +927,7 @@ __global__ __launch_bounds__(256) void k_final(Layout lay)
 {
     __shared__ double key[MERGE_CH];
     __shared__ uint32_t ref[MERGE_CH];
+    __shared__ uint64_t zk[MERGE_CH];
     __shared__ uint8_t keep[MERGE_CH];
     __shared__ int tmp[256];
     const int b = blockIdx.x;
@@ -758,17 +947,18 @@ __global__ __launch_bounds__(256) void k_final(Layout lay)
                 const int slot = lay.kept[(size_t)s * M + k];
                 key[n + k] = lay.E[(size_t)s * 2 * M + slot];
                 ref[n + k] = (uint32_t)(l * M + k);
+                zk[n + k] = lay.zob[(size_t)s * 2 * M + slot];
             }
             n += nk;
             ++l;
         }
         __syncthreads();
-        nrun = sort_dedupe_keep(src, W, key, ref, n, M, tmp, keep);
+        nrun = sort_dedupe_keep(src, W, key, ref, zk, n, M, tmp, keep);
     }
     for (int k = threadIdx.x; k < nrun; k += blockDim.x) {
         lay.out_E[(size_t)b * M + k] = key[k];
         for (int w = 0; w < lay.Wmax; ++w)
-            lay.out_bits[((size_t)b * M + k) * lay.Wmax + w] = w < W ? src.word(ref[k], w) : 0ull;
+            lay.out_bits[((size_t)b * M + k) * lay.Wmax + w] = w < W ? src.decode(ref[k]).word(w) : 0ull;
     }
     if (threadIdx.x == 0) lay.out_count[b] = nrun;
 }
@@ -781,16 +971,30 @@ hipError_t launch_step_begin(const Layout& lay, bool retry_mode, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_step(const Layout& lay, int scan_grid, bool retry_mode, hipStream_t st)
+hipError_t launch_frontier_plan(const Layout& lay, hipStream_t st)
 {
     long long* fr_prefix = lay.item_prefix + (lay.B + 1);
-    if (!retry_mode) {
-        hipLaunchKernelGGL(k_frontier, dim3(lay.S), dim3(256), 0, st, lay, lay.J4);
-        hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, lay, fr_prefix);
-    }
-    hipLaunchKernelGGL(k_prep, dim3(4096), dim3(256), 0, st, lay, (const long long*)fr_prefix);
+    hipLaunchKernelGGL(k_frontier, dim3(lay.S), dim3(256), 0, st, lay, lay.J4);
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, lay, fr_prefix);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep(const Layout& lay, hipStream_t st)
+{
+    const long long* fr_prefix = lay.item_prefix + (lay.B + 1);
+    hipLaunchKernelGGL(k_prep, dim3(4096), dim3(256), 0, st, lay, fr_prefix);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const Layout& lay, int scan_grid, hipStream_t st)
+{
     hipLaunchKernelGGL(k_scan, dim3(scan_grid), dim3(64), 0, st, lay, lay.J4, (const double*)lay.A,
-                       (const double*)lay.T, (const int*)lay.fr_list);
+                       (const FrRec*)lay.rec, (const uint64_t*)lay.fbits);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge(const Layout& lay, hipStream_t st)
+{
     hipLaunchKernelGGL(k_merge, dim3(lay.S), dim3(256), 0, st, lay, lay.J4);
     return hipGetLastError();
 }

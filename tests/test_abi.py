@@ -63,7 +63,7 @@ def test_init_rejects_invalid_arguments(case):
     elif case == "form":
         cfg.form = 7
     elif case == "reserved":
-        cfg.reserved[0] = 1
+        cfg.reserved = 1
     elif case == "L0":
         L = 0
     elif case == "N0":

@@ -180,3 +180,21 @@ def test_c2_full_size_sampled():
         for k in rng.choice(len(gE), 5, replace=False):
             assert oracle.energy(inst.J, inst.h, gb[k]) == gE[k]
     s.destroy()
+
+
+def test_reset_repeats_the_search_exactly():
+    w = wl.custom([100, 140], L=3, M=40, config=17)
+    note("[reset]")
+    s = binding.IsingSearch.from_workload(w)
+    it1, st1 = s.run()
+    first = [s.get_search(k) for k in range(s.B * s.L)]
+    fm = [s.get_states(b) for b in range(s.B)]
+    s.reset()
+    it2, st2 = s.run()
+    assert (it1, st1) == (it2, st2)
+    for k in range(s.B * s.L):
+        assert_same_set(s.get_search(k), first[k], f"reset search {k}")
+    for b in range(s.B):
+        gb, gE = s.get_states(b)
+        assert np.array_equal(gb, fm[b][0]) and np.array_equal(gE, fm[b][1])
+    s.destroy()
