@@ -26,7 +26,7 @@ METRIC = "pair-flip ΔE evals/s + time-to-solution/instance at N=600,M=120 vs pl
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz; FP64 add/compare and 32-bit
 # integer VALU ops each issue at this lane rate (78.6 TFLOP/s FP64 counts an FMA as 2).
 VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
-OPS_PER_PAIR = 3          # sign applied to 4J_ij, add a_j, compare with T - a_i
+OPS_PER_PAIR = 2          # fma(s_i, s_j 4J_ij, a_j) and the compare with T - a_i (a running minimum)
 
 
 def log(msg):

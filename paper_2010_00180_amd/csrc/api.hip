@@ -269,6 +269,10 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     ALLOC(lay.item_prefix, 2 * ((size_t)n_inst + 1));
     ALLOC(lay.ctr, 16);
     ALLOC(lay.flags, 8);
+    ALLOC(lay.nm_count, S);
+    ALLOC(lay.nm_code, S * lay.M);
+    ALLOC(lay.nm_pair, S * lay.M);
+    ALLOC(lay.nm_slot, S * lay.M);
     ALLOC(lay.out_bits, (size_t)n_inst * lay.M * lay.Wmax);
     ALLOC(lay.out_E, (size_t)n_inst * lay.M);
     ALLOC(lay.out_count, n_inst);
@@ -379,6 +383,7 @@ static hipError_t launch_pass(ising_search* h, bool retry_mode)
     if (e == hipSuccess) e = launch_scan(lay, h->scan_grid, st);
     rec(3);
     if (e == hipSuccess) e = launch_merge(lay, st);
+    if (e == hipSuccess) e = launch_fupdate(lay, st);
     rec(4);
     if (e == hipSuccess) ++h->scan_launches;
     return e;

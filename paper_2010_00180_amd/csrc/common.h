@@ -21,7 +21,7 @@ constexpr int TILE = 64;            // rows of one J tile (one row per lane)
 constexpr int TCOL = 32;            // columns of one J tile held in registers
 constexpr int MAX_N = 4096;         // pair indices are packed into 16 bits
 constexpr int PILOT_K = 48;         // lightest sites used for the per-search pilot cut
-constexpr int MERGE_CH = 4096;      // candidates sorted per merge pass (LDS)
+constexpr int MERGE_CH = 2048;      // candidates sorted per merge pass (LDS)
 constexpr int STAGE = 256;          // wave-private survivor staging (records)
 constexpr uint32_t SINGLE = 0xFFFFu;   // j field of a single-flip record
 constexpr uint32_t REF_SURV = 0x80000000u;
@@ -79,6 +79,11 @@ struct Layout {
     long long* item_prefix;  // [B+1]
     unsigned long long* ctr; // [16] device counters (see CTR_*)
     int* flags;              // [8] per-step flags (see FLAG_*)
+    // new kept states of the last merge, for the field update
+    int* nm_count;           // [S]
+    int* nm_code;            // [S][M] parent slot code
+    uint32_t* nm_pair;       // [S][M] i | j << 16
+    int* nm_slot;            // [S][M] slot taken by the new state
     // final merge output
     uint64_t* out_bits;      // [B][M][Wmax]
     double* out_E;           // [B][M]
@@ -105,6 +110,7 @@ hipError_t launch_frontier_plan(const Layout& lay, hipStream_t st);
 hipError_t launch_prep(const Layout& lay, hipStream_t st);
 hipError_t launch_scan(const Layout& lay, int scan_grid, hipStream_t st);
 hipError_t launch_merge(const Layout& lay, hipStream_t st);
+hipError_t launch_fupdate(const Layout& lay, hipStream_t st);
 hipError_t launch_step_begin(const Layout& lay, bool retry_mode, hipStream_t st);
 hipError_t launch_final(const Layout& lay, hipStream_t st);
 

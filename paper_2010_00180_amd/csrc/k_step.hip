@@ -433,17 +433,20 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
 
 // ------------------------------------------------------------------ k_scan
 // One wave per work item (instance b, chunk of sc frontier states, tile of
-// 64 rows i x 32 columns j).  Lane = row i; the wave keeps the 32 values
-// 4J_ij of its row in registers and walks the chunk's states, so one tile
-// load serves sc states.  For state m the pair (i,j) survives iff
-//   a_j + s_i s_j 4J_ij <= T_m - a_i.
-// The sign s_i s_j is applied in place to the high word of the register copy:
-// between consecutive states it changes by (bit_i ^ bit_i') ^ (bit_j ^ bit_j'),
-// and adding 2^31 flips bit 31 exactly like xor, so (hi ^ di) + dj is a single
-// v_xad_u32; then one v_add_f64 with the wave-uniform a_j (scalar registers)
-// and one v_cmp_le_f64.  Pairs outside the triangle or the instance hold NaN,
-// which never passes.  The next state's record, words and a_i are loaded
-// while the current state is scanned.  Survivors are staged in LDS and
+// 64 rows i x 32 columns j).  Lane = row i; the wave keeps y_j = s_j 4J_ij for
+// its row and the tile's 32 columns in registers and walks the chunk's states,
+// so one tile load serves sc states.  For state m the pair (i,j) survives iff
+//   x = fma(s_i, y_j, a_j) = a_j + s_i s_j 4J_ij <= T_m - a_i
+// (exact: the product by +-1 is exact and the fma rounds once, like an add).
+// Only column signs live in the registers; they change between consecutive
+// states of a chunk only at the few sites where the states differ, so a group
+// of 8 columns is re-signed only when one of its columns changed.  The hot
+// loop is one v_fma_f64 and one v_min_f64 per pair and one compare per group;
+// a group whose minimum passes runs the exact pass that records survivors.
+// Pairs outside the triangle or the instance hold NaN, which fmin ignores and
+// no compare passes.  a_j is wave-uniform and read from a per-wave LDS double
+// buffer filled one state ahead; the next state's record, words and a_i are
+// loaded while the current state is scanned.  Survivors are staged in LDS and
 // appended to the search's buffer with one atomic per flush.
 __device__ inline void flush_stage(const Layout& lay, Surv* stage, int& n, int s)
 {
@@ -467,12 +470,25 @@ __global__ __launch_bounds__(64) void k_scan(Layout lay, const double* __restric
 {
     __shared__ Surv stage[STAGE];
     __shared__ double abuf[2][TCOL];   // a_j of the current and the next state
-    __shared__ uint32_t djb[TCOL];     // per column: 2^31 if the sign of s_j changed
+    // per-state data of up to 64 states of the chunk, staged once per item
+    __shared__ double sT[64], sE[64];
+    __shared__ int sS[64], sCode[64];
+    __shared__ uint32_t sWj[64];
+    __shared__ uint64_t sWi[64];
     const uint32_t lane = lane_id();
     const long long total = lay.item_prefix[lay.B];
     const int retry_mode = lay.flags[FLAG_RETRY_MODE];
     const int Wm = lay.Wmax;
-    for (long long item = blockIdx.x; item < total; item += gridDim.x) {
+    const int Npm = lay.Npmax;
+    // Workgroups are dispatched round-robin over the 8 XCDs, so block k runs on
+    // XCD k % 8.  XCD x takes the x-th contiguous eighth of the item list: the
+    // tiles of one chunk of states (and most chunks of one instance) then share
+    // one XCD's L2 for their a_i values and J tiles.
+    const int nx = gridDim.x >= 8 ? 8 : 1;
+    const int xcd = blockIdx.x % nx;
+    const long long seg0 = total * xcd / nx, seg1 = total * (xcd + 1) / nx;
+    const long long stride = gridDim.x / nx;
+    for (long long item = seg0 + blockIdx.x / nx; item < seg1; item += stride) {
         const int b = uniform_int(find_instance(lay.item_prefix, lay.B, item));
         const long long r = item - lay.item_prefix[b];
         const int N = lay.N[b], Np = lay.Npad[b];
@@ -488,7 +504,7 @@ __global__ __launch_bounds__(64) void k_scan(Layout lay, const double* __restric
         const int f0 = c * lay.sc;
         const int f1 = min(f0 + lay.sc, P);
 
-        // the tile: row i = bi*64 + lane, columns j = bc*32 + 0..31
+        // the tile: row i = bi*64 + lane, columns j = bc*32 + 0..31, unsigned
         const int row = bi * TILE + (int)lane;
         const int col0 = bc * TCOL;
         const double* Jt = J4 + lay.joff[b];
@@ -501,93 +517,101 @@ __global__ __launch_bounds__(64) void k_scan(Layout lay, const double* __restric
             Jb[j] = ok ? (uint64_t)__double_as_longlong(v) : 0x7ff8000000000000ull;
         }
         const int wrow = bi, wcol = bc >> 1, shcol = 32 * (bc & 1);
-        uint32_t prev_i = 0, prev_wj = 0;
+        uint32_t prev_wj = 0;   // column signs currently applied to Jb
         int nstage = 0, sstage = -1;
-        int cur = 0;
-        // the first state's data; later states are fetched one state ahead
-        size_t fe = (size_t)b * lay.fmax + f0;
-        FrRec nrec = recs[fe];
-        uint64_t nwi = fbits[fe * Wm + wrow];
-        uint64_t nwj = fbits[fe * Wm + wcol];
-        double nai = Abuf[fe * lay.Npmax + row];
-        double naj = lane < TCOL ? Abuf[fe * lay.Npmax + col0 + lane] : 0.0;
-        if (lane < TCOL) abuf[0][lane] = naj;
-        for (int f = f0; f < f1; ++f) {
-            const FrRec rc = nrec;
-            const uint64_t wi = nwi, wjw = nwj;
-            const double ai = nai;
-            if (f + 1 < f1) {
-                const size_t fn = (size_t)b * lay.fmax + f + 1;
-                nrec = recs[fn];
-                nwi = fbits[fn * Wm + wrow];
-                nwj = fbits[fn * Wm + wcol];
-                nai = Abuf[fn * lay.Npmax + row];
-                if (lane < TCOL) naj = Abuf[fn * lay.Npmax + col0 + lane];
+        for (int g0 = f0; g0 < f1; g0 += 64) {
+            const int ns = min(64, f1 - g0);
+            const size_t fe0 = (size_t)b * lay.fmax + g0;
+            // stage the records of states g0 .. g0+ns-1
+            if ((int)lane < ns) {
+                const FrRec rc = recs[fe0 + lane];
+                sT[lane] = rc.T;
+                sE[lane] = rc.E;
+                sS[lane] = rc.s;
+                sCode[lane] = rc.code;
+                const uint64_t* fw = fbits + (fe0 + lane) * Wm;
+                sWi[lane] = fw[wrow];
+                sWj[lane] = (uint32_t)(fw[wcol] >> shcol);
             }
-            __syncthreads();   // abuf[cur] is complete
-            const int s = uniform_int(rc.s);
-            const bool skip = retry_mode && !lay.retry[s];
-            if (!skip) {
-                if (s != sstage) {
-                    flush_stage(lay, stage, nstage, sstage);
-                    sstage = s;
+            const double* A0 = Abuf + fe0 * Npm;   // a values of state g0
+            double nai = A0[row];
+            double naj = lane < TCOL ? A0[col0 + lane] : 0.0;
+            int cur = 0;
+            if (lane < TCOL) abuf[0][lane] = naj;
+            __syncthreads();
+            for (int k = 0; k < ns; ++k) {
+                const double ai = nai;
+                if (k + 1 < ns) {
+                    const double* An = A0 + (size_t)(k + 1) * Npm;
+                    nai = An[row];
+                    if (lane < TCOL) naj = An[col0 + lane];
                 }
-                const double Ea = rc.E + ai;
-                const double rr = row < N ? rc.T - ai : -INFINITY;
-                const uint32_t cur_i = (uint32_t)(wi >> lane) & 1u;
-                const uint32_t di = (cur_i ^ prev_i) << 31;
-                prev_i = cur_i;
-                const uint32_t wj = (uint32_t)(wjw >> shcol);
-                const uint32_t dw = wj ^ prev_wj;
-                prev_wj = wj;
-                if (lane < TCOL) djb[lane] = ((dw >> lane) & 1u) << 31;
-                __syncthreads();
-                const double* aj = abuf[cur];
-#pragma unroll
-                for (int g = 0; g < TCOL; g += 8) {
-                    double a8[8];
-                    uint32_t d8[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        a8[u] = aj[g + u];
-                        d8[u] = djb[g + u];
+                const int s = uniform_int(sS[k]);
+                const bool skip = retry_mode && !lay.retry[s];
+                if (!skip) {
+                    if (s != sstage) {
+                        flush_stage(lay, stage, nstage, sstage);
+                        sstage = s;
                     }
-                    uint64_t any = 0;
+                    const double Tm = sT[k];
+                    const double Ea = sE[k] + ai;
+                    const double rr = row < N ? Tm - ai : -INFINITY;
+                    const double si = ((sWi[k] >> lane) & 1ull) ? -1.0 : 1.0;
+                    const uint32_t wj = (uint32_t)uniform_int((int)sWj[k]);
+                    const uint32_t dw = wj ^ prev_wj;
+                    prev_wj = wj;
+                    const int code = sCode[k];
+                    const double* aj = abuf[cur];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int j = g + u;
-                        const uint32_t hi = (((uint32_t)(Jb[j] >> 32)) ^ di) + d8[u];
-                        Jb[j] = (Jb[j] & 0xffffffffull) | ((uint64_t)hi << 32);
-                        const double x = a8[u] + __longlong_as_double((long long)Jb[j]);
-                        any |= __builtin_amdgcn_ballot_w64(x <= rr);
-                    }
-                    if (any) {
-                        // rare: recompute the group and record every survivor
+                    for (int g = 0; g < TCOL; g += 8) {
+                        if ((dw >> g) & 0xFFu) {
+                            // a column of this group changed sign since the last state
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                const uint64_t flip = (uint64_t)((dw >> (g + u)) & 1u) << 63;
+                                Jb[g + u] ^= flip;
+                            }
+                        }
+                        double a8[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) a8[u] = aj[g + u];
+                        // running minimum over the group (two chains); NaN pairs drop out of fmin
+                        double mn0 = INFINITY, mn1 = INFINITY;
 #pragma unroll
                         for (int u = 0; u < 8; ++u) {
-                            const double x = a8[u] + __longlong_as_double((long long)Jb[g + u]);
-                            const uint64_t m = __builtin_amdgcn_ballot_w64(x <= rr);
-                            if (m) {
-                                if (nstage > STAGE - 64) flush_stage(lay, stage, nstage, s);
-                                if ((m >> lane) & 1ull) {
-                                    // opaque to the optimiser, so the 32 record codes are formed
-                                    // here instead of being held in registers across the loop
-                                    uint32_t rowv = (uint32_t)row;
-                                    asm volatile("" : "+v"(rowv));
-                                    Surv rec;
-                                    rec.E = Ea + x;
-                                    rec.code = (uint32_t)rc.code;
-                                    rec.pair = rowv | ((uint32_t)(col0 + g + u) << 16);
-                                    stage[nstage + (int)mbcnt64(m)] = rec;
+                            const double x = fma(si, __longlong_as_double((long long)Jb[g + u]), a8[u]);
+                            if (u & 1) mn1 = fmin(mn1, x);
+                            else mn0 = fmin(mn0, x);
+                        }
+                        if (__builtin_amdgcn_ballot_w64(fmin(mn0, mn1) <= rr)) {
+                            // rare: recompute the group and record every survivor
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                const double x = fma(si, __longlong_as_double((long long)Jb[g + u]), a8[u]);
+                                const uint64_t m = __builtin_amdgcn_ballot_w64(x <= rr);
+                                if (m) {
+                                    if (nstage > STAGE - 64) flush_stage(lay, stage, nstage, s);
+                                    if ((m >> lane) & 1ull) {
+                                        // opaque to the optimiser, so the 32 record codes are formed
+                                        // here instead of being held in registers across the loop
+                                        uint32_t rowv = (uint32_t)row;
+                                        asm volatile("" : "+v"(rowv));
+                                        Surv rec;
+                                        rec.E = Ea + x;
+                                        rec.code = (uint32_t)code;
+                                        rec.pair = rowv | ((uint32_t)(col0 + g + u) << 16);
+                                        stage[nstage + (int)mbcnt64(m)] = rec;
+                                    }
+                                    nstage += __builtin_popcountll(m);
                                 }
-                                nstage += __builtin_popcountll(m);
                             }
                         }
                     }
                 }
+                if (k + 1 < ns && lane < TCOL) abuf[cur ^ 1][lane] = naj;
+                cur ^= 1;
+                __syncthreads();   // one wave: an LDS wait before abuf[cur] is read
             }
-            if (f + 1 < f1 && lane < TCOL) abuf[cur ^ 1][lane] = naj;
-            cur ^= 1;
         }
         flush_stage(lay, stage, nstage, sstage);
         __syncthreads();
@@ -765,24 +789,46 @@ __device__ int sort_dedupe_keep(const Src& src, int W, double* key, uint32_t* re
 }
 
 // ------------------------------------------------------------------ k_merge
-// One block per active search.  Kept set and survivors are merged in passes of
-// MERGE_CH candidates: each pass sorts the running best list plus the next
-// survivors by (E, psi), drops duplicates and keeps M.  A survivor buffer that
-// overflowed only yields a tighter cut (its M-th distinct energy) for a
-// re-scan.  Otherwise the new kept set is written: new states take slots the
-// old set does not use, with bits = parent xor flips, E from the record and
-// F_k = F_k(parent) - 2 s_i J_ik - 2 s_j J_jk.
-__global__ __launch_bounds__(256) void k_merge(Layout lay, const double* __restrict__ J4)
+// One block per active search: the new kept set is the M lowest distinct
+// states among the kept set and the survivors, in (E, psi) order.
+// Pre-filter: a 1024-bin histogram of the candidate energies picks the lowest
+// bins holding at least 2M + 64 candidates; bins are monotone in E, so this is
+// a prefix of the sorted candidates, and if it holds M distinct states nothing
+// above it can enter.  Otherwise (or when everything fits) all candidates are
+// sorted, in passes of MERGE_CH that carry the running best M.
+// A survivor buffer that overflowed only yields a tighter cut (its M-th
+// distinct energy) for a re-scan.  Otherwise the new set is written: new states
+// take slots the old set does not use (bits = parent xor flips, E from the
+// record, hash updated); their local fields are written by k_fupdate.
+constexpr int NBIN = 1024;
+
+__device__ double block_reduce(double v, double* red, bool take_max)
+{
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const double o = red[threadIdx.x + w];
+            red[threadIdx.x] = take_max ? fmax(red[threadIdx.x], o) : fmin(red[threadIdx.x], o);
+        }
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_merge(Layout lay, const double* __restrict__ J4)
 {
     __shared__ double key[MERGE_CH];
     __shared__ uint32_t ref[MERGE_CH];
     __shared__ uint64_t zk[MERGE_CH];
     __shared__ uint8_t keep[MERGE_CH];
     __shared__ int tmp[256];
+    __shared__ double red[256];
+    __shared__ int hist[NBIN];
     __shared__ int freeslot[2048];
     __shared__ int kslot[1024];
-    __shared__ int ncode[1024];
-    __shared__ uint32_t npair[1024];
     __shared__ uint8_t used[2048];
     const int s = blockIdx.x;
     const int b = s / lay.L;
@@ -796,33 +842,93 @@ __global__ __launch_bounds__(256) void k_merge(Layout lay, const double* __restr
     const size_t q0 = (size_t)s * 2 * M;
     const int W = words_of(lay.N[b]);
     const Surv* sv = lay.surv + (size_t)s * lay.cap_surv;
+    const int* keptl = lay.kept + (size_t)s * M;
     SearchSrc src{&lay, s, b};
-
-    for (int k = threadIdx.x; k < nk; k += blockDim.x) {
-        const int slot = lay.kept[(size_t)s * M + k];
-        key[k] = lay.E[q0 + slot];
-        ref[k] = (uint32_t)k;
-        zk[k] = lay.zob[q0 + slot];
-    }
-    __syncthreads();
-    int nrun = nk;
-    int pos = 0;
-    do {
-        const int room = MERGE_CH - nrun;
-        const int take = min(cnt - pos, room);
-        for (int t = threadIdx.x; t < take; t += blockDim.x) {
-            const Surv r = sv[pos + t];
+    const int n = nk + cnt;
+    auto candE = [&](int c) -> double { return c < nk ? lay.E[q0 + keptl[c]] : sv[c - nk].E; };
+    // candidate c (0..n) into position p of the sort arrays
+    auto load_cand = [&](int c, int p) {
+        if (c < nk) {
+            const int slot = keptl[c];
+            key[p] = lay.E[q0 + slot];
+            ref[p] = (uint32_t)c;
+            zk[p] = lay.zob[q0 + slot];
+        } else {
+            const Surv r = sv[c - nk];
             const int i = (int)(r.pair & 0xFFFFu), j = (int)(r.pair >> 16);
             uint64_t z = lay.zob[r.code] ^ lay.zkey[i];
             if (j != (int)SINGLE) z ^= lay.zkey[j];
-            key[nrun + t] = r.E;
-            ref[nrun + t] = REF_SURV | (uint32_t)(pos + t);
-            zk[nrun + t] = z;
+            key[p] = r.E;
+            ref[p] = REF_SURV | (uint32_t)(c - nk);
+            zk[p] = z;
+        }
+    };
+
+    int nrun = -1;
+    const int target = 2 * M + 64;
+    if (n > target + 256) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int c = threadIdx.x; c < n; c += blockDim.x) {
+            const double e = candE(c);
+            lo = fmin(lo, e);
+            hi = fmax(hi, e);
+        }
+        lo = block_reduce(lo, red, false);
+        hi = block_reduce(hi, red, true);
+        const double scale = hi > lo ? (double)NBIN / (hi - lo) : 0.0;
+        auto bin_of = [&](double e) -> int {
+            const int k = (int)((e - lo) * scale);
+            return k < 0 ? 0 : (k >= NBIN ? NBIN - 1 : k);
+        };
+        for (int k = threadIdx.x; k < NBIN; k += blockDim.x) hist[k] = 0;
+        __syncthreads();
+        for (int c = threadIdx.x; c < n; c += blockDim.x) atomicAdd(&hist[bin_of(candE(c))], 1);
+        __syncthreads();
+        // first bin at which the running count reaches the target (4 bins per thread)
+        int local = 0;
+        for (int k = 0; k < NBIN / 256; ++k) local += hist[threadIdx.x * (NBIN / 256) + k];
+        int excl;
+        block_exclusive_scan(local, tmp, excl);
+        int run = excl, found = -1;
+        for (int k = 0; k < NBIN / 256 && found < 0; ++k) {
+            run += hist[threadIdx.x * (NBIN / 256) + k];
+            if (run >= target && run - hist[threadIdx.x * (NBIN / 256) + k] < target)
+                found = threadIdx.x * (NBIN / 256) + k;
+        }
+        if (found >= 0) tmp[0] = found;
+        __syncthreads();
+        const int bmax = tmp[0];
+        __syncthreads();
+        // compact the candidates of bins <= bmax (if they fit the sort arrays)
+        int np = 0;
+        for (int c0 = 0; c0 < n; c0 += 256) {
+            const int c = c0 + threadIdx.x;
+            const int in = (c < n && bin_of(candE(c)) <= bmax) ? 1 : 0;
+            int ex;
+            const int tot = block_exclusive_scan(in, tmp, ex);
+            if (in && np + ex < MERGE_CH) load_cand(c, np + ex);
+            np += tot;
         }
         __syncthreads();
-        nrun = sort_dedupe_keep(src, W, key, ref, zk, nrun + take, M, tmp, keep);
-        pos += take;
-    } while (pos < cnt);
+        if (np <= MERGE_CH) {
+            nrun = sort_dedupe_keep(src, W, key, ref, zk, np, M, tmp, keep);
+            if (nrun < M && np < n) nrun = -1;   // not enough distinct states below: sort everything
+        }
+    }
+    if (nrun < 0) {
+        // everything, in passes that carry the running best M
+        for (int c = threadIdx.x; c < nk; c += blockDim.x) load_cand(c, c);
+        __syncthreads();
+        nrun = nk;
+        int pos = nk;
+        do {
+            const int take = min(n - pos, MERGE_CH - nrun);
+            for (int t = threadIdx.x; t < take; t += blockDim.x) load_cand(pos + t, nrun + t);
+            __syncthreads();
+            nrun = sort_dedupe_keep(src, W, key, ref, zk, nrun + take, M, tmp, keep);
+            pos += take;
+        } while (pos < n);
+    }
 
     if (threadIdx.x == 0) atomicAdd(&lay.ctr[CTR_SURV], (unsigned long long)cnt);
     if (ctot > lay.cap_surv) {
@@ -832,6 +938,7 @@ __global__ __launch_bounds__(256) void k_merge(Layout lay, const double* __restr
             const double nc = nrun == M ? key[M - 1] : oldc;
             lay.cut[s] = nc;
             lay.retry[s] = 1;
+            lay.nm_count[s] = 0;
             atomicAdd(&lay.flags[FLAG_OVERFLOW], 1);
             atomicAdd(&lay.ctr[CTR_RETRY], 1ull);
             if (!(nc < oldc)) atomicAdd(&lay.flags[FLAG_STUCK], 1);
@@ -842,7 +949,7 @@ __global__ __launch_bounds__(256) void k_merge(Layout lay, const double* __restr
     // slots used by the current set; new states take the free ones in order
     for (int q = threadIdx.x; q < 2 * M; q += blockDim.x) used[q] = 0;
     __syncthreads();
-    for (int k = threadIdx.x; k < nk; k += blockDim.x) used[lay.kept[(size_t)s * M + k]] = 1;
+    for (int k = threadIdx.x; k < nk; k += blockDim.x) used[keptl[k]] = 1;
     __syncthreads();
     int nfree = 0;
     for (int c0 = 0; c0 < 2 * M; c0 += 256) {
@@ -854,7 +961,6 @@ __global__ __launch_bounds__(256) void k_merge(Layout lay, const double* __restr
         nfree += tot;
     }
     __syncthreads();
-    // slot of every member; new members are numbered in list order
     int nnew = 0;
     for (int c0 = 0; c0 < nrun; c0 += 256) {
         const int k = c0 + threadIdx.x;
@@ -868,62 +974,79 @@ __global__ __launch_bounds__(256) void k_merge(Layout lay, const double* __restr
                 const int slot = freeslot[m];
                 kslot[k] = slot;
                 keep[k] = 1;
-                ncode[m] = (int)r.code;
-                npair[m] = r.pair;
+                lay.nm_code[(size_t)s * M + m] = (int)r.code;
+                lay.nm_pair[(size_t)s * M + m] = r.pair;
+                lay.nm_slot[(size_t)s * M + m] = slot;
                 lay.E[q0 + slot] = r.E;
                 lay.zob[q0 + slot] = zk[k];
                 lay.fresh[q0 + slot] = 1;
-                // stash the member's slot where the field update finds it
-                used[m] = 0;
+                const int i = (int)(r.pair & 0xFFFFu), j = (int)(r.pair >> 16);
+                const uint64_t* xp = lay.bits + (size_t)r.code * lay.Wmax;
+                uint64_t* xn = lay.bits + (q0 + slot) * lay.Wmax;
+                for (int w = 0; w < lay.Wmax; ++w) {
+                    uint64_t v = xp[w];
+                    if ((i >> 6) == w) v ^= 1ull << (i & 63);
+                    if (j != (int)SINGLE && (j >> 6) == w) v ^= 1ull << (j & 63);
+                    xn[w] = v;
+                }
             } else {
-                kslot[k] = lay.kept[(size_t)s * M + ref[k]];
+                kslot[k] = keptl[ref[k]];
                 keep[k] = 0;
             }
         }
         nnew += tot;
     }
     __syncthreads();
-    // old members that stay are no longer new; new member m lives in freeslot[m]
-    for (int k = threadIdx.x; k < nrun; k += blockDim.x)
+    for (int k = threadIdx.x; k < nrun; k += blockDim.x) {
         if (!keep[k]) lay.fresh[q0 + kslot[k]] = 0;
-    // bits of new members
-    for (int t = threadIdx.x; t < nnew * lay.Wmax; t += blockDim.x) {
-        const int m = t / lay.Wmax, w = t - m * lay.Wmax;
-        const uint32_t pr = npair[m];
-        const int i = (int)(pr & 0xFFFFu), j = (int)(pr >> 16);
-        uint64_t v = lay.bits[(size_t)ncode[m] * lay.Wmax + w];
-        if ((i >> 6) == w) v ^= 1ull << (i & 63);
-        if (j != (int)SINGLE && (j >> 6) == w) v ^= 1ull << (j & 63);
-        lay.bits[(q0 + freeslot[m]) * lay.Wmax + w] = v;
-    }
-    // local fields of new members, all members and sites in parallel
-    const int N = lay.N[b], Np = lay.Npad[b];
-    const double* Jb = J4 + lay.joff[b];
-    for (int t = threadIdx.x; t < nnew * Np; t += blockDim.x) {
-        const int m = t / Np, kk = t - m * Np;
-        const uint32_t pr = npair[m];
-        const int i = (int)(pr & 0xFFFFu), j = (int)(pr >> 16);
-        const int code = ncode[m];
-        const uint64_t* xp = lay.bits + (size_t)code * lay.Wmax;
-        const double* Fp = lay.F + (size_t)code * lay.Npmax;
-        double v = Fp[kk] - 0.5 * spin_of(xp, i) * Jb[(size_t)i * Np + kk];   // -2 s_i J = -0.5 s_i (4J)
-        if (j != (int)SINGLE) v -= 0.5 * spin_of(xp, j) * Jb[(size_t)j * Np + kk];
-        lay.F[(q0 + freeslot[m]) * lay.Npmax + kk] = kk < N ? v : 0.0;
-    }
-    for (int k = threadIdx.x; k < nrun; k += blockDim.x)
         lay.kept[(size_t)s * M + k] = kslot[k];
+    }
     if (threadIdx.x == 0) {
         lay.nkept[s] = nrun;
+        lay.nm_count[s] = nnew;
         lay.retry[s] = 0;
         if (nnew > 0) atomicAdd(&lay.flags[FLAG_ACTIVE], 1);
         else lay.active[s] = 0;
     }
 }
 
+// ------------------------------------------------------------------ k_fupdate
+// Local fields of the states that entered in the last merge (row a6):
+// F_k = F_k(parent) - 2 s_i J_ik - 2 s_j J_jk with the parent's spins.  One
+// wave per new state, lanes over sites; grid (search, group of 4 states).
+__global__ __launch_bounds__(256) void k_fupdate(Layout lay, const double* __restrict__ J4)
+{
+    const int s = blockIdx.x;
+    const int m = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (m >= lay.nm_count[s]) return;
+    const int b = s / lay.L;
+    const int N = lay.N[b], Np = lay.Npad[b];
+    const size_t k0 = (size_t)s * lay.M + m;
+    const int code = lay.nm_code[k0];
+    const uint32_t pr = lay.nm_pair[k0];
+    const int slot = lay.nm_slot[k0];
+    const int i = (int)(pr & 0xFFFFu), j = (int)(pr >> 16);
+    const uint64_t* xp = lay.bits + (size_t)code * lay.Wmax;
+    const double ci = -0.5 * spin_of(xp, i);   // -2 s_i J = -0.5 s_i (4J)
+    const bool pairf = j != (int)SINGLE;
+    const double cj = pairf ? -0.5 * spin_of(xp, j) : 0.0;
+    const double* Jb = J4 + lay.joff[b];
+    const double* Ji = Jb + (size_t)i * Np;
+    const double* Jj = Jb + (size_t)(pairf ? j : i) * Np;
+    const double* Fp = lay.F + (size_t)code * lay.Npmax;
+    double* Fn = lay.F + ((size_t)s * 2 * lay.M + slot) * lay.Npmax;
+    for (int k = lane; k < Np; k += 64) {
+        double v = Fp[k] + ci * Ji[k];
+        if (pairf) v += cj * Jj[k];
+        Fn[k] = k < N ? v : 0.0;
+    }
+}
+
 // ------------------------------------------------------------------ k_final
 // Alg. 4: per instance, the M lowest distinct states of the union of its L
 // kept sets, sorted by (E, psi).
-__global__ __launch_bounds__(256) void k_final(Layout lay)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_final(Layout lay)
 {
     __shared__ double key[MERGE_CH];
     __shared__ uint32_t ref[MERGE_CH];
@@ -996,6 +1119,12 @@ hipError_t launch_scan(const Layout& lay, int scan_grid, hipStream_t st)
 hipError_t launch_merge(const Layout& lay, hipStream_t st)
 {
     hipLaunchKernelGGL(k_merge, dim3(lay.S), dim3(256), 0, st, lay, lay.J4);
+    return hipGetLastError();
+}
+
+hipError_t launch_fupdate(const Layout& lay, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fupdate, dim3(lay.S, (lay.M + 3) / 4), dim3(256), 0, st, lay, lay.J4);
     return hipGetLastError();
 }
 
