@@ -92,7 +92,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--instances", type=int, default=120)
+    ap.add_argument("--instances", type=int, default=0, help="reduce the instance count (0 = the full workload)")
+    ap.add_argument("--workload", choices=["c3", "c4"], default="c3",
+                    help="c3: 120 x N=600, L=64 (the metric's workload); c4: 480 instances of uneven N, "
+                         "L=32, run as the batching form (persistent graph, autotuned tiles)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-gib", type=float, default=0.0,
@@ -108,13 +111,22 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    w = workloads.c3_n600(n_instances=args.instances)
+    batching = args.workload == "c4"
+    if batching:
+        w = workloads.c4_uneven(n_instances=args.instances or 480)
+    else:
+        w = workloads.c3_n600(n_instances=args.instances or 120)
     log(f"workload {w.name}: {len(w.instances)} instances, L={w.L}, M={w.M}")
-    s = binding.IsingSearch.from_workload(w, timing=1)
+    s = binding.IsingSearch.from_workload(w, timing=1, persistent=1 if batching else 0)
     torch.cuda.synchronize()
+    tuned = [False]
 
     def one_pass():
         s.reset()
+        if batching and not tuned[0]:
+            s.step()
+            s.autotune()
+            tuned[0] = True
         it, stable = s.run()
         s.get_states(0)
         return it, stable
@@ -144,6 +156,7 @@ def main():
     traffic = load_traffic(digest)
 
     E1 = [float(s.get_states(b)[1][0]) for b in range(len(w.instances))]
+    tiles = s.tuning()
     per_inst = wall / args.steps / len(w.instances)
 
     if args.copy_gib > 0:
@@ -175,9 +188,13 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{w.name}: {len(w.instances)} instances N=600 J~N(0,1)/sqrt(N) h~N(0,1) on the 2^-24 grid, "
-                        f"M={w.M} kept, L={w.L} initial states each, plain FP64 form, run to stable",
-            "instances": len(w.instances), "N": 600, "M": w.M, "L": w.L, "form": "plain",
+            "workload": (f"{w.name}: {len(w.instances)} instances N=600 J~N(0,1)/sqrt(N) h~N(0,1) on the 2^-24 grid, "
+                         f"M={w.M} kept, L={w.L} initial states each, plain FP64 form, run to stable") if not batching else
+                        (f"{w.name}: {len(w.instances)} instances with N drawn from 100..600 (step 100), same "
+                         f"distributions, M={w.M}, L={w.L}, batching form: persistent graph-replayed steps, "
+                         f"autotuned scan tiles per N, run to stable"),
+            "instances": len(w.instances), "N": 600 if not batching else "100..600", "M": w.M, "L": w.L,
+            "form": "plain" if not batching else "plain, batching (persistent + autotuned)",
         },
         "time_per_instance_s": per_inst,
         "tts_per_instance_s": per_inst,
@@ -185,8 +202,9 @@ def main():
         "iterations": iters,
         "mean_E1": sum(E1) / len(E1),
         "scan_kernel_evals_per_s": pairs / scan_s if scan_s > 0 else None,
-        "kernel_ms_per_step": {k: d[k + "_ms"] / args.steps for k in ("scan", "merge", "frontier", "prep", "init")},
+        "kernel_ms_per_step": {k: d[k + "_ms"] / args.steps for k in ("scan", "merge", "frontier", "prep", "init", "step")},
         "survivors": d["survivors"],
+        "scan_states_per_item": sorted(set(zip([i.N for i in w.instances], tiles))),
         "retries": d["retries"],
         "roofline": {
             "kernel": "k_scan",

@@ -62,7 +62,8 @@ typedef struct {
     int32_t form;              /* ising_form_t */
     int32_t states_per_item;   /* scan tile: frontier states per work item; 0 = tuned default */
     int32_t topk_factor;       /* learned form: K = topk_factor * N pairs per state (default 8) */
-    int32_t persistent;        /* 1 = capture one step into a hipGraph and replay it in run() */
+    int32_t persistent;        /* 1 = capture the kernels of one step into a hipGraph once and replay
+                                  it for every step (an internal stream is used when none is given) */
     int32_t timing;            /* 1 = time every kernel family with hipEvents on the handle's stream */
     int32_t reserved;          /* must be zero */
 } ising_config_t;
@@ -81,7 +82,8 @@ typedef struct {
     double frontier_ms;        /* device time of frontier listing, pilot cut and planning, summed */
     double prep_ms;            /* device time of the per-state preparation, summed */
     double init_ms;            /* device time of local fields and seeding (init and reset), summed */
-    uint64_t reserved[2];
+    double step_ms;            /* persistent mode: device time of the replayed step graphs, summed */
+    uint64_t reserved[1];
 } ising_stats_t;
 
 /*
@@ -163,6 +165,19 @@ int ising_search_set_search(ising_search_t *s, int32_t search, const uint64_t *b
                             const uint8_t *front, int32_t count);
 
 int ising_search_get_stats(ising_search_t *s, ising_stats_t *out);
+
+/*
+ * One step (as ising_search_step) that first tunes the pair scan: for every
+ * distinct N among the instances it times the scan for 16, 32, 64 and 128
+ * frontier states per work item on this step's frontier (coordinate descent
+ * over the N buckets) and keeps the fastest.  Results do not depend on the
+ * choice; only the time does.  Best called once the frontier is full (after
+ * the first step).
+ */
+int ising_search_autotune(ising_search_t *s, int32_t *n_active);
+
+/* The states per scan item in use for each instance (n_inst values). */
+int ising_search_get_tuning(ising_search_t *s, int32_t *states_per_item);
 
 /* Frees all device memory of the handle.  NULL is accepted. */
 void ising_search_destroy(ising_search_t *s);

@@ -38,6 +38,8 @@ EXPORTED = (
     "ising_search_get_search",
     "ising_search_set_search",
     "ising_search_get_stats",
+    "ising_search_autotune",
+    "ising_search_get_tuning",
     "ising_search_destroy",
     "ising_search_last_error",
 )
@@ -71,7 +73,8 @@ class IsingStats(ctypes.Structure):
         ("frontier_ms", ctypes.c_double),
         ("prep_ms", ctypes.c_double),
         ("init_ms", ctypes.c_double),
-        ("reserved", ctypes.c_uint64 * 2),
+        ("step_ms", ctypes.c_double),
+        ("reserved", ctypes.c_uint64 * 1),
     ]
 
     def as_dict(self):
@@ -114,6 +117,10 @@ def load(path: str = LIB_PATH):
     L.ising_search_set_search.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_int32]
     L.ising_search_get_stats.restype = ctypes.c_int
     L.ising_search_get_stats.argtypes = [vp, ctypes.POINTER(IsingStats)]
+    L.ising_search_autotune.restype = ctypes.c_int
+    L.ising_search_autotune.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.ising_search_get_tuning.restype = ctypes.c_int
+    L.ising_search_get_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.ising_search_destroy.restype = None
     L.ising_search_destroy.argtypes = [vp]
     L.ising_search_last_error.restype = ctypes.c_char_p
@@ -240,6 +247,16 @@ class IsingSearch:
             front = np.ascontiguousarray(front, dtype=np.uint8)
             fp = front.ctypes.data
         _check(load().ising_search_set_search(self._h, int(search), bits.ctypes.data, fp, bits.shape[0]))
+
+    def autotune(self) -> int:
+        n = ctypes.c_int32(0)
+        _check(load().ising_search_autotune(self._h, ctypes.byref(n)))
+        return n.value
+
+    def tuning(self):
+        out = (ctypes.c_int32 * self.B)()
+        _check(load().ising_search_get_tuning(self._h, out))
+        return list(out)
 
     def stats(self) -> dict:
         st = IsingStats()

@@ -4,6 +4,7 @@
 // k_step.hip; this file only moves data and orders launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -59,8 +60,16 @@ struct ising_search {
     // timing (cfg.timing): events around each kernel family of a step
     bool timing = false;
     hipEvent_t ev[6]{};
-    double t_scan = 0, t_merge = 0, t_frontier = 0, t_prep = 0, t_init = 0;
+    double t_scan = 0, t_merge = 0, t_frontier = 0, t_prep = 0, t_init = 0, t_step = 0;
     uint64_t scan_launches = 0;
+    // states per scan item, per instance (host copy of lay.scb)
+    std::vector<int> sc_h;
+    int* d_scb = nullptr;
+    // persistent mode: one step captured into a graph
+    bool persistent = false;
+    hipStream_t own_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
 };
 
 namespace {
@@ -91,8 +100,14 @@ int dalloc(ising_search* h, T** p, size_t count)
 
 void free_all(ising_search* h)
 {
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    h->gexec = nullptr;
+    h->graph = nullptr;
     for (void* p : h->allocs) (void)hipFree(p);
     h->allocs.clear();
+    if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
+    h->own_stream = nullptr;
     for (hipEvent_t& e : h->ev) {
         if (e) (void)hipEventDestroy(e);
         e = nullptr;
@@ -223,7 +238,17 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     lay.Npmax = pad_of(Nmax);
     lay.fmax = L * cfg->M;
     lay.cap_surv = 32768;
-    lay.sc = cfg->states_per_item > 0 ? cfg->states_per_item : 64;
+    const int sc0 = cfg->states_per_item > 0 ? cfg->states_per_item : 64;
+    hd->sc_h.assign(n_inst, sc0);
+    hd->persistent = cfg->persistent != 0;
+    if (hd->persistent && !hd->stream) {
+        // a graph cannot be captured on the legacy default stream
+        if (hipStreamCreateWithFlags(&hd->own_stream, hipStreamNonBlocking) != hipSuccess) {
+            delete hd;
+            return fail(ISING_ERR_HIP, "hipStreamCreate failed");
+        }
+        hd->stream = hd->own_stream;
+    }
     hd->N.assign(N, N + n_inst);
     hd->Npad.resize(n_inst);
     std::vector<long long> joff(n_inst);
@@ -269,6 +294,7 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     ALLOC(lay.item_prefix, 2 * ((size_t)n_inst + 1));
     ALLOC(lay.ctr, 16);
     ALLOC(lay.flags, 8);
+    ALLOC(hd->d_scb, n_inst);
     ALLOC(lay.nm_count, S);
     ALLOC(lay.nm_code, S * lay.M);
     ALLOC(lay.nm_pair, S * lay.M);
@@ -288,6 +314,7 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     lay.J4 = dJ4;
     lay.h = dh;
     lay.zkey = dz;
+    lay.scb = hd->d_scb;
     hd->x0 = dx0;
     hd->timing = cfg->timing != 0;
     if (hd->timing) {
@@ -338,6 +365,7 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
         cp(dh, hh.data(), sizeof(double) * hh.size());
         cp(dz, zk.data(), sizeof(uint64_t) * zk.size());
         cp(dx0, x0.data(), sizeof(uint64_t) * x0.size());
+        cp(hd->d_scb, hd->sc_h.data(), sizeof(int) * n_inst);
         if (r2 == ISING_OK) {
             hipError_t e = hipMemsetAsync(lay.ctr, 0, 16 * sizeof(unsigned long long), sm);
             if (e == hipSuccess) e = hipMemsetAsync(lay.flags, 0, 8 * sizeof(int), sm);
@@ -398,10 +426,36 @@ static void collect_times(ising_search* h)
     h->t_merge += elapsed_ms(h->ev[3], h->ev[4]);
 }
 
+// Persistent mode: the kernels of one normal pass are captured once into a
+// graph; each step replays it (retry passes after an overflow stay eager).
+static hipError_t launch_graph_pass(ising_search* h)
+{
+    hipError_t e = hipSuccess;
+    if (!h->gexec) {
+        const bool tm = h->timing;
+        h->timing = false;   // no events inside the captured pass
+        e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t e2 = launch_pass(h, false);
+            --h->scan_launches;
+            e = hipStreamEndCapture(h->stream, &h->graph);
+            if (e == hipSuccess) e = e2;
+        }
+        h->timing = tm;
+        if (e == hipSuccess) e = hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) return e;
+    }
+    if (h->timing) e = hipEventRecord(h->ev[0], h->stream);
+    if (e == hipSuccess) e = hipGraphLaunch(h->gexec, h->stream);
+    if (e == hipSuccess && h->timing) e = hipEventRecord(h->ev[5], h->stream);
+    if (e == hipSuccess) ++h->scan_launches;
+    return e;
+}
+
 static int do_step(ising_search* h, int32_t* n_active)
 {
     const Layout& lay = h->lay;
-    hipError_t e = launch_pass(h, false);
+    hipError_t e = h->persistent ? launch_graph_pass(h) : launch_pass(h, false);
     if (e != hipSuccess) {
         h->broken = true;
         return fail(ISING_ERR_HIP, "step launch failed: %s", hipGetErrorString(e));
@@ -411,7 +465,11 @@ static int do_step(ising_search* h, int32_t* n_active)
         h->broken = true;
         return rc;
     }
-    collect_times(h);
+    if (h->persistent) {
+        if (h->timing) h->t_step += elapsed_ms(h->ev[0], h->ev[5]);
+    } else {
+        collect_times(h);
+    }
     int guard = 0;
     while (h->flags_h[FLAG_OVERFLOW] > 0) {
         if (h->flags_h[FLAG_STUCK] > 0 || ++guard > 64)
@@ -432,6 +490,106 @@ static int do_step(ising_search* h, int32_t* n_active)
     }
     h->final_dirty = true;
     if (n_active) *n_active = h->flags_h[FLAG_ACTIVE];
+    return ISING_OK;
+}
+
+// One step that first chooses the states per scan item for every distinct N:
+// after the frontier and the per-state preparation, the scan (which only
+// appends survivors, so it can be repeated after clearing them) is timed for
+// each candidate, one N bucket at a time with the others held at their best.
+extern "C" int ising_search_autotune(ising_search_t* s, int32_t* n_active)
+{
+    g_err.clear();
+    int rc = check_handle(s);
+    if (rc != ISING_OK) return rc;
+    const Layout& lay = s->lay;
+    hipStream_t st = s->stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(ISING_ERR_HIP, "hipEventCreate failed");
+    }
+    static const int cand[] = {16, 32, 64, 128};
+    std::vector<int> sizes(s->N);
+    std::sort(sizes.begin(), sizes.end());
+    sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+    hipError_t e = launch_step_begin(lay, false, st);
+    if (e == hipSuccess) e = launch_frontier_plan(lay, st);
+    auto scan_ms = [&](float& ms) -> hipError_t {
+        hipError_t r = hipMemcpyAsync(s->d_scb, s->sc_h.data(), sizeof(int) * lay.B, hipMemcpyHostToDevice, st);
+        if (r == hipSuccess) r = launch_plan_only(lay, st);
+        if (r == hipSuccess) r = launch_clear_survivors(lay, st);
+        if (r == hipSuccess) r = launch_prep(lay, st);
+        if (r == hipSuccess) r = hipEventRecord(e0, st);
+        if (r == hipSuccess) r = launch_scan(lay, s->scan_grid, st);
+        if (r == hipSuccess) r = hipEventRecord(e1, st);
+        if (r == hipSuccess) r = hipStreamSynchronize(st);
+        if (r == hipSuccess) ms = elapsed_ms(e0, e1);
+        return r;
+    };
+    for (size_t k = 0; k < sizes.size() && e == hipSuccess; ++k) {
+        int best = -1;
+        float best_ms = 0.f;
+        for (int c : cand) {
+            for (int b = 0; b < lay.B; ++b)
+                if (s->N[b] == sizes[k]) s->sc_h[b] = c;
+            float ms = 0.f;
+            e = scan_ms(ms);
+            if (e != hipSuccess) break;
+            if (best < 0 || ms < best_ms) {
+                best = c;
+                best_ms = ms;
+            }
+        }
+        for (int b = 0; b < lay.B; ++b)
+            if (s->N[b] == sizes[k]) s->sc_h[b] = best;
+    }
+    // the step itself with the chosen tiles
+    float ms = 0.f;
+    if (e == hipSuccess) e = scan_ms(ms);
+    if (e == hipSuccess) e = launch_merge(lay, st);
+    if (e == hipSuccess) e = launch_fupdate(lay, st);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) {
+        s->broken = true;
+        return fail(ISING_ERR_HIP, "autotune step failed: %s", hipGetErrorString(e));
+    }
+    ++s->scan_launches;
+    rc = sync_flags(s);
+    if (rc != ISING_OK) {
+        s->broken = true;
+        return rc;
+    }
+    int guard = 0;
+    while (s->flags_h[FLAG_OVERFLOW] > 0) {
+        if (s->flags_h[FLAG_STUCK] > 0 || ++guard > 64)
+            return fail(ISING_ERR_CAPACITY,
+                        "a search has more tied candidates at its cut than its buffer holds (%d records)",
+                        lay.cap_surv);
+        e = launch_pass(s, true);
+        if (e != hipSuccess) {
+            s->broken = true;
+            return fail(ISING_ERR_HIP, "retry launch failed: %s", hipGetErrorString(e));
+        }
+        rc = sync_flags(s);
+        if (rc != ISING_OK) {
+            s->broken = true;
+            return rc;
+        }
+    }
+    s->final_dirty = true;
+    if (n_active) *n_active = s->flags_h[FLAG_ACTIVE];
+    return ISING_OK;
+}
+
+extern "C" int ising_search_get_tuning(ising_search_t* s, int32_t* states_per_item)
+{
+    g_err.clear();
+    int rc = check_handle(s);
+    if (rc != ISING_OK) return rc;
+    if (!states_per_item) return fail(ISING_ERR_INVALID_ARG, "NULL output pointer");
+    for (int b = 0; b < s->lay.B; ++b) states_per_item[b] = s->sc_h[b];
     return ISING_OK;
 }
 
@@ -632,6 +790,7 @@ extern "C" int ising_search_get_stats(ising_search_t* s, ising_stats_t* out)
     out->frontier_ms = s->t_frontier;
     out->prep_ms = s->t_prep;
     out->init_ms = s->t_init;
+    out->step_ms = s->t_step;
     return ISING_OK;
 }
 

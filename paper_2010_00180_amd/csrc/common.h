@@ -48,7 +48,7 @@ struct Layout {
     int Wmax, Npmax;         // words and padded spins of the largest instance
     int fmax;                // frontier entries per instance (= L*M)
     int cap_surv;            // survivor records per search
-    int sc;                  // frontier states per scan item
+    const int* scb;          // [B] frontier states per scan item, per instance (tuned per N)
     const int* N;            // [B]
     const int* Npad;         // [B]
     const long long* joff;   // [B] offset of instance b in J4 (doubles)
@@ -107,6 +107,8 @@ __host__ __device__ inline long long tiles_of(int N) {
 hipError_t launch_init_fields(const Layout& lay, const uint64_t* d_x0, hipStream_t st);
 hipError_t launch_fields_for(const Layout& lay, int search, int count, hipStream_t st);
 hipError_t launch_frontier_plan(const Layout& lay, hipStream_t st);
+hipError_t launch_plan_only(const Layout& lay, hipStream_t st);      // re-plan without counting
+hipError_t launch_clear_survivors(const Layout& lay, hipStream_t st);
 hipError_t launch_prep(const Layout& lay, hipStream_t st);
 hipError_t launch_scan(const Layout& lay, int scan_grid, hipStream_t st);
 hipError_t launch_merge(const Layout& lay, hipStream_t st);

@@ -301,7 +301,7 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
 // ------------------------------------------------------------------ k_plan
 // One block.  Work prefix sums over instances: scan items (chunks x tiles)
 // and frontier entries; also the evaluation counters.
-__global__ __launch_bounds__(1024) void k_plan(Layout lay, long long* __restrict__ fr_prefix)
+__global__ __launch_bounds__(1024) void k_plan(Layout lay, long long* __restrict__ fr_prefix, int count)
 {
     __shared__ long long part_items[1024];
     __shared__ long long part_fr[1024];
@@ -312,7 +312,8 @@ __global__ __launch_bounds__(1024) void k_plan(Layout lay, long long* __restrict
     for (int b = b0; b < b0 + per && b < lay.B; ++b) {
         const long long P = lay.fr_count[b];
         const long long N = lay.N[b];
-        items += (P + lay.sc - 1) / lay.sc * tiles_of((int)N);
+        const int sc = lay.scb[b];
+        items += (P + sc - 1) / sc * tiles_of((int)N);
         fr += P;
         pairs += P * (N * (N - 1) / 2);
         singles += P * N;
@@ -333,7 +334,7 @@ __global__ __launch_bounds__(1024) void k_plan(Layout lay, long long* __restrict
         lay.item_prefix[b] = run_i;
         fr_prefix[b] = run_f;
         const long long P = lay.fr_count[b];
-        run_i += (P + lay.sc - 1) / lay.sc * tiles_of(lay.N[b]);
+        run_i += (P + lay.scb[b] - 1) / lay.scb[b] * tiles_of(lay.N[b]);
         run_f += P;
     }
     if (t == 1023) {
@@ -349,7 +350,7 @@ __global__ __launch_bounds__(1024) void k_plan(Layout lay, long long* __restrict
         if (t < w) { cp[t] += cp[t + w]; cs[t] += cs[t + w]; }
         __syncthreads();
     }
-    if (t == 0 && !lay.flags[FLAG_RETRY_MODE]) {
+    if (t == 0 && count && !lay.flags[FLAG_RETRY_MODE]) {
         lay.ctr[CTR_PAIRS] += cp[0];
         lay.ctr[CTR_SINGLES] += cs[0];
         lay.ctr[CTR_FRONTIER] += (unsigned long long)part_fr[1023];
@@ -501,8 +502,9 @@ __global__ __launch_bounds__(64) void k_scan(Layout lay, const double* __restric
         bi = uniform_int(bi);
         const int bc = uniform_int(2 * bi + t);
         const int P = lay.fr_count[b];
-        const int f0 = c * lay.sc;
-        const int f1 = min(f0 + lay.sc, P);
+        const int sc = lay.scb[b];
+        const int f0 = c * sc;
+        const int f1 = min(f0 + sc, P);
 
         // the tile: row i = bi*64 + lane, columns j = bc*32 + 0..31, unsigned
         const int row = bi * TILE + (int)lane;
@@ -1098,7 +1100,26 @@ hipError_t launch_frontier_plan(const Layout& lay, hipStream_t st)
 {
     long long* fr_prefix = lay.item_prefix + (lay.B + 1);
     hipLaunchKernelGGL(k_frontier, dim3(lay.S), dim3(256), 0, st, lay, lay.J4);
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, lay, fr_prefix);
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, lay, fr_prefix, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_only(const Layout& lay, hipStream_t st)
+{
+    long long* fr_prefix = lay.item_prefix + (lay.B + 1);
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, lay, fr_prefix, 0);
+    return hipGetLastError();
+}
+
+__global__ void k_clear_survivors(Layout lay)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < lay.S) lay.surv_count[t] = 0;
+}
+
+hipError_t launch_clear_survivors(const Layout& lay, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_clear_survivors, dim3((lay.S + 255) / 256), dim3(256), 0, st, lay);
     return hipGetLastError();
 }
 

@@ -198,3 +198,82 @@ def test_reset_repeats_the_search_exactly():
         gb, gE = s.get_states(b)
         assert np.array_equal(gb, fm[b][0]) and np.array_equal(gE, fm[b][1])
     s.destroy()
+
+
+def test_persistent_graph_replays_match_eager_every_step():
+    """Uneven N in one handle; the graph replay of a step must equal the eager
+    launches after every replay (eager copies and synchronizations between)."""
+    w = wl.custom([100, 200, 300, 64, 129, 600], L=3, M=40, config=18)
+    note("[graph] uneven N, persistent vs eager")
+    a = binding.IsingSearch.from_workload(w)
+    g = binding.IsingSearch.from_workload(w, persistent=1)
+    for t in range(400):
+        na = a.step()
+        ng = g.step()
+        assert na == ng, f"step {t + 1}: active {na} vs {ng}"
+        for sid in range(a.B * a.L):
+            assert_same_set(g.get_search(sid), a.get_search(sid), f"graph search {sid} step {t + 1}")
+        if na == 0:
+            break
+    assert na == 0
+    for b in range(a.B):
+        ab, aE = a.get_states(b)
+        gb, gE = g.get_states(b)
+        assert np.array_equal(ab, gb) and np.array_equal(aE, gE)
+    # the small instances against the oracle
+    for b in (3, 4):
+        inst = w.instances[b]
+        for l in range(w.L):
+            ob, oE, _, _ = oracle.search(inst.J, inst.h, w.M, inst.init_bits[l])
+            gb, gE, _ = g.get_search(b * w.L + l)
+            assert np.array_equal(gb, ob) and np.array_equal(gE, oE)
+    a.destroy()
+    g.destroy()
+
+
+def test_autotune_keeps_results_and_picks_candidates():
+    w = wl.custom([100, 300, 100, 500], L=4, M=60, config=19)
+    note("[autotune]")
+    a = binding.IsingSearch.from_workload(w)
+    t = binding.IsingSearch.from_workload(w, persistent=1)
+    a.step()
+    t.step()
+    a.step()
+    t.autotune()
+    tiles = t.tuning()
+    assert all(x in (16, 32, 64, 128) for x in tiles)
+    assert tiles[0] == tiles[2]   # same N, same choice
+    a.run()
+    t.run()
+    for sid in range(a.B * a.L):
+        assert_same_set(t.get_search(sid), a.get_search(sid), f"autotuned search {sid}")
+    a.destroy()
+    t.destroy()
+
+
+def test_uneven_batch_persistent_sampled():
+    """A reduced batch shaped like the 480-instance uneven workload (N drawn from
+    100..600, L=32, M=120), persistent and autotuned, sampled against the oracle."""
+    w = wl.c4_uneven(n_instances=48, L=32)
+    note(f"[c4-shaped] sizes={sorted(set(i.N for i in w.instances))}")
+    s = binding.IsingSearch.from_workload(w, persistent=1)
+    s.step()
+    s.autotune()
+    it, stable = s.run()
+    assert stable
+    rng = np.random.default_rng(4)
+    small = [b for b, inst in enumerate(w.instances) if inst.N == 100]
+    for b in rng.choice(small, 2, replace=False):
+        inst = w.instances[int(b)]
+        l = int(rng.integers(w.L))
+        ob, oE, _, _ = oracle.search(inst.J, inst.h, w.M, inst.init_bits[l])
+        gb, gE, _ = s.get_search(int(b) * w.L + l)
+        assert np.array_equal(gb, ob) and np.array_equal(gE, oE)
+    for b in rng.choice(len(w.instances), 6, replace=False):
+        inst = w.instances[int(b)]
+        gb, gE = s.get_states(int(b))
+        assert len(gE) == w.M and np.all(np.diff(gE) >= 0)
+        assert len({tuple(r) for r in gb}) == len(gb)
+        for k in rng.choice(len(gE), 3, replace=False):
+            assert oracle.energy(inst.J, inst.h, gb[k]) == gE[k]
+    s.destroy()
