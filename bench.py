@@ -87,6 +87,84 @@ def cpu_baseline(w, budget_s):
     }
 
 
+FORM_CODES = {"plain": 0, "split_bf16": 1, "learned": 2}
+
+
+def measure(binding, torch, w, form, steps, warmup, batching, copy_gib):
+    """Complete passes of the method over the batch with one form; device-timed."""
+    s = binding.IsingSearch.from_workload(w, timing=1, persistent=1 if batching else 0,
+                                          form=FORM_CODES[form])
+    torch.cuda.synchronize()
+    tuned = [False]
+
+    def one_pass():
+        s.reset()
+        if batching and not tuned[0]:
+            s.step()
+            s.autotune()
+            tuned[0] = True
+        it, stable = s.run()
+        s.get_states(0)
+        return it, stable
+
+    for k in range(warmup):
+        it, stable = one_pass()
+        log(f"[{form}] warmup {k}: {it} iterations, stable={stable}")
+    st0 = s.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    for k in range(steps):
+        it, stable = one_pass()
+        iters.append(it)
+        log(f"[{form}] step {k}: {it} iterations, stable={stable}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st1 = s.stats()
+    wall = t1 - t0
+    d = {k: st1[k] - st0[k] for k in st1 if isinstance(st1[k], (int, float))}
+    pairs = d["pair_evals"]
+    scan_s = d["scan_ms"] / 1e3
+    launches = max(d["scan_launches"], 1)
+    ops_per_s = OPS_PER_PAIR * pairs / scan_s if scan_s > 0 else 0.0
+    E1 = [float(s.get_states(b)[1][0]) for b in range(len(w.instances))]
+    tiles = s.tuning()
+    if copy_gib > 0:
+        n = int(copy_gib * (1 << 30)) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {n * 8} bytes read, {n * 8} bytes written")
+    s.destroy()
+    torch.cuda.synchronize()
+    return {
+        "wall": wall, "steps": steps, "warmup": warmup, "pairs": pairs,
+        "value": pairs / wall,
+        "ms_per_step": 1e3 * wall / steps,
+        "time_per_instance_s": wall / steps / len(w.instances),
+        "iterations": iters,
+        "E1": E1,
+        "mean_E1": sum(E1) / len(E1),
+        "scan_kernel_evals_per_s": pairs / scan_s if scan_s > 0 else None,
+        "kernel_ms_per_step": {k: d[k + "_ms"] / steps for k in ("scan", "merge", "frontier", "prep", "init", "step")},
+        "survivors": d["survivors"], "retries": d["retries"], "fallbacks": d["fallbacks"],
+        "split_field_err": st1.get("split_field_err"),
+        "scan_states_per_item": sorted(set(zip([i.N for i in w.instances], tiles))),
+        "roofline": {
+            "kernel": "k_scan32" if form == "split_bf16" else "k_scan",
+            "bound": "alu",
+            "achieved": ops_per_s / 1e12,
+            "peak": VALU_LANE_OPS_PER_S / 1e12,
+            "unit": "Tops/s",
+            "frac": ops_per_s / VALU_LANE_OPS_PER_S,
+            "avg_launch_ms": d["scan_ms"] / launches,
+            "ops_per_pair": OPS_PER_PAIR,
+        },
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +176,9 @@ def main():
                          "L=32, run as the batching form (persistent graph, autotuned tiles)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--forms", default="plain,split_bf16",
+                    help="comma list of forms to time; the first gives the headline value")
+    ap.add_argument("--extra-steps", type=int, default=1, help="timed passes for the forms after the first")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="after the timed region, copy this many GiB with torch (counter calibration)")
     args = ap.parse_args()
@@ -117,71 +198,32 @@ def main():
     else:
         w = workloads.c3_n600(n_instances=args.instances or 120)
     log(f"workload {w.name}: {len(w.instances)} instances, L={w.L}, M={w.M}")
-    s = binding.IsingSearch.from_workload(w, timing=1, persistent=1 if batching else 0)
-    torch.cuda.synchronize()
-    tuned = [False]
-
-    def one_pass():
-        s.reset()
-        if batching and not tuned[0]:
-            s.step()
-            s.autotune()
-            tuned[0] = True
-        it, stable = s.run()
-        s.get_states(0)
-        return it, stable
-
-    for k in range(args.warmup):
-        it, stable = one_pass()
-        log(f"warmup {k}: {it} iterations, stable={stable}")
-    st0 = s.stats()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    iters = []
-    for k in range(args.steps):
-        it, stable = one_pass()
-        iters.append(it)
-        log(f"step {k}: {it} iterations, stable={stable}")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st1 = s.stats()
-    wall = t1 - t0
-    d = {k: st1[k] - st0[k] for k in st1}
-    pairs = d["pair_evals"]
-    value = pairs / wall
-    scan_s = d["scan_ms"] / 1e3
-    launches = max(d["scan_launches"], 1)
-    ops_per_s = OPS_PER_PAIR * pairs / scan_s if scan_s > 0 else 0.0
+    forms = [f for f in args.forms.split(",") if f] if not batching else ["plain"]
     digest = source_digest()
-    traffic = load_traffic(digest)
-
-    E1 = [float(s.get_states(b)[1][0]) for b in range(len(w.instances))]
-    tiles = s.tuning()
-    per_inst = wall / args.steps / len(w.instances)
-
-    if args.copy_gib > 0:
-        n = int(args.copy_gib * (1 << 30)) // 8
-        src = torch.ones(n, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"calibration copy: {n * 8} bytes read, {n * 8} bytes written")
+    results = {}
+    for fi, form in enumerate(forms):
+        steps = args.steps if fi == 0 else max(1, args.extra_steps)
+        warmup = args.warmup if fi == 0 else 0
+        results[form] = measure(binding, torch, w, form, steps, warmup, batching, args.copy_gib if fi == 0 else 0)
+    head = results[forms[0]]
 
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and not batching:
         log("timing the CPU oracle on a bounded sample")
         cpu = cpu_baseline(w, args.cpu_seconds)
-    s.destroy()
 
+    traffic = load_traffic(digest)
+    roof = dict(head["roofline"])
+    roof["traffic"] = traffic
+    roof["source_digest"] = digest
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": head["value"],
         "unit": "pair-flip dE evals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * wall / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -189,35 +231,26 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": (f"{w.name}: {len(w.instances)} instances N=600 J~N(0,1)/sqrt(N) h~N(0,1) on the 2^-24 grid, "
-                         f"M={w.M} kept, L={w.L} initial states each, plain FP64 form, run to stable") if not batching else
+                         f"M={w.M} kept, L={w.L} initial states each, {forms[0]} form, run to stable") if not batching else
                         (f"{w.name}: {len(w.instances)} instances with N drawn from 100..600 (step 100), same "
                          f"distributions, M={w.M}, L={w.L}, batching form: persistent graph-replayed steps, "
                          f"autotuned scan tiles per N, run to stable"),
             "instances": len(w.instances), "N": 600 if not batching else "100..600", "M": w.M, "L": w.L,
-            "form": "plain" if not batching else "plain, batching (persistent + autotuned)",
+            "form": forms[0] if not batching else "plain, batching (persistent + autotuned)",
         },
-        "time_per_instance_s": per_inst,
-        "tts_per_instance_s": per_inst,
+        "time_per_instance_s": head["time_per_instance_s"],
+        "tts_per_instance_s": head["time_per_instance_s"],
         "tts_note": "p1 = 1 against the best energy this run finds (no certified reference at N=600), so TTS = t",
-        "iterations": iters,
-        "mean_E1": sum(E1) / len(E1),
-        "scan_kernel_evals_per_s": pairs / scan_s if scan_s > 0 else None,
-        "kernel_ms_per_step": {k: d[k + "_ms"] / args.steps for k in ("scan", "merge", "frontier", "prep", "init", "step")},
-        "survivors": d["survivors"],
-        "scan_states_per_item": sorted(set(zip([i.N for i in w.instances], tiles))),
-        "retries": d["retries"],
-        "roofline": {
-            "kernel": "k_scan",
-            "bound": "alu",
-            "achieved": ops_per_s / 1e12,
-            "peak": VALU_LANE_OPS_PER_S / 1e12,
-            "unit": "Tops/s",
-            "frac": ops_per_s / VALU_LANE_OPS_PER_S,
-            "traffic": traffic,
-            "avg_launch_ms": d["scan_ms"] / launches,
-            "ops_per_pair": OPS_PER_PAIR,
-            "source_digest": digest,
-        },
+        "iterations": head["iterations"],
+        "mean_E1": head["mean_E1"],
+        "scan_kernel_evals_per_s": head["scan_kernel_evals_per_s"],
+        "kernel_ms_per_step": head["kernel_ms_per_step"],
+        "survivors": head["survivors"],
+        "retries": head["retries"],
+        "scan_states_per_item": head["scan_states_per_item"],
+        "roofline": roof,
+        "forms": {f: {k: v for k, v in r.items() if k not in ("E1", "wall", "pairs")} for f, r in results.items()},
+        "forms_same_E1": all(r["E1"] == head["E1"] for r in results.values()),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

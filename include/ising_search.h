@@ -83,7 +83,7 @@ typedef struct {
     double prep_ms;            /* device time of the per-state preparation, summed */
     double init_ms;            /* device time of local fields and seeding (init and reset), summed */
     double step_ms;            /* persistent mode: device time of the replayed step graphs, summed */
-    uint64_t reserved[1];
+    double split_field_err;    /* split form: max |F~ - F| of the initial states' bf16 hi+lo fields */
 } ising_stats_t;
 
 /*

@@ -74,7 +74,7 @@ class IsingStats(ctypes.Structure):
         ("prep_ms", ctypes.c_double),
         ("init_ms", ctypes.c_double),
         ("step_ms", ctypes.c_double),
-        ("reserved", ctypes.c_uint64 * 1),
+        ("split_field_err", ctypes.c_double),
     ]
 
     def as_dict(self):

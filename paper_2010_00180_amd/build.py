@@ -6,7 +6,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/api.hip", "csrc/k_init.hip", "csrc/k_step.hip"]
+SOURCES = ["csrc/api.hip", "csrc/k_init.hip", "csrc/k_step.hip", "csrc/k_split.hip"]
 OUT = os.path.join(HERE, "lib", "libising_search.so")
 
 HIPCC_FLAGS = [

@@ -61,6 +61,8 @@ struct ising_search {
     bool timing = false;
     hipEvent_t ev[6]{};
     double t_scan = 0, t_merge = 0, t_frontier = 0, t_prep = 0, t_init = 0, t_step = 0;
+    double split_err = 0;
+    double* d_maxerr = nullptr;
     uint64_t scan_launches = 0;
     // states per scan item, per instance (host copy of lay.scb)
     std::vector<int> sc_h;
@@ -172,7 +174,7 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     *out = nullptr;
     if (!cfg) return fail(ISING_ERR_INVALID_ARG, "cfg is NULL");
     if (cfg->M < 1 || cfg->M > 1024) return fail(ISING_ERR_INVALID_ARG, "M=%d outside [1, 1024]", cfg->M);
-    if (cfg->form != ISING_FORM_PLAIN)
+    if (cfg->form != ISING_FORM_PLAIN && cfg->form != ISING_FORM_SPLIT_BF16)
         return fail(ISING_ERR_INVALID_ARG, "form %d is not available in this build", cfg->form);
     if (cfg->reserved) return fail(ISING_ERR_INVALID_ARG, "reserved fields must be zero");
     if (cfg->states_per_item < 0 || cfg->states_per_item > 4096)
@@ -291,10 +293,24 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     ALLOC(lay.fbits, (size_t)n_inst * lay.fmax * lay.Wmax);
     ALLOC(lay.surv_count, S);
     ALLOC(lay.surv, S * lay.cap_surv);
-    ALLOC(lay.item_prefix, 2 * ((size_t)n_inst + 1));
+    ALLOC(lay.item_prefix, 3 * ((size_t)n_inst + 1));
     ALLOC(lay.ctr, 16);
     ALLOC(lay.flags, 8);
     ALLOC(hd->d_scb, n_inst);
+    float* dJ32 = nullptr;
+    uint16_t *dJhi = nullptr, *dJlo = nullptr;
+    double *dyb = nullptr, *debf = nullptr;
+    if (cfg->form == ISING_FORM_SPLIT_BF16) {
+        ALLOC(dJ32, (size_t)jtot);
+        ALLOC(dJhi, (size_t)jtot);
+        ALLOC(dJlo, (size_t)jtot);
+        ALLOC(dyb, n_inst);
+        ALLOC(debf, n_inst);
+        ALLOC(lay.Ft, S * lay.Npmax);
+        ALLOC(lay.A32, (size_t)n_inst * lay.fmax * lay.Npmax);
+        ALLOC(lay.RR32, (size_t)n_inst * lay.fmax * lay.Npmax);
+        ALLOC(hd->d_maxerr, 1);
+    }
     ALLOC(lay.nm_count, S);
     ALLOC(lay.nm_code, S * lay.M);
     ALLOC(lay.nm_pair, S * lay.M);
@@ -315,6 +331,12 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     lay.h = dh;
     lay.zkey = dz;
     lay.scb = hd->d_scb;
+    lay.form = cfg->form;
+    lay.J32 = dJ32;
+    lay.Jhi = dJhi;
+    lay.Jlo = dJlo;
+    lay.ybound = dyb;
+    lay.ebf = debf;
     hd->x0 = dx0;
     hd->timing = cfg->timing != 0;
     if (hd->timing) {
@@ -366,11 +388,69 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
         cp(dz, zk.data(), sizeof(uint64_t) * zk.size());
         cp(dx0, x0.data(), sizeof(uint64_t) * x0.size());
         cp(hd->d_scb, hd->sc_h.data(), sizeof(int) * n_inst);
+        std::vector<float> J32h;
+        std::vector<uint16_t> hih, loh;
+        std::vector<double> ybh, ebfh;
+        if (cfg->form == ISING_FORM_SPLIT_BF16) {
+            // fl32(4J), bf16 hi = RN(4J), lo = RN(4J - hi); per instance max |4J| and the
+            // bound on |F~ - F|: split residual |4J - hi - lo| <= 2^-15 |4J| (two roundings to 8
+            // significant bits, with margin for the float step), FP32 accumulation of 2N terms
+            // <= 2.1 N 2^-24 sum|terms|, and the final FP32 add.
+            auto bf16_rn = [](float f) -> uint16_t {
+                uint32_t u;
+                std::memcpy(&u, &f, 4);
+                u += 0x7FFFu + ((u >> 16) & 1u);
+                return (uint16_t)(u >> 16);
+            };
+            auto bf16_to_f = [](uint16_t b) -> float {
+                const uint32_t u = (uint32_t)b << 16;
+                float f;
+                std::memcpy(&f, &u, 4);
+                return f;
+            };
+            J32h.assign((size_t)jtot, 0.f);
+            hih.assign((size_t)jtot, 0);
+            loh.assign((size_t)jtot, 0);
+            ybh.assign(n_inst, 0.0);
+            ebfh.assign(n_inst, 0.0);
+            for (int b = 0; b < n_inst; ++b) {
+                const int n = N[b], np = hd->Npad[b];
+                double emax = 0.0;
+                for (int i = 0; i < n; ++i) {
+                    double R = 0.0;
+                    for (int j = 0; j < n; ++j) {
+                        const double x = 4.0 * J[b][(size_t)i * n + j];
+                        const size_t o = joff[b] + (size_t)i * np + j;
+                        J32h[o] = (float)x;
+                        const uint16_t hb = bf16_rn((float)x);
+                        hih[o] = hb;
+                        loh[o] = bf16_rn((float)(x - (double)bf16_to_f(hb)));
+                        ybh[b] = std::max(ybh[b], std::fabs(x));
+                        R += std::fabs(J[b][(size_t)i * n + j]);
+                    }
+                    const double e = (std::ldexp(1.0, -15) * 4.0 * 0.25 + 2.1 * n * std::ldexp(1.0, -24)) * R +
+                                     std::ldexp(1.0, -23) * (std::fabs(h[b][i]) + R);
+                    emax = std::max(emax, e);
+                }
+                ebfh[b] = emax;
+            }
+            cp(dJ32, J32h.data(), sizeof(float) * J32h.size());
+            cp(dJhi, hih.data(), sizeof(uint16_t) * hih.size());
+            cp(dJlo, loh.data(), sizeof(uint16_t) * loh.size());
+            cp(dyb, ybh.data(), sizeof(double) * n_inst);
+            cp(debf, ebfh.data(), sizeof(double) * n_inst);
+        }
         if (r2 == ISING_OK) {
             hipError_t e = hipMemsetAsync(lay.ctr, 0, 16 * sizeof(unsigned long long), sm);
             if (e == hipSuccess) e = hipMemsetAsync(lay.flags, 0, 8 * sizeof(int), sm);
             if (e == hipSuccess && hd->timing) e = hipEventRecord(hd->ev[0], sm);
             if (e == hipSuccess) e = launch_init_fields(lay, dx0, sm);
+            if (e == hipSuccess && lay.form == ISING_FORM_SPLIT_BF16) {
+                e = hipMemsetAsync(hd->d_maxerr, 0, sizeof(double), sm);
+                if (e == hipSuccess) e = launch_init_split(lay, dx0, hd->d_maxerr, sm);
+                if (e == hipSuccess) e = hipMemcpyAsync(&hd->split_err, hd->d_maxerr, sizeof(double),
+                                                        hipMemcpyDeviceToHost, sm);
+            }
             if (e == hipSuccess && hd->timing) e = hipEventRecord(hd->ev[1], sm);
             if (e == hipSuccess) e = hipStreamSynchronize(sm);
             if (e == hipSuccess && hd->timing) hd->t_init += elapsed_ms(hd->ev[0], hd->ev[1]);
@@ -593,6 +673,16 @@ extern "C" int ising_search_get_tuning(ising_search_t* s, int32_t* states_per_it
     return ISING_OK;
 }
 
+// clear the device maximum of |F~ - F| with a kernel (kept out of hipMemset so a
+// caller may capture the reset into a graph)
+__global__ void k_clear_double(double* p) { *p = 0.0; }
+
+static hipError_t launch_clear_err(ising_search* s)
+{
+    hipLaunchKernelGGL(k_clear_double, dim3(1), dim3(1), 0, s->stream, s->d_maxerr);
+    return hipGetLastError();
+}
+
 extern "C" int ising_search_reset(ising_search_t* s)
 {
     g_err.clear();
@@ -601,6 +691,12 @@ extern "C" int ising_search_reset(ising_search_t* s)
     hipError_t e = hipSuccess;
     if (s->timing) e = hipEventRecord(s->ev[0], s->stream);
     if (e == hipSuccess) e = launch_init_fields(s->lay, s->x0, s->stream);
+    if (e == hipSuccess && s->lay.form == ISING_FORM_SPLIT_BF16) {
+        e = launch_clear_err(s);
+        if (e == hipSuccess) e = launch_init_split(s->lay, s->x0, s->d_maxerr, s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&s->split_err, s->d_maxerr, sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    }
     if (e == hipSuccess && s->timing) e = hipEventRecord(s->ev[1], s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) {
@@ -791,6 +887,7 @@ extern "C" int ising_search_get_stats(ising_search_t* s, ising_stats_t* out)
     out->prep_ms = s->t_prep;
     out->init_ms = s->t_init;
     out->step_ms = s->t_step;
+    out->split_field_err = s->split_err;
     return ISING_OK;
 }
 

@@ -84,6 +84,16 @@ struct Layout {
     int* nm_code;            // [S][M] parent slot code
     uint32_t* nm_pair;       // [S][M] i | j << 16
     int* nm_slot;            // [S][M] slot taken by the new state
+    // split-bf16 form
+    int form;                // 0 plain, 1 split-bf16
+    const float* J32;        // per instance, fl32(4J) (same layout as J4)
+    const uint16_t* Jhi;     // per instance, bf16(4J)
+    const uint16_t* Jlo;     // per instance, bf16(4J - hi)
+    const double* ybound;    // [B] max |4J_ij|
+    const double* ebf;       // [B] bound on |F~ - F| of the bf16 hi+lo fields
+    float* Ft;               // [S][Npmax] F~ of the initial states (bf16 hi+lo GEMM, FP32 sums)
+    float* A32;              // [B][fmax][Npmax] fl32(a_i)
+    float* RR32;             // [B][fmax][Npmax] T - a_i + slack, rounded up to FP32
     // final merge output
     uint64_t* out_bits;      // [B][M][Wmax]
     double* out_E;           // [B][M]
@@ -92,7 +102,7 @@ struct Layout {
 
 enum { CTR_PAIRS = 0, CTR_SINGLES = 1, CTR_FRONTIER = 2, CTR_SURV = 3, CTR_RETRY = 4, CTR_STEPS = 5,
        CTR_FALLBACK = 6 };
-enum { FLAG_ACTIVE = 0, FLAG_OVERFLOW = 1, FLAG_STUCK = 2, FLAG_RETRY_MODE = 3 };
+enum { FLAG_ACTIVE = 0, FLAG_OVERFLOW = 1, FLAG_STUCK = 2, FLAG_RETRY_MODE = 3, FLAG_FIRST = 4 };
 
 __host__ __device__ inline int words_of(int N) { return (N + 63) >> 6; }
 __host__ __device__ inline int pad_of(int N) { return (N + TILE - 1) / TILE * TILE; }
@@ -113,6 +123,9 @@ hipError_t launch_prep(const Layout& lay, hipStream_t st);
 hipError_t launch_scan(const Layout& lay, int scan_grid, hipStream_t st);
 hipError_t launch_merge(const Layout& lay, hipStream_t st);
 hipError_t launch_fupdate(const Layout& lay, hipStream_t st);
+hipError_t launch_init_split(const Layout& lay, const uint64_t* d_x0, double* d_maxerr, hipStream_t st);
+hipError_t launch_prep32(const Layout& lay, hipStream_t st);
+hipError_t launch_scan32(const Layout& lay, int scan_grid, hipStream_t st);
 hipError_t launch_step_begin(const Layout& lay, bool retry_mode, hipStream_t st);
 hipError_t launch_final(const Layout& lay, hipStream_t st);
 

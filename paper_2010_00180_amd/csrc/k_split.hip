@@ -1,0 +1,433 @@
+// Split-bf16 form of the scan.  The local fields of the initial states are
+// also formed on the bf16 matrix cores with 4J = hi + lo split into two bf16
+// parts (the +-1 spins are exact in bf16) and FP32 accumulation; the pair
+// scan runs in FP32 against a threshold that carries a proven error slack; and
+// every pair it admits is re-scored in FP64 before it can enter, so the kept
+// sets are the same as in the FP64 form.  The FP64 steps are the re-scoring,
+// the singles, the pilot cut and the incremental field updates.
+#include "common.h"
+
+namespace qi {
+
+__device__ inline uint32_t lane_id32() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+__device__ inline uint32_t mbcnt64s(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ inline double spin_d(const uint64_t* x, int i)
+{
+    return ((x[i >> 6] >> (i & 63)) & 1ull) ? -1.0 : 1.0;
+}
+
+// ------------------------------------------------------------------ bf16 hi+lo GEMM
+// One wave: 16 sites x 16 searches of acc = (hi + lo) * S with
+// v_mfma_f32_16x16x32_bf16 (lane l: A rows l%16, k = 8*(l/16)..+7; B columns
+// l%16, same k; D rows 4*(l/16)+r, column l%16), then F~ = h + acc/4.
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(64) void k_init_split(Layout lay, const uint64_t* __restrict__ x0)
+{
+    const int b = blockIdx.x;
+    const int N = lay.N[b], Np = lay.Npad[b];
+    const int row0 = blockIdx.y * 16, col0 = blockIdx.z * 16;
+    if (row0 >= Np || col0 >= lay.L) return;
+    const int lane = threadIdx.x;
+    const uint16_t* hi = lay.Jhi + lay.joff[b];
+    const uint16_t* lo = lay.Jlo + lay.joff[b];
+    const int ai = row0 + (lane & 15);
+    const int kq = 8 * (lane >> 4);
+    const int lj = col0 + (lane & 15);
+    const bool colok = lj < lay.L;
+    const uint64_t* xs = x0 + (size_t)(b * lay.L + (colok ? lj : 0)) * lay.Wmax;
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < Np; k0 += 32) {
+        v8bf ah, al, bs;
+        const uint16_t* ph = hi + (size_t)ai * Np + k0 + kq;
+        const uint16_t* pl = lo + (size_t)ai * Np + k0 + kq;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            ah[e] = __builtin_bit_cast(__bf16, ph[e]);
+            al[e] = __builtin_bit_cast(__bf16, pl[e]);
+            const int k = k0 + kq + e;
+            uint16_t sb = 0;   // 0.0
+            if (colok && k < N) sb = ((xs[k >> 6] >> (k & 63)) & 1ull) ? (uint16_t)0xBF80 : (uint16_t)0x3F80;
+            bs[e] = __builtin_bit_cast(__bf16, sb);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bs, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bs, acc, 0, 0, 0);
+    }
+    if (!colok) return;
+    const int s = b * lay.L + lj;
+    const double* h = lay.h + (size_t)b * lay.Npmax;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int site = row0 + 4 * (lane >> 4) + r;
+        if (site < Np) lay.Ft[(size_t)s * lay.Npmax + site] = site < N ? (float)h[site] + 0.25f * acc[r] : 0.f;
+    }
+}
+
+// max |F~ - F| over the initial states, as an ordered bit pattern (non-negative doubles)
+__global__ __launch_bounds__(256) void k_split_err(Layout lay, unsigned long long* out)
+{
+    const int s = blockIdx.x;
+    const int b = s / lay.L;
+    const int N = lay.N[b];
+    const double* F = lay.F + (size_t)s * 2 * lay.M * lay.Npmax;   // slot 0
+    const float* Ft = lay.Ft + (size_t)s * lay.Npmax;
+    double m = 0.0;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) m = fmax(m, fabs((double)Ft[i] - F[i]));
+    atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+
+hipError_t launch_init_split(const Layout& lay, const uint64_t* d_x0, double* d_maxerr, hipStream_t st)
+{
+    dim3 grid(lay.B, (lay.Npmax + 15) / 16, (lay.L + 15) / 16);
+    hipLaunchKernelGGL(k_init_split, grid, dim3(64), 0, st, lay, d_x0);
+    hipLaunchKernelGGL(k_split_err, dim3(lay.S), dim3(256), 0, st, lay,
+                       reinterpret_cast<unsigned long long*>(d_maxerr));
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ k_prep32
+// As the FP64 preparation, and also: fl32(a_i) for the FP32 scan (in the
+// first step from F~ of the bf16 GEMM) and the FP32 threshold
+// RR_i = round_up(T - a_i + delta), with delta = 4u (max|4J| + max|a|)
+// (+ 2 max|F~ - F| in the first step), u = 2^-24.  Then every pair with
+// a_i + a_j + s_i s_j 4J_ij <= T also has fl32(fma(s_i, s_j fl32(4J_ij), fl32(a_j))) <= RR_i.
+__device__ inline double wave_max(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ inline int find_inst(const long long* prefix, int B, long long e)
+{
+    int lo = 0, hi = B;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= e) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_prep32(Layout lay, const long long* __restrict__ fr_prefix)
+{
+    const long long total = fr_prefix[lay.B];
+    const int wave = threadIdx.x >> 6;
+    const uint32_t lane = threadIdx.x & 63;
+    const int retry_mode = lay.flags[FLAG_RETRY_MODE];
+    const int first = lay.flags[FLAG_FIRST];
+    for (long long e = (long long)blockIdx.x * 4 + wave; e < total; e += (long long)gridDim.x * 4) {
+        const int b = find_inst(fr_prefix, lay.B, e);
+        const int f = (int)(e - fr_prefix[b]);
+        const size_t fe = (size_t)b * lay.fmax + f;
+        const int code = lay.fr_list[fe];
+        const int s = code / (2 * lay.M);
+        if (retry_mode && !lay.retry[s]) continue;
+        const size_t q = (size_t)code;
+        const int N = lay.N[b], Np = lay.Npad[b];
+        const double Em = lay.E[q];
+        const double c = lay.cut[s];
+        const double T = c - Em;
+        const uint64_t* x = lay.bits + q * lay.Wmax;
+        const double* F = lay.F + q * lay.Npmax;
+        const bool from_ft = first && (code % (2 * lay.M)) == 0;
+        const float* Ft = lay.Ft + (size_t)s * lay.Npmax;
+        double* A = lay.A + fe * lay.Npmax;
+        float* A32 = lay.A32 + fe * lay.Npmax;
+        float* RR = lay.RR32 + fe * lay.Npmax;
+        if (lane == 0) {
+            FrRec r;
+            r.T = T;
+            r.E = Em;
+            r.s = s;
+            r.code = code;
+            lay.rec[fe] = r;
+        }
+        if ((int)lane < lay.Wmax) lay.fbits[fe * lay.Wmax + lane] = x[lane];
+        if (retry_mode && lane == 0) {
+            atomicAdd(&lay.ctr[CTR_PAIRS], (unsigned long long)N * (N - 1) / 2);
+            atomicAdd(&lay.ctr[CTR_SINGLES], (unsigned long long)N);
+        }
+        double amax = 0.0;
+        for (int i0 = 0; i0 < Np; i0 += 64) {
+            const int i = i0 + lane;
+            double a = 0.0;
+            if (i < N) a = -2.0 * spin_d(x, i) * F[i];
+            amax = fmax(amax, fabs(a));
+            A[i] = a;
+            A32[i] = i < N ? (float)(from_ft ? -2.0 * spin_d(x, i) * (double)Ft[i] : a) : 0.f;
+            const double Ec = Em + a;
+            const bool hit = i < N && Ec <= c;
+            const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
+            if (m) {
+                int base = 0;
+                if (lane == 0) base = atomicAdd(&lay.surv_count[s], __builtin_popcountll(m));
+                base = __shfl(base, 0, 64);
+                if (hit) {
+                    const int pos = base + (int)mbcnt64s(m);
+                    if (pos < lay.cap_surv) {
+                        Surv r;
+                        r.E = Ec;
+                        r.code = (uint32_t)code;
+                        r.pair = (uint32_t)i | (SINGLE << 16);
+                        lay.surv[(size_t)s * lay.cap_surv + pos] = r;
+                    }
+                }
+            }
+        }
+        amax = wave_max(amax);
+        const double u = 5.9604644775390625e-08;   // 2^-24
+        const double delta = 4.0 * u * (lay.ybound[b] + amax) + (from_ft ? 2.0 * lay.ebf[b] : 0.0);
+        for (int i0 = 0; i0 < Np; i0 += 64) {
+            const int i = i0 + lane;
+            RR[i] = i < N ? __double2float_ru(T - A[i] + delta) : -INFINITY;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ k_scan32
+// One wave per (instance, chunk of states, 64 x 64 tile with row block <= column
+// block).  Lane = row i; registers hold y_j = s_j fl32(4J_ij) for 64 columns
+// (column signs re-applied per group of 8 when they change between states);
+// per pair one v_fma_f32 and one v_min_f32, one compare per group against
+// RR_i.  Admitted pairs are re-scored in FP64 (a_i + a_j + s_i s_j 4J_ij
+// against T, all exact) and only then recorded; the rest are counted.
+constexpr int T32 = 64;
+
+__device__ inline void flush32(const Layout& lay, Surv* stage, int& n, int s)
+{
+    if (n == 0) return;
+    __syncthreads();
+    int base = 0;
+    if (lane_id32() == 0) base = atomicAdd(&lay.surv_count[s], n);
+    base = __shfl(base, 0, 64);
+    for (int k = (int)lane_id32(); k < n; k += 64) {
+        const int pos = base + k;
+        if (pos < lay.cap_surv) lay.surv[(size_t)s * lay.cap_surv + pos] = stage[k];
+    }
+    __syncthreads();
+    n = 0;
+}
+
+__device__ inline long long tiles64(int N)
+{
+    const long long nb = (N + TILE - 1) / TILE;
+    return nb * (nb + 1) / 2;
+}
+
+__global__ __launch_bounds__(64) void k_scan32(Layout lay, const float* __restrict__ J32,
+                                               const double* __restrict__ J4,
+                                               const float* __restrict__ A32,
+                                               const float* __restrict__ RR32,
+                                               const double* __restrict__ A64,
+                                               const FrRec* __restrict__ recs,
+                                               const uint64_t* __restrict__ fbits,
+                                               const long long* __restrict__ iprefix)
+{
+    __shared__ Surv stage[STAGE];
+    __shared__ float abuf[2][T32];
+    __shared__ double sT[64], sE[64];
+    __shared__ int sS[64], sCode[64];
+    __shared__ uint64_t sWi[64], sWj[64];
+    const uint32_t lane = lane_id32();
+    const long long total = iprefix[lay.B];
+    const int retry_mode = lay.flags[FLAG_RETRY_MODE];
+    const int Wm = lay.Wmax;
+    const int Npm = lay.Npmax;
+    const int nx = gridDim.x >= 8 ? 8 : 1;
+    const int xcd = blockIdx.x % nx;
+    const long long seg0 = total * xcd / nx, seg1 = total * (xcd + 1) / nx;
+    const long long stride = gridDim.x / nx;
+    unsigned long long rejected = 0;
+    for (long long item = seg0 + blockIdx.x / nx; item < seg1; item += stride) {
+        const int b = __builtin_amdgcn_readfirstlane(find_inst(iprefix, lay.B, item));
+        const long long r = item - iprefix[b];
+        const int N = lay.N[b], Np = lay.Npad[b];
+        const int nb = Np / TILE;
+        const long long T = tiles64(N);
+        const int c = (int)(r / T);
+        int t = (int)(r % T);
+        int bi = 0;
+        while (t >= nb - bi) { t -= nb - bi; ++bi; }
+        bi = __builtin_amdgcn_readfirstlane(bi);
+        const int bj = __builtin_amdgcn_readfirstlane(bi + t);
+        const int P = lay.fr_count[b];
+        const int sc = lay.scb[b];
+        const int f0 = c * sc;
+        const int f1 = min(f0 + sc, P);
+        const int row = bi * TILE + (int)lane;
+        const int col0 = bj * T32;
+        const float* Jt = J32 + lay.joff[b];
+        uint32_t Jb[T32];
+#pragma unroll
+        for (int j = 0; j < T32; ++j) {
+            const int col = col0 + j;
+            const float v = Jt[(size_t)col * Np + row];
+            const bool ok = row < N && col < N && col > row;
+            Jb[j] = ok ? __float_as_uint(v) : 0x7FC00000u;
+        }
+        uint64_t prev_wj = 0;
+        int nstage = 0, sstage = -1;
+        for (int g0 = f0; g0 < f1; g0 += 64) {
+            const int ns = min(64, f1 - g0);
+            const size_t fe0 = (size_t)b * lay.fmax + g0;
+            if ((int)lane < ns) {
+                const FrRec rc = recs[fe0 + lane];
+                sT[lane] = rc.T;
+                sE[lane] = rc.E;
+                sS[lane] = rc.s;
+                sCode[lane] = rc.code;
+                const uint64_t* fw = fbits + (fe0 + lane) * Wm;
+                sWi[lane] = fw[bi];
+                sWj[lane] = fw[bj];
+            }
+            const float* A0 = A32 + fe0 * Npm;
+            const float* R0 = RR32 + fe0 * Npm;
+            float nrr = R0[row];
+            float naj = A0[col0 + lane];
+            int cur = 0;
+            abuf[0][lane] = naj;
+            __syncthreads();
+            for (int k = 0; k < ns; ++k) {
+                const float rrt = nrr;
+                if (k + 1 < ns) {
+                    nrr = R0[(size_t)(k + 1) * Npm + row];
+                    naj = A0[(size_t)(k + 1) * Npm + col0 + lane];
+                }
+                const int s = __builtin_amdgcn_readfirstlane(sS[k]);
+                const bool skip = retry_mode && !lay.retry[s];
+                if (!skip) {
+                    if (s != sstage) {
+                        flush32(lay, stage, nstage, sstage);
+                        sstage = s;
+                    }
+                    const uint64_t wi = sWi[k];
+                    const float si = ((wi >> lane) & 1ull) ? -1.f : 1.f;
+                    const uint32_t wlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)sWj[k]);
+                    const uint32_t whi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(sWj[k] >> 32));
+                    const uint64_t wj = ((uint64_t)whi << 32) | wlo;
+                    const uint64_t dw = wj ^ prev_wj;
+                    prev_wj = wj;
+                    const float* aj = abuf[cur];
+#pragma unroll
+                    for (int g = 0; g < T32; g += 8) {
+                        if ((dw >> g) & 0xFFull) {
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) Jb[g + u] ^= (uint32_t)((dw >> (g + u)) & 1ull) << 31;
+                        }
+                        float a8[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) a8[u] = aj[g + u];
+                        float mn0 = INFINITY, mn1 = INFINITY;
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const float x = fmaf(si, __uint_as_float(Jb[g + u]), a8[u]);
+                            if (u & 1) mn1 = fminf(mn1, x);
+                            else mn0 = fminf(mn0, x);
+                        }
+                        if (__builtin_amdgcn_ballot_w64(fminf(mn0, mn1) <= rrt)) {
+                            // admitted pairs: exact FP64 re-score, then record
+                            const size_t fe = (size_t)b * lay.fmax + g0 + k;
+                            const double Tm = sT[k];
+                            const double* Arow = A64 + fe * Npm;
+                            const double ai = row < N ? Arow[row] : 0.0;
+                            const double sid = (double)si;
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                const float xt = fmaf(si, __uint_as_float(Jb[g + u]), a8[u]);
+                                const bool adm = xt <= rrt;
+                                bool keep = false;
+                                double x = 0.0;
+                                if (adm) {
+                                    const int col = col0 + g + u;
+                                    const double sj = ((wj >> (g + u)) & 1ull) ? -1.0 : 1.0;
+                                    x = Arow[col] + sid * sj * J4[lay.joff[b] + (size_t)row * Np + col];
+                                    keep = ai + x <= Tm;
+                                    if (!keep) ++rejected;
+                                }
+                                const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
+                                if (m) {
+                                    if (nstage > STAGE - 64) flush32(lay, stage, nstage, s);
+                                    if (keep) {
+                                        uint32_t rowv = (uint32_t)row;
+                                        asm volatile("" : "+v"(rowv));
+                                        Surv rec;
+                                        rec.E = (sE[k] + ai) + x;
+                                        rec.code = (uint32_t)sCode[k];
+                                        rec.pair = rowv | ((uint32_t)(col0 + g + u) << 16);
+                                        stage[nstage + (int)mbcnt64s(m)] = rec;
+                                    }
+                                    nstage += __builtin_popcountll(m);
+                                }
+                            }
+                        }
+                    }
+                }
+                if (k + 1 < ns) abuf[cur ^ 1][lane] = naj;
+                cur ^= 1;
+                __syncthreads();
+            }
+        }
+        flush32(lay, stage, nstage, sstage);
+        __syncthreads();
+    }
+    // count re-scored pairs that the exact test rejected
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)rejected, off, 64);
+        const uint32_t hi = __shfl_xor((uint32_t)(rejected >> 32), off, 64);
+        rejected += ((uint64_t)hi << 32) | lo;
+    }
+    if (lane == 0 && rejected) atomicAdd(&lay.ctr[CTR_FALLBACK], rejected);
+}
+
+// ------------------------------------------------------------------ k_plan32
+// Work prefix over instances for the 64 x 64 tiles of the FP32 scan.
+__global__ __launch_bounds__(1024) void k_plan32(Layout lay, long long* __restrict__ iprefix)
+{
+    __shared__ long long part[1024];
+    const int t = threadIdx.x;
+    const int per = (lay.B + 1023) / 1024;
+    const int b0 = t * per;
+    long long items = 0;
+    for (int b = b0; b < b0 + per && b < lay.B; ++b) {
+        const long long P = lay.fr_count[b];
+        items += (P + lay.scb[b] - 1) / lay.scb[b] * tiles64(lay.N[b]);
+    }
+    part[t] = items;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const long long a = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += a;
+        __syncthreads();
+    }
+    long long run = part[t] - items;
+    for (int b = b0; b < b0 + per && b < lay.B; ++b) {
+        iprefix[b] = run;
+        run += (lay.fr_count[b] + lay.scb[b] - 1) / lay.scb[b] * tiles64(lay.N[b]);
+    }
+    if (t == 1023) iprefix[lay.B] = part[1023];
+}
+
+hipError_t launch_prep32(const Layout& lay, hipStream_t st)
+{
+    const long long* fr_prefix = lay.item_prefix + (lay.B + 1);
+    hipLaunchKernelGGL(k_prep32, dim3(4096), dim3(256), 0, st, lay, fr_prefix);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan32(const Layout& lay, int scan_grid, hipStream_t st)
+{
+    long long* iprefix = lay.item_prefix + 2 * (lay.B + 1);
+    hipLaunchKernelGGL(k_plan32, dim3(1), dim3(1024), 0, st, lay, iprefix);
+    hipLaunchKernelGGL(k_scan32, dim3(scan_grid), dim3(64), 0, st, lay, lay.J32, lay.J4, (const float*)lay.A32,
+                       (const float*)lay.RR32, (const double*)lay.A, (const FrRec*)lay.rec,
+                       (const uint64_t*)lay.fbits, (const long long*)iprefix);
+    return hipGetLastError();
+}
+
+}  // namespace qi

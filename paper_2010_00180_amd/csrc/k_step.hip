@@ -836,6 +836,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int b = s / lay.L;
     const int M = lay.M;
     const int retry_mode = lay.flags[FLAG_RETRY_MODE];
+    if (blockIdx.x == 0 && threadIdx.x == 0) lay.flags[FLAG_FIRST] = 0;   // the first step has been scanned
     if (!lay.active[s]) return;
     if (retry_mode && !lay.retry[s]) return;
     const int nk = lay.nkept[s];
@@ -1125,6 +1126,7 @@ hipError_t launch_clear_survivors(const Layout& lay, hipStream_t st)
 
 hipError_t launch_prep(const Layout& lay, hipStream_t st)
 {
+    if (lay.form == 1) return launch_prep32(lay, st);
     const long long* fr_prefix = lay.item_prefix + (lay.B + 1);
     hipLaunchKernelGGL(k_prep, dim3(4096), dim3(256), 0, st, lay, fr_prefix);
     return hipGetLastError();
@@ -1132,6 +1134,7 @@ hipError_t launch_prep(const Layout& lay, hipStream_t st)
 
 hipError_t launch_scan(const Layout& lay, int scan_grid, hipStream_t st)
 {
+    if (lay.form == 1) return launch_scan32(lay, scan_grid, st);
     hipLaunchKernelGGL(k_scan, dim3(scan_grid), dim3(64), 0, st, lay, lay.J4, (const double*)lay.A,
                        (const FrRec*)lay.rec, (const uint64_t*)lay.fbits);
     return hipGetLastError();

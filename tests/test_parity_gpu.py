@@ -277,3 +277,41 @@ def test_uneven_batch_persistent_sampled():
         for k in rng.choice(len(gE), 3, replace=False):
             assert oracle.energy(inst.J, inst.h, gb[k]) == gE[k]
     s.destroy()
+
+
+# ---------------------------------------------------------------- split-bf16 form
+def ebf_bound(inst):
+    """The bound on |F~ - F| that the library uses for the bf16 hi+lo fields."""
+    R = np.abs(inst.J).sum(axis=1)
+    n = inst.N
+    return float(np.max((2.0 ** -15 + 2.1 * n * 2.0 ** -24) * R + 2.0 ** -23 * (np.abs(inst.h) + R)))
+
+
+@pytest.mark.parametrize("N,M,L,dist", [(24, 8, 4, "sk"), (65, 40, 2, "sk"), (130, 60, 2, "sk"),
+                                        (200, 120, 1, "sk"), (70, 50, 2, "pmj"), (90, 30, 2, "sk_h0")])
+def test_split_form_stepwise(N, M, L, dist):
+    w = wl.custom([N], L=L, M=M, config=21, dist=dist, seed_offset=N + M)
+    st = stepwise_parity(w, f"split N={N} {dist}", form=binding.FORM_SPLIT_BF16)
+    assert 0.0 <= st["split_field_err"] <= ebf_bound(w.instances[0])
+
+
+def test_split_form_matches_plain_full_c2():
+    w = wl.c2_n200()
+    note("[split c2] plain vs split")
+    a = binding.IsingSearch.from_workload(w)
+    s = binding.IsingSearch.from_workload(w, form=binding.FORM_SPLIT_BF16)
+    ia, _ = a.run()
+    is_, _ = s.run()
+    assert ia == is_
+    for sid in range(0, w.n_searches, 7):
+        assert_same_set(s.get_search(sid), a.get_search(sid), f"split c2 search {sid}")
+    for b in range(len(w.instances)):
+        ab, aE = a.get_states(b)
+        sb, sE = s.get_states(b)
+        assert np.array_equal(ab, sb) and np.array_equal(aE, sE)
+    st = s.stats()
+    note(f"[split c2] field err {st['split_field_err']:.3e} bound {max(ebf_bound(i) for i in w.instances):.3e} "
+         f"re-scored and rejected {st['fallbacks']}")
+    assert 0.0 < st["split_field_err"] <= max(ebf_bound(i) for i in w.instances)
+    a.destroy()
+    s.destroy()
