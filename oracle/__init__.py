@@ -54,6 +54,10 @@ def load(path: str):
                            _u64p, _dp, _ip]
     L.qo_brute_lowest.restype = ctypes.c_int
     L.qo_brute_lowest.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int, _u64p, _dp, _ip]
+    L.qo_step_proposed.restype = ctypes.c_int
+    L.qo_step_proposed.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int, ctypes.c_int, _u64p, _dp,
+                                   ctypes.c_int, _ip, _ip, ctypes.POINTER(ctypes.c_uint32),
+                                   _u64p, _dp, _u8p, _ip]
     L.qo_num_threads.restype = ctypes.c_int
     L.qo_num_threads.argtypes = []
     return L
@@ -134,6 +138,35 @@ def step(J, h, M, bits, E=None, front=None, literal=False):
                       ctypes.byref(nn))
     if r < 0:
         raise MemoryError("qo_step failed")
+    k = nn.value
+    return ob[:k], oE[:k], of[:k], r
+
+
+def step_proposed(J, h, M, bits, E, parents, pair_lists):
+    """One learned-form step: S_t plus, for each parent index, its N single
+    flips and only the listed pair flips (codes i | j << 16).  Returns
+    (bits, E, front, n_new)."""
+    J, h = _prep(J, h)
+    N = len(h)
+    W = _W(N)
+    bits = np.ascontiguousarray(bits, dtype=np.uint64).reshape(-1, W)
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    par = np.ascontiguousarray(parents, dtype=np.int32)
+    npairs = np.ascontiguousarray([len(p) for p in pair_lists], dtype=np.int32)
+    flat = np.ascontiguousarray(np.concatenate([np.asarray(p, np.uint32) for p in pair_lists])
+                                if len(pair_lists) else np.zeros(0, np.uint32), dtype=np.uint32)
+    if flat.size == 0:
+        flat = np.zeros(1, np.uint32)
+    ob = np.zeros((M, W), dtype=np.uint64)
+    oE = np.zeros(M, dtype=np.float64)
+    of = np.zeros(M, dtype=np.uint8)
+    nn = ctypes.c_int(0)
+    r = lib().qo_step_proposed(N, _d(J), _d(h), M, bits.shape[0], _u64(bits), _d(E), len(par),
+                               par.ctypes.data_as(_ip), npairs.ctypes.data_as(_ip),
+                               flat.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                               _u64(ob), _d(oE), of.ctypes.data_as(_u8p), ctypes.byref(nn))
+    if r < 0:
+        raise ValueError("qo_step_proposed failed (allocation or a malformed pair)")
     k = nn.value
     return ob[:k], oE[:k], of[:k], r
 

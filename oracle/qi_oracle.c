@@ -254,6 +254,67 @@ int qo_step(int N, const double *J, const double *h, int M, int literal,
  * including the last one that found no new state.  Returns 1 if stable, 0 if
  * the cap was reached first, -1 on failure.
  */
+/*
+ * One step of the learned-proposal form (not in the paper; the proposal ranks
+ * pair flips and only the ranked-in pairs are offered).  The candidates are
+ * S_t itself, the N single flips of every expanded parent, and for parent p
+ * only the pair flips listed for it: pairs[off_p .. off_p + npairs[p]), each
+ * encoded i | j << 16 with i < j.  parent[p] indexes S_t.  The kept set is the
+ * M lowest distinct candidates, as in qo_step.  Returns the number of new
+ * states, or -1 on allocation failure or a malformed pair.
+ */
+int qo_step_proposed(int N, const double *J, const double *h, int M,
+                     int n_in, const uint64_t *in_bits, const double *in_E,
+                     int n_par, const int *parent, const int *npairs, const uint32_t *pairs,
+                     uint64_t *out_bits, double *out_E, uint8_t *out_front, int *n_out)
+{
+    int W = words_of(N);
+    klist R;
+    if (klist_init(&R, M, W) != 0) return -1;
+    uint64_t *child = (uint64_t *)malloc(sizeof(uint64_t) * W);
+    if (!child) { klist_free(&R); return -1; }
+    for (int k = 0; k < n_in; ++k)
+        klist_offer(&R, in_E[k], in_bits + (size_t)k * W, 0);
+    size_t off = 0;
+    int bad = 0;
+    for (int p = 0; p < n_par && !bad; ++p) {
+        const uint64_t *x = in_bits + (size_t)parent[p] * W;
+        double Ex = in_E[parent[p]];
+        int sites[2];
+        for (int i = 0; i < N; ++i) {
+            memcpy(child, x, sizeof(uint64_t) * W);
+            child[i >> 6] ^= (uint64_t)1 << (i & 63);
+            sites[0] = i;
+            klist_offer(&R, Ex + qo_flip_change(N, J, h, x, 1, sites), child, 1);
+        }
+        for (int q = 0; q < npairs[p]; ++q) {
+            uint32_t code = pairs[off + q];
+            int i = (int)(code & 0xFFFFu), j = (int)(code >> 16);
+            if (!(0 <= i && i < j && j < N)) { bad = 1; break; }
+            memcpy(child, x, sizeof(uint64_t) * W);
+            child[i >> 6] ^= (uint64_t)1 << (i & 63);
+            child[j >> 6] ^= (uint64_t)1 << (j & 63);
+            sites[0] = i; sites[1] = j;
+            klist_offer(&R, Ex + qo_flip_change(N, J, h, x, 2, sites), child, 1);
+        }
+        off += (size_t)npairs[p];
+    }
+    int n_new = -1;
+    if (!bad) {
+        n_new = 0;
+        for (int k = 0; k < R.n; ++k) {
+            out_E[k] = R.E[k];
+            out_front[k] = R.flag[k];
+            memcpy(out_bits + (size_t)k * W, R.bits + (size_t)k * W, sizeof(uint64_t) * W);
+            n_new += R.flag[k];
+        }
+        *n_out = R.n;
+    }
+    free(child);
+    klist_free(&R);
+    return n_new;
+}
+
 int qo_search(int N, const double *J, const double *h, int M, int max_iters, int literal,
               const uint64_t *x0, uint64_t *out_bits, double *out_E, int *n_out, int *iters)
 {
