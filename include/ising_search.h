@@ -53,8 +53,14 @@ typedef enum {
     ISING_FORM_PLAIN = 0,      /* FP64 local fields, FP64 energy-change scan */
     ISING_FORM_SPLIT_BF16 = 1, /* initial local fields from J = hi + lo (bf16) on MFMA with FP32
                                   accumulation, FP32 scan with a proven error slack, FP64 re-score */
-    ISING_FORM_LEARNED = 2     /* pair flips ranked by a small MLP; only the top K are scored exactly */
+    ISING_FORM_LEARNED = 2     /* pair flips ranked by a small network; only the best K per state are
+                                  evaluated exactly (see the learned-form section below) */
 } ising_form_t;
+
+enum {
+    ISING_FLAG_RECORD_PROPOSALS = 1   /* learned form: keep each step's proposals for
+                                         ising_search_get_proposals (B*L*M*K*4 bytes) */
+};
 
 typedef struct {
     int32_t M;                 /* states kept per search, >= 1 */
@@ -65,7 +71,7 @@ typedef struct {
     int32_t persistent;        /* 1 = capture the kernels of one step into a hipGraph once and replay
                                   it for every step (an internal stream is used when none is given) */
     int32_t timing;            /* 1 = time every kernel family with hipEvents on the handle's stream */
-    int32_t reserved;          /* must be zero */
+    int32_t flags;             /* ISING_FLAG_* bits; other bits must be zero */
 } ising_config_t;
 
 typedef struct {
@@ -84,6 +90,10 @@ typedef struct {
     double init_ms;            /* device time of local fields and seeding (init and reset), summed */
     double step_ms;            /* persistent mode: device time of the replayed step graphs, summed */
     double split_field_err;    /* split form: max |F~ - F| of the initial states' bf16 hi+lo fields */
+    uint64_t scored_pairs;     /* learned form: pair flips scored by the ranking kernel */
+    uint64_t ranked_states;    /* learned form: states expanded with ranked pairs */
+    uint64_t trace_samples;    /* samples offered to the trace buffer since ising_search_set_trace */
+    double learn_ms;           /* learned form: device time of the ranking kernel, summed */
 } ising_stats_t;
 
 /*
@@ -178,6 +188,105 @@ int ising_search_autotune(ising_search_t *s, int32_t *n_active);
 
 /* The states per scan item in use for each instance (n_inst values). */
 int ising_search_get_tuning(ising_search_t *s, int32_t *states_per_item);
+
+/*
+ * ---------------------------------------------------------------- learned form
+ * Not part of the paper (whose own lever for a cheaper step is a smaller
+ * H1): a small network ranks the pair flips of each new state so that only
+ * K = topk_factor * N of them (all of them if fewer) are evaluated exactly.
+ * Features of the pair flip (i, j) of state x with local fields F = h + J s:
+ *   (s_i F_i, s_j F_j, sqrt(N) J_ij, s_i s_j)
+ * Network: 4 -> 64 -> 64 -> 1 with relu, evaluated on the bf16 matrix cores
+ * with FP32 accumulation (weights, features and hidden activations rounded to
+ * bf16, nearest even).  Parameter vector (ising_mlp_num_params() = 4545 FP32
+ * values): W1[64][4], b1[64], W2[64][64], b2[64], w3[64], b3 (row-major).
+ * A step of a search ranks the pairs of the states that entered in the last
+ * step (their single flips are all offered) and keeps the M lowest distinct
+ * states of the kept set and the offered children, exactly as the plain
+ * step would for that candidate set.  When such a step brings nothing new,
+ * the next step evaluates every pair flip of every kept state whose pairs
+ * were not all evaluated before; if that finds nothing either, the set is a
+ * fixed point of the exact step and the search stops.  stats.fallbacks counts
+ * these full steps.
+ */
+
+/* Scorers of the learned form. */
+enum {
+    ISING_SCORER_NETWORK = 0,   /* the network with the given parameters */
+    ISING_SCORER_FIELDS = 1,    /* s_i F_i + s_j F_j (the energy change without the coupling term) */
+    ISING_SCORER_UNIFORM = 2    /* a hash of (seed, state, pair): a uniformly random ranking */
+};
+
+/*
+ * Choose the scorer (required before the first step of a learned-form
+ * handle).  params: host array of 4545 finite FP32 values for the network
+ * scorer (copied), ignored otherwise; seed salts the uniform scorer.
+ * Errors: INVALID_ARG (not the learned form, unknown scorer, NULL or
+ * non-finite parameters).
+ */
+int ising_search_set_scorer(ising_search_t *s, int32_t scorer, const float *params, uint64_t seed);
+
+/*
+ * Capture training samples during later steps (any form).  For a fraction
+ * `rate` of the states each step expands (chosen by a hash of seed, step and
+ * state), one sample per pair flip of that state that entered the kept set
+ * (label 1) and `pairs_per_state` uniformly drawn pairs i < j, labelled 1 iff
+ * the child is a new member of the next kept set.  Sample k is written to
+ * feat[4k .. 4k+3] (the four features above, FP32) and label[k] (0 or 1) while
+ * k < capacity.  feat and label are device pointers owned by the caller and
+ * must stay valid while tracing; NULL, NULL, 0 stops tracing.  The count of
+ * samples offered (possibly above capacity) is reset here and read with
+ * ising_search_get_trace_count.
+ */
+int ising_search_set_trace(ising_search_t *s, float *feat, uint8_t *label, int64_t capacity,
+                           int32_t pairs_per_state, float rate, uint64_t seed);
+int ising_search_get_trace_count(ising_search_t *s, int64_t *count);
+
+/*
+ * Proposals of the last step of one search (handles created with
+ * ISING_FLAG_RECORD_PROPOSALS).  For each ranked parent p < *n_parents:
+ * its words in parent_bits[p*W .. p*W+W), its n_pairs[p] proposed pairs
+ * (i | j << 16, i < j, in no particular order) in pairs[p*K .. p*K+n_pairs[p])
+ * with K = ising_search_topk(s).  *mode is 0 when the step ranked pairs and 1
+ * when it enumerated all pairs (then there are no ranked parents).  Call it
+ * before the next step.  Errors: BAD_STATE (not recording), CAPACITY (more
+ * than max_parents parents).
+ */
+int ising_search_get_proposals(ising_search_t *s, int32_t search, uint64_t *parent_bits, uint32_t *pairs,
+                               int32_t *n_pairs, int32_t max_parents, int32_t *n_parents, int32_t *mode);
+
+/* K of the largest instance (the row stride of get_proposals), or -1 for a bad handle. */
+int32_t ising_search_topk(ising_search_t *s);
+
+/*
+ * Training of the network on the device, in FP32.  All array arguments are
+ * device pointers owned by the caller; work is queued on `stream` (a
+ * hipStream_t, NULL = default stream) and these calls do not synchronise.
+ * Loss: the class-weighted binary cross-entropy with logits averaged over the
+ * samples, L = mean(pos_weight * y * softplus(-z) + (1 - y) * softplus(z)).
+ * feat: n x 4 FP32 features; label: n bytes (nonzero = 1).
+ */
+int32_t ising_mlp_num_params(void);
+/* Bytes of the workspace that ising_mlp_loss_grad and ising_mlp_train need. */
+int64_t ising_mlp_workspace_bytes(void);
+/* logits[k] of sample k in FP32 (no rounding to bf16). */
+int ising_mlp_forward(const float *params, const float *feat, int64_t n, float *logits, void *stream);
+/* grad (4545) = dL/dparams over all n samples, and *loss (device, may be NULL). */
+int ising_mlp_loss_grad(const float *params, const float *feat, const uint8_t *label, int64_t n,
+                        float pos_weight, float *grad, float *loss, void *workspace,
+                        int64_t workspace_bytes, void *stream);
+/* One Adam step (t >= 1): m, v and params updated in place (Kingma and Ba, Alg. 1). */
+int ising_mlp_adam(float *params, float *m, float *v, const float *grad, int32_t t, float lr,
+                   float beta1, float beta2, float eps, void *stream);
+/*
+ * `steps` Adam steps (beta1 = 0.9, beta2 = 0.999, eps = 1e-8, step numbers
+ * t0+1 ..), each on a minibatch of `batch` samples drawn uniformly with
+ * replacement by a hash of (seed, step, k).  *loss (device, may be NULL)
+ * receives the last minibatch's loss.
+ */
+int ising_mlp_train(float *params, float *m, float *v, const float *feat, const uint8_t *label, int64_t n,
+                    int32_t batch, int32_t steps, int32_t t0, float lr, float pos_weight, uint64_t seed,
+                    float *loss, void *workspace, int64_t workspace_bytes, void *stream);
 
 /* Frees all device memory of the handle.  NULL is accepted. */
 void ising_search_destroy(ising_search_t *s);

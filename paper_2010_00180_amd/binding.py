@@ -28,6 +28,11 @@ ISING_ERR_CAPACITY = -6
 FORM_PLAIN = 0
 FORM_SPLIT_BF16 = 1
 FORM_LEARNED = 2
+FLAG_RECORD_PROPOSALS = 1
+SCORER_NETWORK = 0
+SCORER_FIELDS = 1
+SCORER_UNIFORM = 2
+MLP_NPARAM = 4545
 
 EXPORTED = (
     "ising_search_init",
@@ -42,6 +47,17 @@ EXPORTED = (
     "ising_search_get_tuning",
     "ising_search_destroy",
     "ising_search_last_error",
+    "ising_search_set_scorer",
+    "ising_search_set_trace",
+    "ising_search_get_trace_count",
+    "ising_search_get_proposals",
+    "ising_search_topk",
+    "ising_mlp_num_params",
+    "ising_mlp_workspace_bytes",
+    "ising_mlp_forward",
+    "ising_mlp_loss_grad",
+    "ising_mlp_adam",
+    "ising_mlp_train",
 )
 
 
@@ -54,7 +70,7 @@ class IsingConfig(ctypes.Structure):
         ("topk_factor", ctypes.c_int32),
         ("persistent", ctypes.c_int32),
         ("timing", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
     ]
 
 
@@ -75,10 +91,14 @@ class IsingStats(ctypes.Structure):
         ("init_ms", ctypes.c_double),
         ("step_ms", ctypes.c_double),
         ("split_field_err", ctypes.c_double),
+        ("scored_pairs", ctypes.c_uint64),
+        ("ranked_states", ctypes.c_uint64),
+        ("trace_samples", ctypes.c_uint64),
+        ("learn_ms", ctypes.c_double),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class IsingError(RuntimeError):
@@ -125,6 +145,29 @@ def load(path: str = LIB_PATH):
     L.ising_search_destroy.argtypes = [vp]
     L.ising_search_last_error.restype = ctypes.c_char_p
     L.ising_search_last_error.argtypes = []
+    i32, i64, u64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_float
+    L.ising_search_set_scorer.restype = ctypes.c_int
+    L.ising_search_set_scorer.argtypes = [vp, i32, vp, u64]
+    L.ising_search_set_trace.restype = ctypes.c_int
+    L.ising_search_set_trace.argtypes = [vp, vp, vp, i64, i32, f32, u64]
+    L.ising_search_get_trace_count.restype = ctypes.c_int
+    L.ising_search_get_trace_count.argtypes = [vp, ctypes.POINTER(i64)]
+    L.ising_search_get_proposals.restype = ctypes.c_int
+    L.ising_search_get_proposals.argtypes = [vp, i32, vp, vp, vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.ising_search_topk.restype = i32
+    L.ising_search_topk.argtypes = [vp]
+    L.ising_mlp_num_params.restype = i32
+    L.ising_mlp_num_params.argtypes = []
+    L.ising_mlp_workspace_bytes.restype = i64
+    L.ising_mlp_workspace_bytes.argtypes = []
+    L.ising_mlp_forward.restype = ctypes.c_int
+    L.ising_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+    L.ising_mlp_loss_grad.restype = ctypes.c_int
+    L.ising_mlp_loss_grad.argtypes = [vp, vp, vp, i64, f32, vp, vp, vp, i64, vp]
+    L.ising_mlp_adam.restype = ctypes.c_int
+    L.ising_mlp_adam.argtypes = [vp, vp, vp, vp, i32, f32, f32, f32, f32, vp]
+    L.ising_mlp_train.restype = ctypes.c_int
+    L.ising_mlp_train.argtypes = [vp, vp, vp, vp, vp, i64, i32, i32, i32, f32, f32, u64, vp, vp, i64, vp]
     _lib = L
     return L
 
@@ -159,7 +202,7 @@ class IsingSearch:
 
     def __init__(self, Ns: Sequence[int], Js, hs, init_bits, M: int, form: int = FORM_PLAIN,
                  max_iters: int = 0, states_per_item: int = 0, topk_factor: int = 8,
-                 persistent: int = 0, timing: int = 0, stream: Optional[int] = None):
+                 persistent: int = 0, timing: int = 0, stream: Optional[int] = None, flags: int = 0):
         L = load()
         self.Ns = [int(n) for n in Ns]
         self.B = len(self.Ns)
@@ -187,7 +230,7 @@ class IsingSearch:
         Narr = (ctypes.c_int32 * self.B)(*self.Ns)
         cfg = IsingConfig(M=self.M, max_iters=int(max_iters), form=int(form),
                           states_per_item=int(states_per_item), topk_factor=int(topk_factor),
-                          persistent=int(persistent), timing=int(timing))
+                          persistent=int(persistent), timing=int(timing), flags=int(flags))
         if stream is None:
             stream = current_stream_handle()
         h = ctypes.c_void_p()
@@ -263,6 +306,45 @@ class IsingSearch:
         _check(load().ising_search_get_stats(self._h, ctypes.byref(st)))
         return st.as_dict()
 
+    # learned-proposal form
+    def set_scorer(self, scorer: int, params=None, seed: int = 0):
+        pp = None
+        if params is not None:
+            params = np.ascontiguousarray(params, dtype=np.float32)
+            if params.size != MLP_NPARAM:
+                raise ValueError(f"the network has {MLP_NPARAM} parameters, got {params.size}")
+            pp = params.ctypes.data
+        _check(load().ising_search_set_scorer(self._h, int(scorer), pp, ctypes.c_uint64(seed)))
+
+    def set_trace(self, feat_ptr: int, label_ptr: int, capacity: int, pairs_per_state: int = 8,
+                  rate: float = 1.0, seed: int = 0):
+        """Device buffers (pointers, e.g. torch tensors' data_ptr()) of capacity x 4 FP32 and capacity bytes."""
+        _check(load().ising_search_set_trace(self._h, ctypes.c_void_p(feat_ptr or None),
+                                             ctypes.c_void_p(label_ptr or None), int(capacity),
+                                             int(pairs_per_state), float(rate), ctypes.c_uint64(seed)))
+
+    def trace_count(self) -> int:
+        c = ctypes.c_int64(0)
+        _check(load().ising_search_get_trace_count(self._h, ctypes.byref(c)))
+        return c.value
+
+    def topk(self) -> int:
+        return int(load().ising_search_topk(self._h))
+
+    def get_proposals(self, search: int, max_parents: Optional[int] = None):
+        """Returns (mode, [(parent_bits (W,), pair codes (n,))]) of the last step of one search."""
+        W = _words(self.Ns[search // self.L])
+        K = self.topk()
+        mp = self.M if max_parents is None else int(max_parents)
+        pb = np.zeros((mp, W), dtype=np.uint64)
+        pr = np.zeros((mp, K), dtype=np.uint32)
+        npr = np.zeros(mp, dtype=np.int32)
+        n = ctypes.c_int32(0)
+        md = ctypes.c_int32(0)
+        _check(load().ising_search_get_proposals(self._h, int(search), pb.ctypes.data, pr.ctypes.data,
+                                                 npr.ctypes.data, mp, ctypes.byref(n), ctypes.byref(md)))
+        return md.value, [(pb[k].copy(), pr[k, :npr[k]].copy()) for k in range(n.value)]
+
     def destroy(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             load().ising_search_destroy(self._h)
@@ -273,3 +355,36 @@ class IsingSearch:
             self.destroy()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- training of the scoring network
+# Thin wrappers over the device entry points: every argument is a device
+# pointer (an integer such as torch's data_ptr()), work goes on `stream`.
+
+def mlp_workspace_bytes() -> int:
+    return int(load().ising_mlp_workspace_bytes())
+
+
+def _vp(p):
+    return ctypes.c_void_p(int(p)) if p else None
+
+
+def mlp_forward(params, feat, n, logits, stream=None):
+    _check(load().ising_mlp_forward(_vp(params), _vp(feat), int(n), _vp(logits), _vp(stream)))
+
+
+def mlp_loss_grad(params, feat, label, n, pos_weight, grad, loss, workspace, workspace_bytes, stream=None):
+    _check(load().ising_mlp_loss_grad(_vp(params), _vp(feat), _vp(label), int(n), float(pos_weight), _vp(grad),
+                                      _vp(loss), _vp(workspace), int(workspace_bytes), _vp(stream)))
+
+
+def mlp_adam(params, m, v, grad, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(load().ising_mlp_adam(_vp(params), _vp(m), _vp(v), _vp(grad), int(t), float(lr), float(beta1),
+                                 float(beta2), float(eps), _vp(stream)))
+
+
+def mlp_train(params, m, v, feat, label, n, batch, steps, t0, lr, pos_weight, seed, loss, workspace,
+              workspace_bytes, stream=None):
+    _check(load().ising_mlp_train(_vp(params), _vp(m), _vp(v), _vp(feat), _vp(label), int(n), int(batch),
+                                  int(steps), int(t0), float(lr), float(pos_weight), ctypes.c_uint64(seed), _vp(loss),
+                                  _vp(workspace), int(workspace_bytes), _vp(stream)))

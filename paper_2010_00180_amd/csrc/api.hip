@@ -1,7 +1,8 @@
 // Host side of the C ABI declared in include/ising_search.h: argument
 // validation, device allocation, the per-step launch sequence and result
-// copies.  Every device computation happens in the kernels of k_init.hip and
-// k_step.hip; this file only moves data and orders launches.
+// copies.  Every device computation happens in the kernels (k_init.hip,
+// k_step.hip, k_split.hip, k_learn.hip, k_mlp.hip); this file only moves data
+// and orders launches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -59,8 +60,14 @@ struct ising_search {
     int flags_h[8]{};
     // timing (cfg.timing): events around each kernel family of a step
     bool timing = false;
-    hipEvent_t ev[6]{};
-    double t_scan = 0, t_merge = 0, t_frontier = 0, t_prep = 0, t_init = 0, t_step = 0;
+    hipEvent_t ev[7]{};
+    double t_scan = 0, t_merge = 0, t_frontier = 0, t_prep = 0, t_init = 0, t_step = 0, t_learn = 0;
+    // learned-proposal form
+    bool scorer_set = false;
+    bool record = false;
+    bool tracing = false;
+    int learn_grid = 0;
+    float* d_mlp = nullptr;
     double split_err = 0;
     double* d_maxerr = nullptr;
     uint64_t scan_launches = 0;
@@ -114,6 +121,15 @@ void free_all(ising_search* h)
         if (e) (void)hipEventDestroy(e);
         e = nullptr;
     }
+}
+
+// The captured step holds the Layout by value: drop it when the layout changes.
+void drop_graph(ising_search* h)
+{
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    h->gexec = nullptr;
+    h->graph = nullptr;
 }
 
 float elapsed_ms(hipEvent_t a, hipEvent_t b)
@@ -174,9 +190,13 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     *out = nullptr;
     if (!cfg) return fail(ISING_ERR_INVALID_ARG, "cfg is NULL");
     if (cfg->M < 1 || cfg->M > 1024) return fail(ISING_ERR_INVALID_ARG, "M=%d outside [1, 1024]", cfg->M);
-    if (cfg->form != ISING_FORM_PLAIN && cfg->form != ISING_FORM_SPLIT_BF16)
+    if (cfg->form != ISING_FORM_PLAIN && cfg->form != ISING_FORM_SPLIT_BF16 && cfg->form != ISING_FORM_LEARNED)
         return fail(ISING_ERR_INVALID_ARG, "form %d is not available in this build", cfg->form);
-    if (cfg->reserved) return fail(ISING_ERR_INVALID_ARG, "reserved fields must be zero");
+    if (cfg->flags & ~ISING_FLAG_RECORD_PROPOSALS) return fail(ISING_ERR_INVALID_ARG, "unknown flag bits 0x%x", cfg->flags);
+    if ((cfg->flags & ISING_FLAG_RECORD_PROPOSALS) && cfg->form != ISING_FORM_LEARNED)
+        return fail(ISING_ERR_INVALID_ARG, "proposals are recorded by the learned form only");
+    if (cfg->topk_factor < 0 || cfg->topk_factor > 64)
+        return fail(ISING_ERR_INVALID_ARG, "topk_factor=%d outside [0, 64]", cfg->topk_factor);
     if (cfg->states_per_item < 0 || cfg->states_per_item > 4096)
         return fail(ISING_ERR_INVALID_ARG, "states_per_item=%d outside [0, 4096]", cfg->states_per_item);
     if (n_inst < 1) return fail(ISING_ERR_INVALID_ARG, "n_inst=%d < 1", n_inst);
@@ -217,6 +237,31 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
         }
     }
 
+    // learned form: K = topk * N proposals per state; candidate keys in LDS are
+    // twice K when two blocks still fit a CU, else as many as one block may
+    // hold, and at least K plus one round of appends
+    const int topk = cfg->topk_factor > 0 ? cfg->topk_factor : 8;
+    int kmax = 1, cap_lr = 0;
+    {
+        const long long allp = (long long)Nmax * (Nmax - 1) / 2;
+        const long long k = (long long)topk * Nmax;
+        kmax = (int)std::max(1LL, std::min(k, allp));
+    }
+    if (cfg->form == ISING_FORM_LEARNED) {
+        const long long fixed = (long long)words_of(Nmax) * 8 + (long long)pad_of(Nmax) * 2 + 2048;
+        const long long want = 2LL * kmax + 1024;
+        const long long room = LR_ROOM;
+        long long cap = want;
+        if (cap * 8 + fixed > 78 * 1024) {
+            const long long two = (78 * 1024 - fixed) / 8;
+            cap = two >= kmax + 2 * room ? two : std::min(want, (150 * 1024 - fixed) / 8);
+        }
+        if (cap < kmax + room)
+            return fail(ISING_ERR_INVALID_ARG, "K = %d proposals per state do not fit the ranking kernel's LDS "
+                        "(use a smaller topk_factor)", kmax);
+        cap_lr = (int)cap;
+    }
+
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
         (void)hipGetLastError();
@@ -239,7 +284,11 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     lay.Wmax = words_of(Nmax);
     lay.Npmax = pad_of(Nmax);
     lay.fmax = L * cfg->M;
-    lay.cap_surv = 32768;
+    lay.cap_surv = cfg->form == ISING_FORM_LEARNED ? 65536 : 32768;
+    lay.topk = topk;
+    lay.kmax = kmax;
+    lay.cap_lr = cap_lr;
+    hd->record = (cfg->flags & ISING_FLAG_RECORD_PROPOSALS) != 0;
     const int sc0 = cfg->states_per_item > 0 ? cfg->states_per_item : 64;
     hd->sc_h.assign(n_inst, sc0);
     hd->persistent = cfg->persistent != 0;
@@ -293,7 +342,7 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     ALLOC(lay.fbits, (size_t)n_inst * lay.fmax * lay.Wmax);
     ALLOC(lay.surv_count, S);
     ALLOC(lay.surv, S * lay.cap_surv);
-    ALLOC(lay.item_prefix, 3 * ((size_t)n_inst + 1));
+    ALLOC(lay.item_prefix, 4 * ((size_t)n_inst + 1));
     ALLOC(lay.ctr, 16);
     ALLOC(lay.flags, 8);
     ALLOC(hd->d_scb, n_inst);
@@ -311,6 +360,19 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
         ALLOC(lay.RR32, (size_t)n_inst * lay.fmax * lay.Npmax);
         ALLOC(hd->d_maxerr, 1);
     }
+    uint16_t* dJn = nullptr;
+    if (cfg->form == ISING_FORM_LEARNED) {
+        ALLOC(lay.xfull, S * M2);
+        ALLOC(lay.mode, S);
+        ALLOC(lay.last_mode, S);
+        ALLOC(dJn, (size_t)jtot);
+        ALLOC(hd->d_mlp, (size_t)MLP_NPARAM);
+        if (hd->record) {
+            ALLOC(lay.prop, (size_t)n_inst * lay.fmax * lay.kmax);
+            ALLOC(lay.prop_n, (size_t)n_inst * lay.fmax);
+        }
+    }
+    ALLOC(lay.lr_count, n_inst);
     ALLOC(lay.nm_count, S);
     ALLOC(lay.nm_code, S * lay.M);
     ALLOC(lay.nm_pair, S * lay.M);
@@ -337,6 +399,10 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     lay.Jlo = dJlo;
     lay.ybound = dyb;
     lay.ebf = debf;
+    lay.Jn16 = dJn;
+    lay.mlp = hd->d_mlp;
+    lay.scorer = 0;
+    lay.seed = 0;
     hd->x0 = dx0;
     hd->timing = cfg->timing != 0;
     if (hd->timing) {
@@ -440,6 +506,24 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
             cp(dyb, ybh.data(), sizeof(double) * n_inst);
             cp(debf, ebfh.data(), sizeof(double) * n_inst);
         }
+        std::vector<uint16_t> jnh;
+        if (cfg->form == ISING_FORM_LEARNED) {
+            // bf16(sqrt(N) J_ij), rounded to nearest even, for the scoring network's features
+            jnh.assign((size_t)jtot, 0);
+            for (int b = 0; b < n_inst; ++b) {
+                const int n = N[b], np = hd->Npad[b];
+                const double sq = std::sqrt((double)n);
+                for (int i = 0; i < n; ++i)
+                    for (int j = 0; j < n; ++j) {
+                        const float f = (float)(sq * J[b][(size_t)i * n + j]);
+                        uint32_t u;
+                        std::memcpy(&u, &f, 4);
+                        u += 0x7FFFu + ((u >> 16) & 1u);
+                        jnh[joff[b] + (size_t)i * np + j] = (uint16_t)(u >> 16);
+                    }
+            }
+            cp(dJn, jnh.data(), sizeof(uint16_t) * jnh.size());
+        }
         if (r2 == ISING_OK) {
             hipError_t e = hipMemsetAsync(lay.ctr, 0, 16 * sizeof(unsigned long long), sm);
             if (e == hipSuccess) e = hipMemsetAsync(lay.flags, 0, 8 * sizeof(int), sm);
@@ -463,6 +547,17 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     if (hipGetDeviceProperties(&prop, hd->device) == hipSuccess && prop.multiProcessorCount > 0)
         cus = prop.multiProcessorCount;
     hd->scan_grid = cus * 16;
+    if (cfg->form == ISING_FORM_LEARNED) {
+        const size_t lds = learn_lds_bytes(lay);
+        if (learn_set_lds(lds) != hipSuccess) {
+            (void)hipGetLastError();
+            return bail(fail(ISING_ERR_HIP, "the ranking kernel cannot use %zu bytes of LDS", lds));
+        }
+        hd->learn_grid = cus * (lds + 2048 <= 80 * 1024 ? 2 : 1);
+        uint64_t* tmp = nullptr;
+        if (dalloc(hd, &tmp, (size_t)hd->learn_grid * lay.kmax) != ISING_OK) return bail(ISING_ERR_OUT_OF_MEMORY);
+        lay.lr_tmp = tmp;
+    }
     {
         std::lock_guard<std::mutex> g(g_live_mu);
         g_live.insert(hd);
@@ -489,9 +584,14 @@ static hipError_t launch_pass(ising_search* h, bool retry_mode)
     if (e == hipSuccess) e = launch_prep(lay, st);
     rec(2);
     if (e == hipSuccess) e = launch_scan(lay, h->scan_grid, st);
+    if (lay.form == ISING_FORM_LEARNED) {
+        rec(6);
+        if (e == hipSuccess) e = launch_learn(lay, h->learn_grid, st);
+    }
     rec(3);
     if (e == hipSuccess) e = launch_merge(lay, st);
     if (e == hipSuccess) e = launch_fupdate(lay, st);
+    if (e == hipSuccess && h->tracing && !retry_mode) e = launch_trace(lay, st);
     rec(4);
     if (e == hipSuccess) ++h->scan_launches;
     return e;
@@ -502,7 +602,12 @@ static void collect_times(ising_search* h)
     if (!h->timing) return;
     h->t_frontier += elapsed_ms(h->ev[0], h->ev[1]);
     h->t_prep += elapsed_ms(h->ev[1], h->ev[2]);
-    h->t_scan += elapsed_ms(h->ev[2], h->ev[3]);
+    if (h->lay.form == ISING_FORM_LEARNED) {
+        h->t_scan += elapsed_ms(h->ev[2], h->ev[6]);
+        h->t_learn += elapsed_ms(h->ev[6], h->ev[3]);
+    } else {
+        h->t_scan += elapsed_ms(h->ev[2], h->ev[3]);
+    }
     h->t_merge += elapsed_ms(h->ev[3], h->ev[4]);
 }
 
@@ -535,6 +640,8 @@ static hipError_t launch_graph_pass(ising_search* h)
 static int do_step(ising_search* h, int32_t* n_active)
 {
     const Layout& lay = h->lay;
+    if (lay.form == ISING_FORM_LEARNED && !h->scorer_set)
+        return fail(ISING_ERR_BAD_STATE, "the learned form needs ising_search_set_scorer before stepping");
     hipError_t e = h->persistent ? launch_graph_pass(h) : launch_pass(h, false);
     if (e != hipSuccess) {
         h->broken = true;
@@ -582,6 +689,8 @@ extern "C" int ising_search_autotune(ising_search_t* s, int32_t* n_active)
     g_err.clear();
     int rc = check_handle(s);
     if (rc != ISING_OK) return rc;
+    if (s->lay.form == ISING_FORM_LEARNED && !s->scorer_set)
+        return fail(ISING_ERR_BAD_STATE, "the learned form needs ising_search_set_scorer before stepping");
     const Layout& lay = s->lay;
     hipStream_t st = s->stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -627,8 +736,10 @@ extern "C" int ising_search_autotune(ising_search_t* s, int32_t* n_active)
     // the step itself with the chosen tiles
     float ms = 0.f;
     if (e == hipSuccess) e = scan_ms(ms);
+    if (e == hipSuccess && lay.form == ISING_FORM_LEARNED) e = launch_learn(lay, s->learn_grid, st);
     if (e == hipSuccess) e = launch_merge(lay, st);
     if (e == hipSuccess) e = launch_fupdate(lay, st);
+    if (e == hipSuccess && s->tracing) e = launch_trace(lay, st);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (e != hipSuccess) {
@@ -858,6 +969,11 @@ extern "C" int ising_search_set_search(ising_search_t* s, int32_t search, const 
     HIP_TRY(hipMemcpyAsync(lay.nkept + search, &count, sizeof(int), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemcpyAsync(lay.active + search, &one, sizeof(int), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemcpyAsync(lay.retry + search, &zero, sizeof(int), hipMemcpyHostToDevice, s->stream));
+    if (lay.form == ISING_FORM_LEARNED) {
+        // installed states have not had their pairs enumerated; the next step ranks
+        HIP_TRY(hipMemsetAsync(lay.xfull + (size_t)search * M2, 0, M2, s->stream));
+        HIP_TRY(hipMemcpyAsync(lay.mode + search, &zero, sizeof(int), hipMemcpyHostToDevice, s->stream));
+    }
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->final_dirty = true;
     return ISING_OK;
@@ -888,6 +1004,10 @@ extern "C" int ising_search_get_stats(ising_search_t* s, ising_stats_t* out)
     out->init_ms = s->t_init;
     out->step_ms = s->t_step;
     out->split_field_err = s->split_err;
+    out->scored_pairs = c[CTR_SCORED];
+    out->ranked_states = c[CTR_LEARNED];
+    out->trace_samples = c[CTR_TRACE];
+    out->learn_ms = s->t_learn;
     return ISING_OK;
 }
 
@@ -902,4 +1022,227 @@ extern "C" void ising_search_destroy(ising_search_t* s)
     else (void)hipDeviceSynchronize();
     free_all(s);
     delete s;
+}
+
+// ------------------------------------------------------------------ learned-proposal form
+extern "C" int ising_search_set_scorer(ising_search_t* s, int32_t scorer, const float* params, uint64_t seed)
+{
+    g_err.clear();
+    int rc = check_handle(s);
+    if (rc != ISING_OK) return rc;
+    if (s->lay.form != ISING_FORM_LEARNED) return fail(ISING_ERR_INVALID_ARG, "the handle is not of the learned form");
+    if (scorer < ISING_SCORER_NETWORK || scorer > ISING_SCORER_UNIFORM)
+        return fail(ISING_ERR_INVALID_ARG, "scorer %d is not one of the scorers", scorer);
+    if (scorer == ISING_SCORER_NETWORK) {
+        if (!params) return fail(ISING_ERR_INVALID_ARG, "the network scorer needs its parameters");
+        for (int k = 0; k < MLP_NPARAM; ++k)
+            if (!std::isfinite(params[k])) return fail(ISING_ERR_INVALID_ARG, "parameter %d is not finite", k);
+        HIP_TRY(hipMemcpyAsync(s->d_mlp, params, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+    }
+    s->lay.scorer = scorer;
+    s->lay.seed = seed;
+    s->scorer_set = true;
+    drop_graph(s);
+    return ISING_OK;
+}
+
+extern "C" int ising_search_set_trace(ising_search_t* s, float* feat, uint8_t* label, int64_t capacity,
+                                      int32_t pairs_per_state, float rate, uint64_t seed)
+{
+    g_err.clear();
+    int rc = check_handle(s);
+    if (rc != ISING_OK) return rc;
+    Layout& lay = s->lay;
+    if (!feat || !label || capacity <= 0) {
+        if (feat || label || capacity != 0) return fail(ISING_ERR_INVALID_ARG, "trace buffers: all NULL / 0 to stop");
+        lay.tr_feat = nullptr;
+        lay.tr_label = nullptr;
+        lay.tr_cap = 0;
+        s->tracing = false;
+        drop_graph(s);
+        return ISING_OK;
+    }
+    if (pairs_per_state < 0 || pairs_per_state > 1 << 20)
+        return fail(ISING_ERR_INVALID_ARG, "pairs_per_state=%d outside [0, 2^20]", pairs_per_state);
+    if (!(rate >= 0.f && rate <= 1.f)) return fail(ISING_ERR_INVALID_ARG, "rate outside [0, 1]");
+    lay.tr_feat = feat;
+    lay.tr_label = label;
+    lay.tr_cap = capacity;
+    lay.tr_neg = pairs_per_state;
+    lay.tr_rate = rate;
+    lay.seed = seed;
+    s->tracing = true;
+    const unsigned long long zero = 0;
+    HIP_TRY(hipMemcpyAsync(lay.ctr + CTR_TRACE, &zero, sizeof zero, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    drop_graph(s);
+    return ISING_OK;
+}
+
+extern "C" int ising_search_get_trace_count(ising_search_t* s, int64_t* count)
+{
+    g_err.clear();
+    int rc = check_handle(s);
+    if (rc != ISING_OK) return rc;
+    if (!count) return fail(ISING_ERR_INVALID_ARG, "count is NULL");
+    unsigned long long c = 0;
+    HIP_TRY(hipMemcpyAsync(&c, s->lay.ctr + CTR_TRACE, sizeof c, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    *count = (int64_t)c;
+    return ISING_OK;
+}
+
+extern "C" int ising_search_get_proposals(ising_search_t* s, int32_t search, uint64_t* parent_bits, uint32_t* pairs,
+                                          int32_t* n_pairs, int32_t max_parents, int32_t* n_parents, int32_t* mode)
+{
+    g_err.clear();
+    int rc = check_handle(s);
+    if (rc != ISING_OK) return rc;
+    const Layout& lay = s->lay;
+    if (!s->record) return fail(ISING_ERR_BAD_STATE, "the handle does not record proposals (ISING_FLAG_RECORD_PROPOSALS)");
+    if (search < 0 || search >= lay.S) return fail(ISING_ERR_INVALID_ARG, "search %d outside [0, %d)", search, lay.S);
+    if (!n_parents || !mode || (max_parents > 0 && (!parent_bits || !pairs || !n_pairs)))
+        return fail(ISING_ERR_INVALID_ARG, "NULL output pointer");
+    const int b = search / lay.L;
+    const int W = words_of(s->N[b]);
+    int nl = 0, md = 0;
+    HIP_TRY(hipMemcpyAsync(&nl, lay.lr_count + b, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(&md, lay.last_mode + search, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    std::vector<int> codes(nl > 0 ? nl : 1);
+    const size_t base = (size_t)b * lay.fmax + (size_t)(lay.fmax - nl);
+    if (nl > 0)
+        HIP_TRY(hipMemcpyAsync(codes.data(), lay.fr_list + base, sizeof(int) * nl, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    int np = 0;
+    std::vector<uint64_t> w(lay.Wmax);
+    for (int k = 0; k < nl; ++k) {
+        if (codes[k] / (2 * lay.M) != search) continue;
+        if (np >= max_parents) return fail(ISING_ERR_CAPACITY, "more than max_parents=%d ranked parents", max_parents);
+        const size_t fe = base + k;
+        int cnt = 0;
+        HIP_TRY(hipMemcpyAsync(&cnt, lay.prop_n + fe, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipMemcpyAsync(w.data(), lay.fbits + fe * lay.Wmax, sizeof(uint64_t) * lay.Wmax,
+                               hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        if (cnt < 0 || cnt > lay.kmax) return fail(ISING_ERR_BAD_STATE, "corrupt proposal count %d", cnt);
+        if (cnt > 0)
+            HIP_TRY(hipMemcpyAsync(pairs + (size_t)np * lay.kmax, lay.prop + fe * lay.kmax, sizeof(uint32_t) * cnt,
+                                   hipMemcpyDeviceToHost, s->stream));
+        for (int q = 0; q < W; ++q) parent_bits[(size_t)np * W + q] = w[q];
+        n_pairs[np] = cnt;
+        ++np;
+    }
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    *n_parents = np;
+    *mode = md;
+    return ISING_OK;
+}
+
+extern "C" int32_t ising_search_topk(ising_search_t* s)
+{
+    if (check_handle(s) != ISING_OK) return -1;
+    return s->lay.kmax;
+}
+
+// ------------------------------------------------------------------ training of the scoring network
+namespace {
+constexpr int64_t MLP_WS_GRID = 1024;   // blocks of the gradient kernel at most
+int64_t mlp_ws_need() { return (MLP_WS_GRID * (MLP_NPARAM + 1) + MLP_NPARAM + 1) * (int64_t)sizeof(float); }
+int have_device()
+{
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        return fail(ISING_ERR_NO_DEVICE, "no HIP device available");
+    }
+    return ISING_OK;
+}
+}  // namespace
+
+extern "C" int64_t ising_mlp_workspace_bytes(void) { return mlp_ws_need(); }
+
+extern "C" int32_t ising_mlp_num_params(void) { return MLP_NPARAM; }
+
+extern "C" int ising_mlp_forward(const float* params, const float* feat, int64_t n, float* logits, void* stream)
+{
+    g_err.clear();
+    if (!params || !feat || !logits || n < 0) return fail(ISING_ERR_INVALID_ARG, "NULL pointer or n < 0");
+    int rc = have_device();
+    if (rc != ISING_OK) return rc;
+    if (n == 0) return ISING_OK;
+    hipError_t e = launch_mlp_forward(params, feat, n, logits, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(ISING_ERR_HIP, "forward launch failed: %s", hipGetErrorString(e));
+    return ISING_OK;
+}
+
+extern "C" int ising_mlp_loss_grad(const float* params, const float* feat, const uint8_t* label, int64_t n,
+                                   float pos_weight, float* grad, float* loss, void* workspace, int64_t workspace_bytes,
+                                   void* stream)
+{
+    g_err.clear();
+    if (!params || !feat || !label || !grad || !workspace || n < 1)
+        return fail(ISING_ERR_INVALID_ARG, "NULL pointer or n < 1");
+    if (workspace_bytes < mlp_ws_need())
+        return fail(ISING_ERR_INVALID_ARG, "workspace of %lld bytes < %lld", (long long)workspace_bytes,
+                    (long long)mlp_ws_need());
+    if (!(pos_weight > 0.f) || !std::isfinite(pos_weight)) return fail(ISING_ERR_INVALID_ARG, "pos_weight must be > 0");
+    int rc = have_device();
+    if (rc != ISING_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    float* partial = static_cast<float*>(workspace);
+    const int grid = mlp_grid_for(n);
+    hipError_t e = launch_mlp_grad(params, feat, label, n, n, 0, -1, pos_weight, partial, grid, st);
+    if (e == hipSuccess) e = launch_mlp_reduce(partial, grid, grad, loss, st);
+    if (e != hipSuccess) return fail(ISING_ERR_HIP, "gradient launch failed: %s", hipGetErrorString(e));
+    return ISING_OK;
+}
+
+extern "C" int ising_mlp_adam(float* params, float* m, float* v, const float* grad, int32_t t, float lr, float beta1,
+                              float beta2, float eps, void* stream)
+{
+    g_err.clear();
+    if (!params || !m || !v || !grad) return fail(ISING_ERR_INVALID_ARG, "NULL pointer");
+    if (t < 1 || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f) || !(lr > 0.f))
+        return fail(ISING_ERR_INVALID_ARG, "Adam hyper-parameters out of range");
+    int rc = have_device();
+    if (rc != ISING_OK) return rc;
+    const float c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, t)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, t)));
+    hipError_t e = launch_mlp_adam(params, m, v, grad, lr, beta1, beta2, eps, c1, c2, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(ISING_ERR_HIP, "Adam launch failed: %s", hipGetErrorString(e));
+    return ISING_OK;
+}
+
+extern "C" int ising_mlp_train(float* params, float* m, float* v, const float* feat, const uint8_t* label, int64_t n,
+                               int32_t batch, int32_t steps, int32_t t0, float lr, float pos_weight, uint64_t seed,
+                               float* loss, void* workspace, int64_t workspace_bytes, void* stream)
+{
+    g_err.clear();
+    if (!params || !m || !v || !feat || !label || !workspace || n < 1)
+        return fail(ISING_ERR_INVALID_ARG, "NULL pointer or n < 1");
+    if (batch < 1 || steps < 0 || t0 < 0) return fail(ISING_ERR_INVALID_ARG, "batch < 1, steps < 0 or t0 < 0");
+    if (workspace_bytes < mlp_ws_need())
+        return fail(ISING_ERR_INVALID_ARG, "workspace of %lld bytes < %lld", (long long)workspace_bytes,
+                    (long long)mlp_ws_need());
+    if (!(pos_weight > 0.f) || !std::isfinite(pos_weight) || !(lr > 0.f))
+        return fail(ISING_ERR_INVALID_ARG, "pos_weight and lr must be > 0");
+    int rc = have_device();
+    if (rc != ISING_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    float* partial = static_cast<float*>(workspace);
+    float* grad = partial + MLP_WS_GRID * (MLP_NPARAM + 1);
+    const int grid = mlp_grid_for(batch);
+    const double b1 = 0.9, b2 = 0.999;
+    for (int k = 0; k < steps; ++k) {
+        const int t = t0 + k + 1;
+        hipError_t e = launch_mlp_grad(params, feat, label, n, batch, seed, k + t0, pos_weight, partial, grid, st);
+        if (e == hipSuccess) e = launch_mlp_reduce(partial, grid, grad, loss, st);
+        if (e == hipSuccess)
+            e = launch_mlp_adam(params, m, v, grad, lr, (float)b1, (float)b2, 1e-8f,
+                                (float)(1.0 / (1.0 - std::pow(b1, t))), (float)(1.0 / (1.0 - std::pow(b2, t))), st);
+        if (e != hipSuccess) return fail(ISING_ERR_HIP, "training launch failed: %s", hipGetErrorString(e));
+    }
+    return ISING_OK;
 }

@@ -11,6 +11,9 @@
 //   front  per instance: list of (search, slot) of states to expand.
 //   A      per frontier entry: a_i = -2 s_i F_i (the single-flip change).
 //   surv   per search: candidate records {E_child, parent slot, i | j<<16}.
+// Learned-proposal form: frontier states whose pair flips are ranked by the
+// scoring network are listed from the back of the instance's frontier list,
+// states enumerated in full from the front.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -25,6 +28,13 @@ constexpr int MERGE_CH = 2048;      // candidates sorted per merge pass (LDS)
 constexpr int STAGE = 256;          // wave-private survivor staging (records)
 constexpr uint32_t SINGLE = 0xFFFFu;   // j field of a single-flip record
 constexpr uint32_t REF_SURV = 0x80000000u;
+constexpr int MLP_H = 64;           // hidden width of the pair-scoring network
+constexpr int MLP_NPARAM = 4 * MLP_H + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1;   // 4545
+constexpr int MLP_W1 = 0, MLP_B1 = 4 * MLP_H, MLP_W2 = MLP_B1 + MLP_H, MLP_B2 = MLP_W2 + MLP_H * MLP_H,
+              MLP_W3 = MLP_B2 + MLP_H, MLP_B3 = MLP_W3 + MLP_H;
+constexpr int LR_WAVES = 4;                        // waves of the ranking kernel's block
+constexpr int LR_R = 16;                           // blocks of 16 pairs per wave between barriers
+constexpr int LR_ROOM = LR_WAVES * LR_R * 16;      // keys appended per round at most
 
 struct Surv {
     double E;        // energy of the child
@@ -76,7 +86,7 @@ struct Layout {
     int* surv_count;         // [S]
     Surv* surv;              // [S][cap_surv]
     // scheduling and counters
-    long long* item_prefix;  // [B+1]
+    long long* item_prefix;  // [4][B+1]: scan items, prepared entries, FP32 scan items, ranked entries
     unsigned long long* ctr; // [16] device counters (see CTR_*)
     int* flags;              // [8] per-step flags (see FLAG_*)
     // new kept states of the last merge, for the field update
@@ -94,6 +104,27 @@ struct Layout {
     float* Ft;               // [S][Npmax] F~ of the initial states (bf16 hi+lo GEMM, FP32 sums)
     float* A32;              // [B][fmax][Npmax] fl32(a_i)
     float* RR32;             // [B][fmax][Npmax] T - a_i + slack, rounded up to FP32
+    // learned-proposal form
+    uint8_t* xfull;          // [S][2M] 1 = every pair flip of the state was evaluated exactly
+    int* mode;               // [S] 0 = the next step ranks pairs, 1 = it enumerates all pairs
+    int* last_mode;          // [S] the mode of the last step
+    int* lr_count;           // [B] ranked frontier entries, at fr_list[fmax-lr_count .. fmax)
+    int topk;                // K = topk * N proposals per state
+    int scorer;              // 0 network, 1 f_i + f_j, 2 hashed uniform
+    uint64_t seed;           // salt of the uniform scorer and of the trace sampling
+    const float* mlp;        // [MLP_NPARAM] FP32 master parameters; bf16 is taken in the kernel
+    const uint16_t* Jn16;    // per instance, bf16(sqrt(N) J_ij) (same layout as J4)
+    uint32_t* prop;          // [B][fmax][kmax] proposals of the last step (i | j << 16), or null
+    int* prop_n;             // [B][fmax] proposals recorded per entry
+    int kmax;                // row stride of prop (K of the largest instance)
+    int cap_lr;              // candidate keys held in LDS per ranked state
+    uint64_t* lr_tmp;        // [grid][kmax] compaction buffer of the ranking kernel
+    // trace capture (features, label) of expanded states
+    float* tr_feat;          // [tr_cap][4]
+    uint8_t* tr_label;       // [tr_cap]
+    long long tr_cap;
+    int tr_neg;              // sampled pair flips per traced state
+    float tr_rate;           // fraction of expanded states traced
     // final merge output
     uint64_t* out_bits;      // [B][M][Wmax]
     double* out_E;           // [B][M]
@@ -101,7 +132,7 @@ struct Layout {
 };
 
 enum { CTR_PAIRS = 0, CTR_SINGLES = 1, CTR_FRONTIER = 2, CTR_SURV = 3, CTR_RETRY = 4, CTR_STEPS = 5,
-       CTR_FALLBACK = 6 };
+       CTR_FALLBACK = 6, CTR_SCORED = 7, CTR_LEARNED = 8, CTR_TRACE = 9 };
 enum { FLAG_ACTIVE = 0, FLAG_OVERFLOW = 1, FLAG_STUCK = 2, FLAG_RETRY_MODE = 3, FLAG_FIRST = 4 };
 
 __host__ __device__ inline int words_of(int N) { return (N + 63) >> 6; }
@@ -127,6 +158,18 @@ hipError_t launch_init_split(const Layout& lay, const uint64_t* d_x0, double* d_
 hipError_t launch_prep32(const Layout& lay, hipStream_t st);
 hipError_t launch_scan32(const Layout& lay, int scan_grid, hipStream_t st);
 hipError_t launch_step_begin(const Layout& lay, bool retry_mode, hipStream_t st);
+hipError_t launch_learn(const Layout& lay, int grid, hipStream_t st);
+hipError_t learn_set_lds(size_t bytes);
+size_t learn_lds_bytes(const Layout& lay);
+hipError_t launch_trace(const Layout& lay, hipStream_t st);
+// training of the scoring network (device pointers; partial = workspace)
+int mlp_grid_for(long long count);
+hipError_t launch_mlp_grad(const float* P, const float* X, const uint8_t* y, long long n, long long count,
+                           uint64_t seed, int step, float pos_w, float* partial, int grid, hipStream_t st);
+hipError_t launch_mlp_reduce(const float* partial, int grid, float* grad, float* loss, hipStream_t st);
+hipError_t launch_mlp_adam(float* P, float* m, float* v, const float* g, float lr, float b1, float b2, float eps,
+                           float c1, float c2, hipStream_t st);
+hipError_t launch_mlp_forward(const float* P, const float* X, long long n, float* z, hipStream_t st);
 hipError_t launch_final(const Layout& lay, hipStream_t st);
 
 }  // namespace qi

@@ -88,6 +88,11 @@ __global__ __launch_bounds__(64) void k_seed(Layout lay, const uint64_t* __restr
         lay.nkept[s] = 1;
         lay.active[s] = 1;
         lay.retry[s] = 0;
+        if (lay.form == 2) {
+            lay.xfull[q] = 0;
+            lay.mode[s] = 0;
+            lay.last_mode[s] = 0;
+        }
         if (s == 0) lay.flags[FLAG_FIRST] = lay.form == 1 ? 1 : 0;
     }
 }

@@ -1,0 +1,498 @@
+// Learned-proposal form (not in the paper, whose own lever for a cheaper
+// search is a smaller H1).  For every ranked frontier state a small network
+// scores all N(N-1)/2 pair flips from the features
+//   (f_i, f_j, sqrt(N) J_ij, s_i s_j),   f_i = s_i F_i = -a_i / 2,
+// the K = topk * N best are evaluated exactly in FP64 (a_i + a_j + s_i s_j 4J_ij,
+// the same energy change as the full scan) and filtered by the step's cut.
+// The single flips of ranked states are offered by the preparation kernel.
+//
+// k_learn: one block (4 waves) per ranked state.  A wave scores 16 pairs
+// (row i, columns j..j+15) per pass of the network on the bf16 matrix cores
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation):
+//   layer 1  4 MFMAs: rows = 64 hidden units, K = 8 feature slots
+//            (f_i, f_j, Jn, ss, 1 for the bias, zeros), columns = 16 pairs
+//   layer 2  8 MFMAs: 64 x 64, the bias in the accumulator
+//   output   2 MFMAs: row 0 = w3, the bias in the accumulator
+// The D layout of one layer (lane l holds rows 4(l/16)+r, column l%16) is the
+// next layer's B operand after relu and rounding to bf16, once the hidden
+// index is permuted: logical k = 8q + t of K-step kk is hidden unit
+// 32 kk + 16 (t/4) + 4q + t%4.  The weight operands carry the same permutation.
+// Scores become 64-bit keys (ordered score, ~pair code: ties go to the smaller
+// code); keys above a block-wide threshold are appended to an LDS buffer, and
+// when it fills, a radix select (8-bit digits) finds the K-th largest key,
+// which becomes the threshold, and the K best are compacted through a
+// per-block global buffer.
+//
+// k_trace: (features, label) samples for training, from the states expanded
+// in a step once its merge has committed.
+#include "common.h"
+
+namespace qi {
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+
+
+__device__ inline uint32_t lr_lane() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+__device__ inline uint32_t lr_mbcnt(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// finaliser of splitmix64 (Steele, Lea and Flood)
+__device__ inline uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ inline uint32_t ord_score(float z)
+{
+    if (!(z == z)) return 0u;   // NaN ranks last
+    const uint32_t u = __float_as_uint(z);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ inline __bf16 bfb(uint16_t u) { return __builtin_bit_cast(__bf16, u); }
+
+__device__ inline v8bf relu_pack(v4f a, v4f b)
+{
+    v8bf x;
+    x[0] = (__bf16)a[0];
+    x[1] = (__bf16)a[1];
+    x[2] = (__bf16)a[2];
+    x[3] = (__bf16)a[3];
+    x[4] = (__bf16)b[0];
+    x[5] = (__bf16)b[1];
+    x[6] = (__bf16)b[2];
+    x[7] = (__bf16)b[3];
+    // relu on the bf16 bit patterns: a set sign bit is a negative int16
+    v8s s = __builtin_bit_cast(v8s, x);
+    const v8s zero = {0, 0, 0, 0, 0, 0, 0, 0};
+    s = __builtin_elementwise_max(s, zero);
+    return __builtin_bit_cast(v8bf, s);
+}
+
+struct Net {
+    v8bf a1[4];
+    v8bf a2[4][2];
+    v4f c2[4];
+    v8bf a3[2];
+    v4f c3;
+};
+
+// The network's operands in this lane's registers (bf16 rounded to nearest even).
+__device__ inline void load_net(const float* __restrict__ P, Net& n)
+{
+    const int l = (int)(lr_lane() & 63u), q = l >> 4, r = l & 15;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            float v = 0.f;
+            if (q == 0 && t < 4) v = P[MLP_W1 + (16 * m + r) * 4 + t];
+            if (q == 0 && t == 4) v = P[MLP_B1 + 16 * m + r];
+            n.a1[m][t] = (__bf16)v;
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                n.a2[o][kk][t] = (__bf16)P[MLP_W2 + (16 * o + r) * MLP_H + 32 * kk + 16 * (t >> 2) + 4 * q + (t & 3)];
+        }
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) n.c2[o][rr] = P[MLP_B2 + 16 * o + 4 * q + rr];
+    }
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const float w = P[MLP_W3 + 32 * kk + 16 * (t >> 2) + 4 * q + (t & 3)];
+            n.a3[kk][t] = (__bf16)(r == 0 ? w : 0.f);
+        }
+    }
+    const float b3 = P[MLP_B3];
+    n.c3[0] = q == 0 ? b3 : 0.f;
+    n.c3[1] = 0.f;
+    n.c3[2] = 0.f;
+    n.c3[3] = 0.f;
+}
+
+// Logit of the pair in column l%16 (valid in lanes 0..15).
+__device__ inline float net_score(const Net& n, v8bf x)
+{
+    const v4f z4 = {0.f, 0.f, 0.f, 0.f};
+    const v4f d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a1[0], x, z4, 0, 0, 0);
+    const v4f d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a1[1], x, z4, 0, 0, 0);
+    const v4f d2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a1[2], x, z4, 0, 0, 0);
+    const v4f d3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a1[3], x, z4, 0, 0, 0);
+    const v8bf h0 = relu_pack(d0, d1), h1 = relu_pack(d2, d3);
+    v4f e[4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        e[o] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a2[o][0], h0, n.c2[o], 0, 0, 0);
+        e[o] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a2[o][1], h1, e[o], 0, 0, 0);
+    }
+    const v8bf g0 = relu_pack(e[0], e[1]), g1 = relu_pack(e[2], e[3]);
+    v4f out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a3[0], g0, n.c3, 0, 0, 0);
+    out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a3[1], g1, out, 0, 0, 0);
+    return out[0];
+}
+
+struct LrShared {
+    int cnt, cnt2, d, rank, cntd;
+    unsigned long long thr, kth;
+};
+
+// Keep the K largest of cand[0..cnt) (cnt > K, keys distinct): radix select of
+// the K-th largest key, then compaction through gtmp.  Sets cnt = K and the
+// threshold to the K-th key.  Called by the whole block.
+__device__ void lr_select(uint64_t* cand, int cnt, int K, uint64_t* __restrict__ gtmp, int* hist, LrShared& sh)
+{
+    const int tid = threadIdx.x;
+    uint64_t prefix = 0, pmask = 0;
+    int rank = K;
+    bool unique = false;
+    for (int shift = 56;; shift -= 8) {
+        for (int d = tid; d < 256; d += blockDim.x) hist[d] = 0;
+        __syncthreads();
+        for (int e = tid; e < cnt; e += blockDim.x) {
+            const uint64_t k = cand[e];
+            if ((k & pmask) == prefix) atomicAdd(&hist[(int)((k >> shift) & 255u)], 1);
+        }
+        __syncthreads();
+        if (tid < 64) {
+            // lane l holds digits 255-4l .. 252-4l (largest first)
+            const int l = tid;
+            int c[4], loc = 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                c[u] = hist[255 - 4 * l - u];
+                loc += c[u];
+            }
+            int incl = loc;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int v = __shfl_up(incl, off, 64);
+                if (l >= off) incl += v;
+            }
+            int run = incl - loc;
+            if (run < rank && rank <= incl) {
+                for (int u = 0; u < 4; ++u) {
+                    if (run + c[u] >= rank) {
+                        sh.d = 255 - 4 * l - u;
+                        sh.rank = rank - run;
+                        sh.cntd = c[u];
+                        break;
+                    }
+                    run += c[u];
+                }
+            }
+        }
+        __syncthreads();
+        prefix |= (uint64_t)sh.d << shift;
+        pmask |= 0xFFull << shift;
+        rank = sh.rank;
+        if (shift == 0) break;
+        if (sh.cntd == 1) {
+            unique = true;
+            break;
+        }
+    }
+    if (unique) {
+        for (int e = tid; e < cnt; e += blockDim.x)
+            if ((cand[e] & pmask) == prefix) sh.kth = cand[e];
+    } else if (tid == 0) {
+        sh.kth = prefix;
+    }
+    if (tid == 0) sh.cnt2 = 0;
+    __syncthreads();
+    const uint64_t kth = sh.kth;
+    for (int e = tid; e < cnt; e += blockDim.x) {
+        const uint64_t k = cand[e];
+        if (k >= kth) {
+            const int pos = atomicAdd(&sh.cnt2, 1);
+            if (pos < K) gtmp[pos] = k;
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < K; e += blockDim.x) cand[e] = gtmp[e];
+    if (tid == 0) {
+        sh.cnt = K;
+        sh.thr = kth;
+    }
+    __syncthreads();
+}
+
+__device__ inline int lr_find(const long long* prefix, int B, long long e)
+{
+    int lo = 0, hi = B;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= e) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_learn(Layout lay)
+{
+    extern __shared__ __align__(16) unsigned char lr_smem[];
+    __shared__ LrShared sh;
+    __shared__ int hist[256];
+    uint64_t* cand = reinterpret_cast<uint64_t*>(lr_smem);
+    uint64_t* sbits = cand + lay.cap_lr;
+    uint16_t* f16s = reinterpret_cast<uint16_t*>(sbits + lay.Wmax);
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const uint32_t lane = (uint32_t)tid & 63u;
+    const long long* lr_prefix = lay.item_prefix + 3 * (lay.B + 1);
+    const long long total = lr_prefix[lay.B];
+    const int retry_mode = lay.flags[FLAG_RETRY_MODE];
+    uint64_t* gtmp = lay.lr_tmp + (size_t)blockIdx.x * lay.kmax;
+    Net net;
+    if (lay.scorer == 0) load_net(lay.mlp, net);
+    for (long long e = blockIdx.x; e < total; e += gridDim.x) {
+        const int b = lr_find(lr_prefix, lay.B, e);
+        const int kq = (int)(e - lr_prefix[b]);
+        const size_t fe = (size_t)b * lay.fmax + (size_t)(lay.fmax - lay.lr_count[b] + kq);
+        const FrRec rc = lay.rec[fe];
+        const int s = rc.s;
+        if (retry_mode && !lay.retry[s]) continue;
+        const int N = lay.N[b], Np = lay.Npad[b];
+        const int W = words_of(N);
+        const double* A = lay.A + fe * lay.Npmax;
+        const long long npairs = (long long)N * (N - 1) / 2;
+        const long long kl = (long long)lay.topk * N;
+        const int K = (int)(kl < npairs ? kl : npairs);
+        for (int w = tid; w < W; w += blockDim.x) sbits[w] = lay.fbits[fe * lay.Wmax + w];
+        for (int i = tid; i < N; i += blockDim.x)
+            f16s[i] = __builtin_bit_cast(uint16_t, (__bf16)(float)(-0.5 * A[i]));
+        if (tid == 0) {
+            sh.cnt = 0;
+            sh.thr = 0;
+        }
+        __syncthreads();
+
+        // blocks of 16 pairs: row i, columns j0 .. j0+15 (j0 = i+1, i+17, ...)
+        const long long n1 = N - 1;
+        const long long a16 = n1 / 16, rem = n1 % 16;
+        const long long NB = n1 > 0 ? 8 * a16 * (a16 + 1) + rem * (a16 + 1) : 0;
+        const long long rounds = (NB + (long long)LR_WAVES * LR_R - 1) / ((long long)LR_WAVES * LR_R);
+        int gi = 0, gj = 1;   // this wave's block: the wave-th of the row-major block list
+        for (int u = 0; u < wave; ++u) {
+            gj += 16;
+            if (gj >= N) { ++gi; gj = gi + 1; }
+        }
+        const uint64_t zp = lay.zob[rc.code] ^ lay.seed;
+        const uint16_t* Jn = lay.Jn16 + lay.joff[b];
+        for (long long r = 0; r < rounds; ++r) {
+            const uint64_t thr = sh.thr;
+            for (int u = 0; u < LR_R; ++u) {
+                const long long g = (long long)LR_WAVES * (r * LR_R + u) + wave;
+                if (g >= NB) break;
+                const int j = gj + (int)(lane & 15u);
+                const bool valid = lane < 16 && j < N;
+                const int jc = j < N ? j : N - 1;
+                const uint32_t code = (uint32_t)gi | ((uint32_t)jc << 16);
+                float z;
+                if (lay.scorer == 0) {
+                    const bool neg = (((sbits[gi >> 6] >> (gi & 63)) ^ (sbits[jc >> 6] >> (jc & 63))) & 1ull) != 0;
+                    const bool lo = lane < 16;
+                    const __bf16 zb = bfb(0);
+                    v8bf x;
+                    x[0] = lo ? bfb(f16s[gi]) : zb;
+                    x[1] = lo ? bfb(f16s[jc]) : zb;
+                    x[2] = lo ? bfb(Jn[(size_t)gi * Np + jc]) : zb;
+                    x[3] = lo ? bfb(neg ? (uint16_t)0xBF80 : (uint16_t)0x3F80) : zb;
+                    x[4] = lo ? bfb(0x3F80) : zb;
+                    x[5] = zb;
+                    x[6] = zb;
+                    x[7] = zb;
+                    z = net_score(net, x);
+                } else if (lay.scorer == 1) {
+                    z = (float)(-0.5 * (A[gi] + A[jc]));
+                } else {
+                    z = (float)(mix64(zp + 0x9E3779B97F4A7C15ull * ((uint64_t)code + 1ull)) >> 40) *
+                        5.9604644775390625e-08f;
+                }
+                const uint64_t key = valid ? (((uint64_t)ord_score(z) << 32) | (uint64_t)(~code)) : 0ull;
+                const bool pass = key > thr;
+                const uint64_t m = __builtin_amdgcn_ballot_w64(pass);
+                if (m) {
+                    int base = 0;
+                    if (lane == 0) base = atomicAdd(&sh.cnt, __popcll(m));
+                    base = __shfl(base, 0, 64);
+                    if (pass) cand[base + (int)lr_mbcnt(m)] = key;
+                }
+                for (int v = 0; v < LR_WAVES; ++v) {
+                    gj += 16;
+                    if (gj >= N) { ++gi; gj = gi + 1; }
+                }
+            }
+            __syncthreads();
+            if (sh.cnt > lay.cap_lr - LR_ROOM) lr_select(cand, sh.cnt, K, gtmp, hist, sh);
+        }
+        if (sh.cnt > K) lr_select(cand, sh.cnt, K, gtmp, hist, sh);
+        const int nfin = sh.cnt;
+
+        // exact FP64 energy change of the proposals, filtered by the cut
+        const double* Jb = lay.J4 + lay.joff[b];
+        for (int e0 = 0; e0 < nfin; e0 += blockDim.x) {
+            const int ee = e0 + tid;
+            bool hit = false;
+            double Ec = 0.0;
+            uint32_t code = 0;
+            if (ee < nfin) {
+                code = ~(uint32_t)cand[ee];
+                const int i = (int)(code & 0xFFFFu), j = (int)(code >> 16);
+                const bool neg = (((sbits[i >> 6] >> (i & 63)) ^ (sbits[j >> 6] >> (j & 63))) & 1ull) != 0;
+                const double y = Jb[(size_t)i * Np + j];
+                const double dE = A[i] + A[j] + (neg ? -y : y);
+                Ec = rc.E + dE;
+                hit = dE <= rc.T;
+                if (lay.prop) lay.prop[fe * lay.kmax + ee] = code;
+            }
+            const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
+            if (m) {
+                int base = 0;
+                if (lane == 0) base = atomicAdd(&lay.surv_count[s], __popcll(m));
+                base = __shfl(base, 0, 64);
+                if (hit) {
+                    const int pos = base + (int)lr_mbcnt(m);
+                    if (pos < lay.cap_surv) {
+                        Surv rr;
+                        rr.E = Ec;
+                        rr.code = (uint32_t)rc.code;
+                        rr.pair = code;
+                        lay.surv[(size_t)s * lay.cap_surv + pos] = rr;
+                    }
+                }
+            }
+        }
+        if (lay.prop && tid == 0) lay.prop_n[fe] = nfin;
+        __syncthreads();
+    }
+}
+
+size_t learn_lds_bytes(const Layout& lay)
+{
+    return (size_t)lay.cap_lr * 8 + (size_t)lay.Wmax * 8 + (size_t)lay.Npmax * 2;
+}
+
+hipError_t learn_set_lds(size_t bytes)
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(k_learn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
+hipError_t launch_learn(const Layout& lay, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_learn, dim3(grid), dim3(256), learn_lds_bytes(lay), st, lay);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ k_trace
+// One wave per prepared entry of a committed search, traced with probability
+// tr_rate: one sample per pair flip of this parent that entered the kept set
+// (label 1) and tr_neg uniformly drawn pairs i < j labelled by membership of
+// the child among the new kept states (exact energy, then the Zobrist hash).
+__global__ __launch_bounds__(256) void k_trace(Layout lay, const long long* __restrict__ fr_prefix)
+{
+    const long long total = fr_prefix[lay.B];
+    const int wave = threadIdx.x >> 6;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t salt = (uint64_t)lay.ctr[CTR_STEPS] * 0x9E3779B97F4A7C15ull;
+    const int M = lay.M;
+    for (long long e = (long long)blockIdx.x * 4 + wave; e < total; e += (long long)gridDim.x * 4) {
+        const int b = lr_find(fr_prefix, lay.B, e);
+        const int f = (int)(e - fr_prefix[b]);
+        const int P = lay.fr_count[b];
+        const size_t fe = (size_t)b * lay.fmax + (f >= P ? lay.fmax - lay.lr_count[b] + (f - P) : f);
+        const FrRec rc = lay.rec[fe];
+        const int s = rc.s;
+        if (lay.retry[s]) continue;   // the merge of this search did not commit
+        const uint64_t hsel = mix64(lay.seed ^ salt ^ ((uint64_t)(uint32_t)rc.code << 17));
+        if ((float)(hsel >> 40) * 5.9604644775390625e-08f >= lay.tr_rate) continue;
+        const int N = lay.N[b], Np = lay.Npad[b];
+        if (N < 2) continue;
+        const double* A = lay.A + fe * lay.Npmax;
+        const uint64_t* x = lay.fbits + fe * lay.Wmax;
+        const double* Jb = lay.J4 + lay.joff[b];
+        const double sq = sqrt((double)N);
+        const size_t q0 = (size_t)s * 2 * M;
+        const int nk = lay.nkept[s];
+        const int* kept = lay.kept + (size_t)s * M;
+        auto emit = [&](bool on, int i, int j, bool label) {
+            const uint64_t m = __builtin_amdgcn_ballot_w64(on);
+            if (!m) return;
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(&lay.ctr[CTR_TRACE], (unsigned long long)__popcll(m));
+            base = __shfl(base, 0, 64);
+            if (!on) return;
+            const unsigned long long pos = base + lr_mbcnt(m);
+            if (pos >= (unsigned long long)lay.tr_cap) return;
+            const bool neg = (((x[i >> 6] >> (i & 63)) ^ (x[j >> 6] >> (j & 63))) & 1ull) != 0;
+            float* o = lay.tr_feat + pos * 4;
+            o[0] = (float)(-0.5 * A[i]);
+            o[1] = (float)(-0.5 * A[j]);
+            o[2] = (float)(sq * (0.25 * Jb[(size_t)i * Np + j]));
+            o[3] = neg ? -1.f : 1.f;
+            lay.tr_label[pos] = label ? 1 : 0;
+        };
+        // pair flips of this parent that entered
+        const int nm = lay.nm_count[s];
+        for (int m0 = 0; m0 < nm; m0 += 64) {
+            const int m = m0 + (int)lane;
+            bool on = false;
+            int i = 0, j = 1;
+            if (m < nm && lay.nm_code[(size_t)s * M + m] == rc.code) {
+                const uint32_t pr = lay.nm_pair[(size_t)s * M + m];
+                if ((pr >> 16) != SINGLE) {
+                    on = true;
+                    i = (int)(pr & 0xFFFFu);
+                    j = (int)(pr >> 16);
+                }
+            }
+            emit(on, i, j, true);
+        }
+        // uniformly drawn pairs, labelled by membership
+        for (int r0 = 0; r0 < lay.tr_neg; r0 += 64) {
+            const int r = r0 + (int)lane;
+            const bool on = r < lay.tr_neg;
+            const uint64_t u = mix64(hsel + 0x632BE59BD9B4E019ull * (uint64_t)(r + 1));
+            int i = (int)((u & 0xFFFFFFFFull) % (uint64_t)N);
+            int j = (int)((u >> 32) % (uint64_t)(N - 1));
+            if (j >= i) ++j;
+            if (i > j) { const int t = i; i = j; j = t; }
+            const bool neg = (((x[i >> 6] >> (i & 63)) ^ (x[j >> 6] >> (j & 63))) & 1ull) != 0;
+            const double y = Jb[(size_t)i * Np + j];
+            const double Ec = rc.E + A[i] + A[j] + (neg ? -y : y);
+            const uint64_t zc = lay.zob[rc.code] ^ lay.zkey[i] ^ lay.zkey[j];
+            int lo = 0, hi = nk;   // first kept index with E >= Ec
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (lay.E[q0 + kept[mid]] < Ec) lo = mid + 1; else hi = mid;
+            }
+            bool in = false;
+            for (int k = lo; k < nk && lay.E[q0 + kept[k]] == Ec; ++k) {
+                const int slot = kept[k];
+                if (lay.zob[q0 + slot] == zc && lay.fresh[q0 + slot]) in = true;
+            }
+            emit(on, i, j, in);
+        }
+    }
+}
+
+hipError_t launch_trace(const Layout& lay, hipStream_t st)
+{
+    const long long* fr_prefix = lay.item_prefix + (lay.B + 1);
+    hipLaunchKernelGGL(k_trace, dim3(1024), dim3(256), 0, st, lay, fr_prefix);
+    return hipGetLastError();
+}
+
+}  // namespace qi

@@ -58,7 +58,10 @@ __device__ int block_exclusive_scan(int v, int* tmp, int& excl)
 __global__ void k_step_begin(Layout lay, int retry_mode)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (!retry_mode && t < lay.B) lay.fr_count[t] = 0;
+    if (!retry_mode && t < lay.B) {
+        lay.fr_count[t] = 0;
+        lay.lr_count[t] = 0;
+    }
     if (t < lay.S && (!retry_mode || lay.retry[t])) lay.surv_count[t] = 0;
     // a retry pass keeps the count of searches that already committed
     if (t == FLAG_OVERFLOW || t == FLAG_STUCK) lay.flags[t] = 0;
@@ -146,26 +149,42 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
     const int nk = lay.nkept[s];
     const int* kept = lay.kept + (size_t)s * M;
     const size_t q0 = (size_t)s * 2 * M;
+    // learned-proposal form: a ranking step expands the new states with ranked
+    // pairs; a full step (after a ranking step found nothing) enumerates every
+    // kept state whose pairs were not all evaluated yet
+    const bool learned = lay.form == 2;
+    const int mode = learned ? lay.mode[s] : 1;
+    const bool ranked = learned && mode == 0;
 
-    // rank the new states in kept (energy) order
+    // rank the states to expand in kept (energy) order
     int nfresh = 0;
     for (int c0 = 0; c0 < nk; c0 += 256) {
         const int k = c0 + threadIdx.x;
         const int slot = k < nk ? kept[k] : 0;
-        const int isnew = (k < nk && lay.fresh[q0 + slot]) ? 1 : 0;
+        int isnew = 0;
+        if (k < nk) isnew = (learned && !ranked) ? !lay.xfull[q0 + slot] : lay.fresh[q0 + slot];
         int excl;
         const int tot = block_exclusive_scan(isnew, tmp, excl);
-        if (isnew) idx[nfresh + excl] = (uint32_t)slot;   // new slots, lowest energy first
+        if (isnew) idx[nfresh + excl] = (uint32_t)slot;   // lowest energy first
         nfresh += tot;
     }
     __syncthreads();
-    if (threadIdx.x == 0 && nfresh > 0) tmp[0] = atomicAdd(&lay.fr_count[b], nfresh);
+    if (threadIdx.x == 0) {
+        if (learned) {
+            lay.last_mode[s] = mode;
+            if (!ranked && nfresh > 0) atomicAdd(&lay.ctr[CTR_FALLBACK], 1ull);
+        }
+        if (nfresh > 0) tmp[0] = atomicAdd(ranked ? &lay.lr_count[b] : &lay.fr_count[b], nfresh);
+    }
     if ((int)threadIdx.x < NPILOT) pslot[threadIdx.x] = (int)threadIdx.x < nfresh ? (int)idx[threadIdx.x] : -1;
     __syncthreads();
     if (nfresh > 0) {
         const int fr_base = tmp[0];
-        for (int r = threadIdx.x; r < nfresh; r += blockDim.x)
-            lay.fr_list[(size_t)b * lay.fmax + fr_base + r] = (int)(s * 2 * M + idx[r]);
+        for (int r = threadIdx.x; r < nfresh; r += blockDim.x) {
+            const size_t pos = ranked ? (size_t)(lay.fmax - 1 - (fr_base + r)) : (size_t)(fr_base + r);
+            lay.fr_list[(size_t)b * lay.fmax + pos] = (int)(s * 2 * M + idx[r]);
+            if (learned && !ranked) lay.xfull[q0 + idx[r]] = 1;
+        }
     }
     const double ecut = nk == M ? lay.E[q0 + kept[M - 1]] : INFINITY;
     __syncthreads();
@@ -175,8 +194,10 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
     }
     const int N = lay.N[b], Np = lay.Npad[b];
     const int W = words_of(N);
+    // a ranking step offers every single flip but only ranked pairs, so its
+    // pilots contribute their lightest single flips only
     const int K = N < PK ? N : PK;
-    const int nc = K * (K + 1) / 2;
+    const int nc = ranked ? (N < PCAND ? N : PCAND) : K * (K + 1) / 2;
     const int np = nfresh < NPILOT ? nfresh : NPILOT;
     if (nc * np < M) {   // too few candidates to bound anything
         if (threadIdx.x == 0) lay.cut[s] = ecut;
@@ -219,7 +240,10 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
         for (int t = threadIdx.x; t < nc; t += blockDim.x) {
             double v;
             uint32_t id;
-            if (t < K) {
+            if (ranked) {
+                v = key[t];
+                id = (1u << 25) | (idx[t] << 12);
+            } else if (t < K) {
                 v = aK[t];
                 id = (1u << 25) | ((uint32_t)iK[t] << 12);
             } else {
@@ -301,58 +325,81 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
 // ------------------------------------------------------------------ k_plan
 // One block.  Work prefix sums over instances: scan items (chunks x tiles)
 // and frontier entries; also the evaluation counters.
+// Prepared entries are the fully enumerated ones followed by the ranked ones
+// (learned form); ranked entries also get a prefix of their own.
+__device__ inline long long proposals_of(const Layout& lay, long long N)
+{
+    const long long P = N * (N - 1) / 2, K = (long long)lay.topk * N;
+    return K < P ? K : P;
+}
+
 __global__ __launch_bounds__(1024) void k_plan(Layout lay, long long* __restrict__ fr_prefix, int count)
 {
     __shared__ long long part_items[1024];
     __shared__ long long part_fr[1024];
+    __shared__ long long part_lr[1024];
+    long long* lr_prefix = lay.item_prefix + 3 * (lay.B + 1);
     const int t = threadIdx.x;
     const int per = (lay.B + 1023) / 1024;
     const int b0 = t * per;
-    long long items = 0, fr = 0, pairs = 0, singles = 0;
+    long long items = 0, fr = 0, lr = 0, pairs = 0, singles = 0, scored = 0;
     for (int b = b0; b < b0 + per && b < lay.B; ++b) {
         const long long P = lay.fr_count[b];
+        const long long Q = lay.lr_count[b];
         const long long N = lay.N[b];
         const int sc = lay.scb[b];
         items += (P + sc - 1) / sc * tiles_of((int)N);
-        fr += P;
-        pairs += P * (N * (N - 1) / 2);
-        singles += P * N;
+        fr += P + Q;
+        lr += Q;
+        pairs += P * (N * (N - 1) / 2) + Q * proposals_of(lay, N);
+        scored += Q * (N * (N - 1) / 2);
+        singles += (P + Q) * N;
     }
     part_items[t] = items;
     part_fr[t] = fr;
+    part_lr[t] = lr;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
         const long long ai = t >= off ? part_items[t - off] : 0;
         const long long af = t >= off ? part_fr[t - off] : 0;
+        const long long al = t >= off ? part_lr[t - off] : 0;
         __syncthreads();
         part_items[t] += ai;
         part_fr[t] += af;
+        part_lr[t] += al;
         __syncthreads();
     }
-    long long run_i = part_items[t] - items, run_f = part_fr[t] - fr;
+    long long run_i = part_items[t] - items, run_f = part_fr[t] - fr, run_l = part_lr[t] - lr;
     for (int b = b0; b < b0 + per && b < lay.B; ++b) {
         lay.item_prefix[b] = run_i;
         fr_prefix[b] = run_f;
+        lr_prefix[b] = run_l;
         const long long P = lay.fr_count[b];
+        const long long Q = lay.lr_count[b];
         run_i += (P + lay.scb[b] - 1) / lay.scb[b] * tiles_of(lay.N[b]);
-        run_f += P;
+        run_f += P + Q;
+        run_l += Q;
     }
     if (t == 1023) {
         lay.item_prefix[lay.B] = part_items[1023];
         fr_prefix[lay.B] = part_fr[1023];
+        lr_prefix[lay.B] = part_lr[1023];
     }
     // counters (the retry pass counts in k_prep instead)
-    __shared__ unsigned long long cp[1024], cs[1024];
+    __shared__ unsigned long long cp[1024], cs[1024], cq[1024];
     cp[t] = (unsigned long long)pairs;
     cs[t] = (unsigned long long)singles;
+    cq[t] = (unsigned long long)scored;
     __syncthreads();
     for (int w = 512; w > 0; w >>= 1) {
-        if (t < w) { cp[t] += cp[t + w]; cs[t] += cs[t + w]; }
+        if (t < w) { cp[t] += cp[t + w]; cs[t] += cs[t + w]; cq[t] += cq[t + w]; }
         __syncthreads();
     }
     if (t == 0 && count && !lay.flags[FLAG_RETRY_MODE]) {
         lay.ctr[CTR_PAIRS] += cp[0];
         lay.ctr[CTR_SINGLES] += cs[0];
+        lay.ctr[CTR_SCORED] += cq[0];
+        lay.ctr[CTR_LEARNED] += (unsigned long long)part_lr[1023];
         lay.ctr[CTR_FRONTIER] += (unsigned long long)part_fr[1023];
         lay.ctr[CTR_STEPS] += 1;
     }
@@ -381,7 +428,9 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
     for (long long e = (long long)blockIdx.x * 4 + wave; e < total; e += (long long)gridDim.x * 4) {
         const int b = find_instance(fr_prefix, lay.B, e);
         const int f = (int)(e - fr_prefix[b]);
-        const size_t fe = (size_t)b * lay.fmax + f;
+        const int P = lay.fr_count[b];
+        const bool ranked = f >= P;   // learned form: a ranked entry, listed from the back
+        const size_t fe = (size_t)b * lay.fmax + (ranked ? lay.fmax - lay.lr_count[b] + (f - P) : f);
         const int code = lay.fr_list[fe];
         const int s = code / (2 * lay.M);
         if (retry_mode && !lay.retry[s]) continue;
@@ -402,8 +451,10 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
         }
         if ((int)lane < lay.Wmax) lay.fbits[fe * lay.Wmax + lane] = x[lane];
         if (retry_mode && lane == 0) {
-            atomicAdd(&lay.ctr[CTR_PAIRS], (unsigned long long)N * (N - 1) / 2);
+            const unsigned long long all = (unsigned long long)N * (N - 1) / 2;
+            atomicAdd(&lay.ctr[CTR_PAIRS], ranked ? (unsigned long long)proposals_of(lay, N) : all);
             atomicAdd(&lay.ctr[CTR_SINGLES], (unsigned long long)N);
+            if (ranked) atomicAdd(&lay.ctr[CTR_SCORED], all);
         }
         for (int i0 = 0; i0 < Np; i0 += 64) {
             const int i = i0 + lane;
@@ -983,6 +1034,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 lay.E[q0 + slot] = r.E;
                 lay.zob[q0 + slot] = zk[k];
                 lay.fresh[q0 + slot] = 1;
+                if (lay.form == 2) lay.xfull[q0 + slot] = 0;
                 const int i = (int)(r.pair & 0xFFFFu), j = (int)(r.pair >> 16);
                 const uint64_t* xp = lay.bits + (size_t)r.code * lay.Wmax;
                 uint64_t* xn = lay.bits + (q0 + slot) * lay.Wmax;
@@ -1008,8 +1060,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         lay.nkept[s] = nrun;
         lay.nm_count[s] = nnew;
         lay.retry[s] = 0;
-        if (nnew > 0) atomicAdd(&lay.flags[FLAG_ACTIVE], 1);
-        else lay.active[s] = 0;
+        if (lay.form == 2) {
+            // learned form: a ranking step that finds nothing is followed by a
+            // full enumeration; a full enumeration that finds nothing certifies
+            // that the set is stable under the exact step
+            const int mode = lay.mode[s];
+            if (nnew > 0) {
+                lay.mode[s] = 0;
+                atomicAdd(&lay.flags[FLAG_ACTIVE], 1);
+            } else if (mode == 0) {
+                lay.mode[s] = 1;
+                atomicAdd(&lay.flags[FLAG_ACTIVE], 1);
+            } else {
+                lay.active[s] = 0;
+            }
+        } else if (nnew > 0) {
+            atomicAdd(&lay.flags[FLAG_ACTIVE], 1);
+        } else {
+            lay.active[s] = 0;
+        }
     }
 }
 

@@ -20,7 +20,7 @@ def declared_symbols():
     for fn in os.listdir(inc):
         if fn.endswith(".h"):
             src = open(os.path.join(inc, fn)).read()
-            out |= set(re.findall(r"\b(ising_search_[a-z_]+)\s*\(", src))
+            out |= set(re.findall(r"\b(ising_(?:search|mlp)_[a-z_]+)\s*\(", src))
     return out
 
 
@@ -49,7 +49,7 @@ def _good(N=10, L=2):
     return inst
 
 
-@pytest.mark.parametrize("case", ["M0", "Mbig", "form", "reserved", "L0", "N0", "Nbig", "asym", "diag",
+@pytest.mark.parametrize("case", ["M0", "Mbig", "form", "flags", "L0", "N0", "Nbig", "asym", "diag",
                                   "nan", "offgrid", "stray", "bound"])
 def test_init_rejects_invalid_arguments(case):
     inst = _good()
@@ -62,8 +62,8 @@ def test_init_rejects_invalid_arguments(case):
         cfg.M = 5000
     elif case == "form":
         cfg.form = 7
-    elif case == "reserved":
-        cfg.reserved = 1
+    elif case == "flags":
+        cfg.flags = 2
     elif case == "L0":
         L = 0
     elif case == "N0":
@@ -110,3 +110,60 @@ def test_init_without_device_reports_no_device():
     inst = _good()
     rc, hnd = _init(binding.IsingConfig(M=8), [inst.N], [inst.J], [inst.h], 2, [inst.init_bits])
     assert rc == binding.ISING_ERR_NO_DEVICE, binding.last_error()
+
+
+@pytest.mark.parametrize("case", ["record_plain", "topk_neg", "topk_big", "k_too_big"])
+def test_init_rejects_invalid_learned_configs(case):
+    inst = _good(N=30)
+    N, J, h, x = inst.N, inst.J, inst.h, inst.init_bits
+    cfg = binding.IsingConfig(M=8, form=binding.FORM_LEARNED)
+    if case == "record_plain":
+        cfg.form = binding.FORM_PLAIN
+        cfg.flags = binding.FLAG_RECORD_PROPOSALS
+    elif case == "topk_neg":
+        cfg.topk_factor = -1
+    elif case == "topk_big":
+        cfg.topk_factor = 65
+    elif case == "k_too_big":
+        # K = 64 * 4000 proposals per state cannot be held by the ranking kernel
+        inst = workloads.make_instance(4000, 43, 2)
+        N, J, h, x = inst.N, inst.J, inst.h, inst.init_bits
+        cfg.topk_factor = 64
+    rc, hnd = _init(cfg, [N], [J], [h], 2, [x])
+    assert rc == binding.ISING_ERR_INVALID_ARG, (case, rc, binding.last_error())
+    assert hnd.value is None
+
+
+def test_training_entry_points_validate_before_touching_memory():
+    lib = binding.load()
+    assert lib.ising_mlp_num_params() == binding.MLP_NPARAM == 4545
+    ws = lib.ising_mlp_workspace_bytes()
+    assert ws >= 4 * (1024 * 4546 + 4546)
+    vp = ctypes.c_void_p
+    fake = vp(0x1000)
+    E = binding.ISING_ERR_INVALID_ARG
+    assert lib.ising_mlp_forward(None, fake, 4, fake, None) == E
+    assert lib.ising_mlp_forward(fake, fake, -1, fake, None) == E
+    assert lib.ising_mlp_loss_grad(fake, fake, fake, 0, 1.0, fake, None, fake, ws, None) == E
+    assert lib.ising_mlp_loss_grad(fake, fake, fake, 10, 1.0, fake, None, fake, ws - 4, None) == E
+    assert lib.ising_mlp_loss_grad(fake, fake, fake, 10, 0.0, fake, None, fake, ws, None) == E
+    assert lib.ising_mlp_adam(fake, fake, fake, fake, 0, 1e-3, 0.9, 0.999, 1e-8, None) == E
+    assert lib.ising_mlp_adam(fake, fake, fake, fake, 1, 1e-3, 1.0, 0.999, 1e-8, None) == E
+    assert lib.ising_mlp_train(fake, fake, fake, fake, fake, 10, 0, 1, 0, 1e-3, 1.0, 0, None, fake, ws, None) == E
+    assert lib.ising_mlp_train(fake, fake, fake, fake, fake, 10, 8, 1, 0, 1e-3, 1.0, 0, None, None, ws, None) == E
+    assert lib.ising_search_set_scorer(None, 0, None, 0) == binding.ISING_ERR_BAD_STATE
+    assert lib.ising_search_topk(None) == -1
+
+
+def test_training_entry_points_report_no_device():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present (this test passes placeholder pointers)")
+    except Exception:
+        pass
+    lib = binding.load()
+    fake = ctypes.c_void_p(0x1000)
+    ws = lib.ising_mlp_workspace_bytes()
+    assert lib.ising_mlp_forward(fake, fake, 4, fake, None) == binding.ISING_ERR_NO_DEVICE
+    assert lib.ising_mlp_loss_grad(fake, fake, fake, 10, 1.0, fake, None, fake, ws, None) == binding.ISING_ERR_NO_DEVICE
