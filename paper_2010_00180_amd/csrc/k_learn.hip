@@ -4,7 +4,8 @@
 //   (f_i, f_j, sqrt(N) J_ij, s_i s_j),   f_i = s_i F_i = -a_i / 2,
 // the K = topk * N best are evaluated exactly in FP64 (a_i + a_j + s_i s_j 4J_ij,
 // the same energy change as the full scan) and filtered by the step's cut.
-// The single flips of ranked states are offered by the preparation kernel.
+// The single flips of ranked states are offered here too, under the same
+// per-state bound (below).
 //
 // k_learn: one block (4 waves) per ranked state.  A wave scores 16 pairs
 // (row i, columns j..j+15) per pass of the network on the bf16 matrix cores
@@ -147,8 +148,43 @@ __device__ inline float net_score(const Net& n, v8bf x)
 
 struct LrShared {
     int cnt, cnt2, d, rank, cntd;
-    unsigned long long thr, kth;
+    unsigned long long thr, kth, dmax;
+    double red[LR_WAVES];
 };
+
+// doubles as unsigned integers in the same order
+__device__ inline unsigned long long ord_double(double v)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
+__device__ inline double unord_double(unsigned long long u)
+{
+    return __longlong_as_double((long long)((u >> 63) ? (u & 0x7FFFFFFFFFFFFFFFull) : ~u));
+}
+
+__device__ inline double lr_block_min(double v, LrShared& sh)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) sh.red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = sh.red[0];
+    for (int w = 1; w < LR_WAVES; ++w) r = fmin(r, sh.red[w]);
+    __syncthreads();
+    return r;
+}
+
+__device__ inline double lr_block_max(double v, LrShared& sh)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) sh.red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = sh.red[0];
+    for (int w = 1; w < LR_WAVES; ++w) r = fmax(r, sh.red[w]);
+    __syncthreads();
+    return r;
+}
 
 // Keep the K largest of cand[0..cnt) (cnt > K, keys distinct): radix select of
 // the K-th largest key, then compaction through gtmp.  Sets cnt = K and the
@@ -340,22 +376,98 @@ __global__ __launch_bounds__(256) void k_learn(Layout lay)
         if (sh.cnt > K) lr_select(cand, sh.cnt, K, gtmp, hist, sh);
         const int nfin = sh.cnt;
 
-        // exact FP64 energy change of the proposals, filtered by the cut
+        // exact FP64 energy change of the proposals (kept in gtmp), and the
+        // state's own bound: its N single flips and nfin proposals are distinct
+        // states, so when there are at least M of them, the M-th lowest of their
+        // energy changes bounds the search's M-th lowest candidate, and nothing
+        // of this state above it can enter.  The bound is taken as the largest
+        // change in the lowest histogram bins that hold M of them.
         const double* Jb = lay.J4 + lay.joff[b];
-        for (int e0 = 0; e0 < nfin; e0 += blockDim.x) {
+        double dlo = INFINITY, dhi = -INFINITY;
+        for (int ee = tid; ee < nfin; ee += blockDim.x) {
+            const uint32_t code = ~(uint32_t)cand[ee];
+            const int i = (int)(code & 0xFFFFu), j = (int)(code >> 16);
+            const bool neg = (((sbits[i >> 6] >> (i & 63)) ^ (sbits[j >> 6] >> (j & 63))) & 1ull) != 0;
+            const double y = Jb[(size_t)i * Np + j];
+            const double dE = A[i] + A[j] + (neg ? -y : y);
+            reinterpret_cast<double*>(gtmp)[ee] = dE;
+            dlo = fmin(dlo, dE);
+            dhi = fmax(dhi, dE);
+        }
+        for (int i = tid; i < N; i += blockDim.x) {
+            dlo = fmin(dlo, A[i]);
+            dhi = fmax(dhi, A[i]);
+        }
+        const int ncand = nfin + N;
+        double Tl = rc.T;
+        if (ncand >= lay.M) {
+            dlo = lr_block_min(dlo, sh);
+            dhi = lr_block_max(dhi, sh);
+            const double scale = dhi > dlo ? 256.0 / (dhi - dlo) : 0.0;
+            auto bin_of = [&](double v) -> int {
+                const int k = (int)((v - dlo) * scale);
+                return k < 0 ? 0 : (k > 255 ? 255 : k);
+            };
+            for (int d = tid; d < 256; d += blockDim.x) hist[d] = 0;
+            if (tid == 0) sh.dmax = 0ull;
+            __syncthreads();
+            for (int ee = tid; ee < nfin; ee += blockDim.x)
+                atomicAdd(&hist[bin_of(reinterpret_cast<const double*>(gtmp)[ee])], 1);
+            for (int i = tid; i < N; i += blockDim.x) atomicAdd(&hist[bin_of(A[i])], 1);
+            __syncthreads();
+            if (tid < 64) {
+                // lane l holds bins 4l .. 4l+3 (lowest first)
+                const int l = tid;
+                int c[4], loc = 0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    c[u] = hist[4 * l + u];
+                    loc += c[u];
+                }
+                int incl = loc;
+                for (int off = 1; off < 64; off <<= 1) {
+                    const int v = __shfl_up(incl, off, 64);
+                    if (l >= off) incl += v;
+                }
+                int run = incl - loc;
+                if (run < lay.M && lay.M <= incl) {
+                    for (int u = 0; u < 4; ++u) {
+                        run += c[u];
+                        if (run >= lay.M) {
+                            sh.d = 4 * l + u;
+                            break;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            const int bstar = sh.d;
+            for (int ee = tid; ee < nfin; ee += blockDim.x) {
+                const double v = reinterpret_cast<const double*>(gtmp)[ee];
+                if (bin_of(v) <= bstar) atomicMax(&sh.dmax, ord_double(v));
+            }
+            for (int i = tid; i < N; i += blockDim.x)
+                if (bin_of(A[i]) <= bstar) atomicMax(&sh.dmax, ord_double(A[i]));
+            __syncthreads();
+            const double bound = unord_double(sh.dmax);
+            Tl = bound < Tl ? bound : Tl;
+        }
+        // survivors: single flips, then the proposals
+        for (int e0 = 0; e0 < ncand; e0 += blockDim.x) {
             const int ee = e0 + tid;
             bool hit = false;
-            double Ec = 0.0;
+            double dE = 0.0;
             uint32_t code = 0;
-            if (ee < nfin) {
-                code = ~(uint32_t)cand[ee];
-                const int i = (int)(code & 0xFFFFu), j = (int)(code >> 16);
-                const bool neg = (((sbits[i >> 6] >> (i & 63)) ^ (sbits[j >> 6] >> (j & 63))) & 1ull) != 0;
-                const double y = Jb[(size_t)i * Np + j];
-                const double dE = A[i] + A[j] + (neg ? -y : y);
-                Ec = rc.E + dE;
-                hit = dE <= rc.T;
-                if (lay.prop) lay.prop[fe * lay.kmax + ee] = code;
+            if (ee < N) {
+                dE = A[ee];
+                code = (uint32_t)ee | (SINGLE << 16);
+                hit = dE <= Tl;
+            } else if (ee < ncand) {
+                const int k = ee - N;
+                dE = reinterpret_cast<const double*>(gtmp)[k];
+                code = ~(uint32_t)cand[k];
+                hit = dE <= Tl;
+                if (lay.prop) lay.prop[fe * lay.kmax + k] = code;
             }
             const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
             if (m) {
@@ -366,7 +478,7 @@ __global__ __launch_bounds__(256) void k_learn(Layout lay)
                     const int pos = base + (int)lr_mbcnt(m);
                     if (pos < lay.cap_surv) {
                         Surv rr;
-                        rr.E = Ec;
+                        rr.E = rc.E + dE;
                         rr.code = (uint32_t)rc.code;
                         rr.pair = code;
                         lay.surv[(size_t)s * lay.cap_surv + pos] = rr;

@@ -462,7 +462,7 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
             if (i < N) a = -2.0 * spin_of(x, i) * F[i];
             A[i] = a;
             const double Ec = Em + a;
-            const bool hit = i < N && Ec <= c;
+            const bool hit = !ranked && i < N && Ec <= c;   // a ranked state's singles go with its pairs
             const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
             if (m) {
                 int base = 0;
