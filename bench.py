@@ -8,7 +8,10 @@ timed region starts.
 
 Workload: 120 instances, N = 600, J_ij ~ N(0,1)/sqrt(N), h_i ~ N(0,1) (both on
 the 2^-24 grid), M = 120 kept states, 64 initial states per instance, plain
-FP64 form.  Prints one JSON line.
+FP64 form.  The split-bf16 form runs the same workload; the learned-proposal
+form (network trained first on traces of other instances of the same shape)
+runs a bounded sample of it, next to the plain form on the same sample, and
+its miss rate is judged against full enumeration.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
@@ -88,6 +91,134 @@ def cpu_baseline(w, budget_s):
 
 
 FORM_CODES = {"plain": 0, "split_bf16": 1, "learned": 2}
+# multiply-adds of the scoring network per pair, counted as 2 flops each:
+# layer 1 (4 x 64), layer 2 (64 x 64), output (64)
+NET_FLOP_PER_PAIR = 2 * (4 * 64 + 64 * 64 + 64)
+BF16_MFMA_PEAK = 2.5e15   # MI355X dense bf16 matrix-core peak, FLOP/s
+
+
+def train_network(binding, torch, workloads, seed=1):
+    """Traces of plain runs on instances of the measured shape that are not in
+    the measured workload, then FP32 training on the device (Adam)."""
+    tw = workloads.custom([600] * 4, L=16, M=120, seed_offset=500)
+    cap = 1 << 22
+    feat = torch.zeros((cap, 4), dtype=torch.float32, device="cuda")
+    lab = torch.zeros(cap, dtype=torch.uint8, device="cuda")
+    s = binding.IsingSearch.from_workload(tw)
+    s.set_trace(feat.data_ptr(), lab.data_ptr(), cap, pairs_per_state=16, rate=0.1, seed=seed)
+    t0 = time.perf_counter()
+    s.run()
+    torch.cuda.synchronize()
+    t_trace = time.perf_counter() - t0
+    n = min(s.trace_count(), cap)
+    s.destroy()
+    npos = int(lab[:n].sum().item())
+    P = torch.tensor(workloads.network_params(seed).astype("float32"), device="cuda")
+    m = torch.zeros_like(P)
+    v = torch.zeros_like(P)
+    wsb = binding.mlp_workspace_bytes()
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    loss = torch.zeros(1, device="cuda")
+    steps, batch = 2000, 8192
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    binding.mlp_train(P.data_ptr(), m.data_ptr(), v.data_ptr(), feat.data_ptr(), lab.data_ptr(), n, batch, steps, 0,
+                      2e-3, (n - npos) / max(npos, 1), seed + 7, loss.data_ptr(), ws.data_ptr(), wsb,
+                      torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    info = {"trace_instances": "4 x N=600 (other seeds), L=16, M=120, plain form", "samples": n, "positives": npos,
+            "trace_s": t_trace, "adam_steps": steps, "batch": batch, "lr": 2e-3, "train_s": t_train,
+            "last_loss": float(loss.item())}
+    return P.cpu().numpy(), info
+
+
+def judge_miss_rate(binding, torch, inst, L, M, scorer, params, max_steps):
+    """Miss rate of ranking steps: |S_full \\ S_ranked| / |S_full|, where S_full is the
+    exact step (plain form) from the same kept set expanding the same states."""
+    import numpy as np
+    import dataclasses
+    from paper_2010_00180_amd.workloads import Workload
+    w = Workload("judge", 3, [dataclasses.replace(inst, init_bits=inst.init_bits[:L])], M=M, L=L)
+    lr = binding.IsingSearch.from_workload(w, form=FORM_CODES["learned"])
+    lr.set_scorer(scorer, params, seed=17)
+    judge = binding.IsingSearch.from_workload(w)
+    rates = []
+    for t in range(max_steps):
+        before = [lr.get_search(k) for k in range(L)]
+        for k, (bb, bE, bf) in enumerate(before):
+            judge.set_search(k, bb, bf)
+        active = lr.step()
+        judge.step()
+        for k, (bb, bE, bf) in enumerate(before):
+            if bf.sum() == 0:
+                continue   # a full step, or a search that has stopped
+            jb, _, _ = judge.get_search(k)
+            gb, _, _ = lr.get_search(k)
+            got = {x.tobytes() for x in gb}
+            rates.append(float(np.mean([x.tobytes() not in got for x in jb])))
+        if active == 0:
+            break
+    lr.destroy()
+    judge.destroy()
+    return {"mean": float(np.mean(rates)) if rates else None, "judged_search_steps": len(rates)}
+
+
+def measure_learned(binding, torch, w, params, steps):
+    """Complete passes of the learned form, and of the plain form on the same instances."""
+    out = {}
+    for form in ("plain", "learned"):
+        s = binding.IsingSearch.from_workload(w, timing=1, form=FORM_CODES[form])
+        if form == "learned":
+            s.set_scorer(binding.SCORER_NETWORK, params)
+        st0 = s.stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters = []
+        for k in range(steps):
+            s.reset()
+            it, stable = s.run()
+            s.get_states(0)
+            iters.append(it)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st1 = s.stats()
+        d = {k: st1[k] - st0[k] for k in st1 if isinstance(st1[k], (int, float))}
+        finals = [s.get_search(k)[0].tobytes() for k in range(len(w.instances) * w.L)]
+        E1 = [float(s.get_states(b)[1][0]) for b in range(len(w.instances))]
+        s.destroy()
+        out[form] = {"wall": wall, "d": d, "iters": iters, "finals": finals, "E1": E1}
+    lr, pl = out["learned"], out["plain"]
+    d = lr["d"]
+    learn_s = d["learn_ms"] / 1e3
+    flops = NET_FLOP_PER_PAIR * d["scored_pairs"]
+    return {
+        "instances": len(w.instances), "L": w.L, "M": w.M, "steps": steps,
+        "value": d["pair_evals"] / lr["wall"],
+        "unit": "exact pair-flip dE evals/s",
+        "scored_pairs_per_s": d["scored_pairs"] / lr["wall"],
+        "ms_per_step": 1e3 * lr["wall"] / steps,
+        "time_per_instance_s": lr["wall"] / steps / len(w.instances),
+        "plain_time_per_instance_s_same_sample": pl["wall"] / steps / len(w.instances),
+        "exact_pair_evals_per_pass": d["pair_evals"] / steps,
+        "plain_exact_pair_evals_per_pass": pl["d"]["pair_evals"] / steps,
+        "exact_evals_saved_factor": pl["d"]["pair_evals"] / max(d["pair_evals"], 1),
+        "iterations": lr["iters"], "plain_iterations": pl["iters"],
+        "full_enumeration_steps": d["fallbacks"], "ranked_states": d["ranked_states"], "retries": d["retries"],
+        "mean_E1": sum(lr["E1"]) / len(lr["E1"]), "plain_mean_E1": sum(pl["E1"]) / len(pl["E1"]),
+        "same_E1_as_plain": lr["E1"] == pl["E1"],
+        "fraction_of_searches_ending_unlike_plain": sum(a != b for a, b in zip(lr["finals"], pl["finals"])) /
+                                                     len(pl["finals"]),
+        "kernel_ms_per_step": {k: d[k + "_ms"] / steps for k in ("learn", "scan", "merge", "frontier", "prep")},
+        "roofline": {
+            "kernel": "k_learn", "bound": "mfma",
+            "achieved": flops / learn_s / 1e12 if learn_s > 0 else None,
+            "peak": BF16_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
+            "frac": flops / learn_s / BF16_MFMA_PEAK if learn_s > 0 else None,
+            "avg_launch_ms": d["learn_ms"] / max(d["scan_launches"], 1),
+            "flop_per_scored_pair": NET_FLOP_PER_PAIR,
+        },
+    }
 
 
 def measure(binding, torch, w, form, steps, warmup, batching, copy_gib):
@@ -176,8 +307,12 @@ def main():
                          "L=32, run as the batching form (persistent graph, autotuned tiles)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--forms", default="plain,split_bf16",
+    ap.add_argument("--forms", default="plain,split_bf16,learned",
                     help="comma list of forms to time; the first gives the headline value")
+    ap.add_argument("--learned-instances", type=int, default=2,
+                    help="instances of the workload the learned form runs on (a bounded sample)")
+    ap.add_argument("--judge-steps", type=int, default=40,
+                    help="ranking steps judged against full enumeration per scorer (one instance, L=16)")
     ap.add_argument("--extra-steps", type=int, default=1, help="timed passes for the forms after the first")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="after the timed region, copy this many GiB with torch (counter calibration)")
@@ -199,11 +334,37 @@ def main():
         w = workloads.c3_n600(n_instances=args.instances or 120)
     log(f"workload {w.name}: {len(w.instances)} instances, L={w.L}, M={w.M}")
     forms = [f for f in args.forms.split(",") if f] if not batching else ["plain"]
+    if forms[0] == "learned":
+        print("the learned form runs on a sample; put plain or split_bf16 first", file=sys.stderr)
+        sys.exit(2)
     digest = source_digest()
     results = {}
+    learned = None
     for fi, form in enumerate(forms):
         steps = args.steps if fi == 0 else max(1, args.extra_steps)
         warmup = args.warmup if fi == 0 else 0
+        if form == "learned":
+            import numpy as np
+            log("[learned] tracing and training the scoring network")
+            params, tinfo = train_network(binding, torch, workloads)
+            log(f"[learned] {tinfo}")
+            sample = workloads.c3_n600(n_instances=max(1, args.learned_instances))
+            log(f"[learned] timing {len(sample.instances)} instances")
+            learned = measure_learned(binding, torch, sample, params, max(1, args.extra_steps))
+            learned["training"] = tinfo
+            inst0 = sample.instances[0]
+            judge = {}
+            for name, sc, pr in (("network", binding.SCORER_NETWORK, params),
+                                 ("untrained_network", binding.SCORER_NETWORK, workloads.network_params(1).astype(np.float32)),
+                                 ("fields", binding.SCORER_FIELDS, None),
+                                 ("uniform", binding.SCORER_UNIFORM, None)):
+                log(f"[learned] judging the {name} ranking")
+                judge[name] = judge_miss_rate(binding, torch, inst0, 16, sample.M, sc, pr, args.judge_steps)
+            learned["miss_rate_vs_full_enumeration"] = judge
+            learned["miss_rate_note"] = ("ranking steps of instance 0, searches 0-15, first "
+                                         f"{args.judge_steps} steps: |S_full minus S_ranked| / |S_full|, S_full = the "
+                                         "exact step from the same kept set expanding the same states; K = 8N")
+            continue
         results[form] = measure(binding, torch, w, form, steps, warmup, batching, args.copy_gib if fi == 0 else 0)
     head = results[forms[0]]
 
@@ -251,6 +412,7 @@ def main():
         "roofline": roof,
         "forms": {f: {k: v for k, v in r.items() if k not in ("E1", "wall", "pairs")} for f, r in results.items()},
         "forms_same_E1": all(r["E1"] == head["E1"] for r in results.values()),
+        "learned": learned,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

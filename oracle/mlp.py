@@ -92,19 +92,6 @@ def adam_step(p, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def init_params(seed: int) -> np.ndarray:
-    """He-style random initialisation (the scale does not matter for the tests)."""
-    rng = np.random.default_rng(seed)
-    P = np.zeros(NPARAM)
-    P[OFF_W1:OFF_B1] = rng.normal(0, np.sqrt(2 / 4), 4 * H)
-    P[OFF_B1:OFF_W2] = rng.normal(0, 0.1, H)
-    P[OFF_W2:OFF_B2] = rng.normal(0, np.sqrt(2 / H), H * H)
-    P[OFF_B2:OFF_W3] = rng.normal(0, 0.1, H)
-    P[OFF_W3:OFF_B3] = rng.normal(0, np.sqrt(1 / H), H)
-    P[OFF_B3] = 0.0
-    return P
-
-
 def spins(x, N) -> np.ndarray:
     """s_i = 1 - 2 sigma_i of one state (W words)."""
     x = np.asarray(x, np.uint64).reshape(-1)

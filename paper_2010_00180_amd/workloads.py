@@ -155,3 +155,19 @@ def c5_learned(N: int, n_instances: int = 120, L: int = 64) -> Workload:
 def custom(Ns: Sequence[int], L: int, M: int, config: int = 9, dist: str = "sk", seed_offset: int = 0) -> Workload:
     inst = [make_instance(n, seed_for(config, seed_offset + k), L, dist) for k, n in enumerate(Ns)]
     return Workload(f"custom_{dist}", config, inst, M=M, L=L)
+
+
+# Initial parameters of the learned form's scoring network (4545 values in the
+# order W1[64][4], b1[64], W2[64][64], b2[64], w3[64], b3): a seeded He-style
+# draw, used as the starting point of training and as an untrained baseline.
+NET_PARAMS = 4 * 64 + 64 + 64 * 64 + 64 + 64 + 1
+
+
+def network_params(seed: int) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed_for(9, seed)))
+    P = np.zeros(NET_PARAMS)
+    o = 0
+    for size, std in ((4 * 64, np.sqrt(2 / 4)), (64, 0.1), (64 * 64, np.sqrt(2 / 64)), (64, 0.1), (64, np.sqrt(1 / 64))):
+        P[o:o + size] = rng.normal(0.0, std, size)
+        o += size
+    return P

@@ -75,7 +75,7 @@ def codes_of(ii, jj):
 
 
 def random_params(seed):
-    return mlp.init_params(seed).astype(np.float32)
+    return wl.network_params(seed).astype(np.float32)
 
 
 def index_of_states(bits):

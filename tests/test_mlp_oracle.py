@@ -25,7 +25,7 @@ def _samples(n, seed):
 
 @pytest.mark.parametrize("pos_w", [1.0, 7.5])
 def test_gradient_matches_central_differences(pos_w):
-    P = mlp.init_params(1)
+    P = workloads.network_params(1)
     X, y = _samples(40, 2)
     L, G = mlp.loss_grad(P, X, y, pos_w)
     rng = np.random.default_rng(3)
