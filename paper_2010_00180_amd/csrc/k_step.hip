@@ -37,21 +37,35 @@ __device__ inline double spin_of(const uint64_t* x, int i)
 }
 
 // Exclusive prefix sum of v over a block of 256 threads; returns the total.
+// Inclusive sums within each wave by shuffles, then the four wave totals.
 __device__ int block_exclusive_scan(int v, int* tmp, int& excl)
 {
-    const int t = threadIdx.x;
-    tmp[t] = v;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const int add = t >= off ? tmp[t - off] : 0;
-        __syncthreads();
-        tmp[t] += add;
-        __syncthreads();
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    int incl = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += u;
     }
-    excl = tmp[t] - v;
-    const int total = tmp[255];
+    if (lane == 63) tmp[w] = incl;
     __syncthreads();
+    int base = 0, total = 0;
+    for (int k = 0; k < 4; ++k) {
+        const int sk = tmp[k];
+        base += k < w ? sk : 0;
+        total += sk;
+    }
+    excl = base + incl - v;
+    __syncthreads();   // tmp is reused by the next call
     return total;
+}
+
+// Within one wave, LDS accesses complete in program order, so stages of a
+// sort that stay inside the wave's own elements need no block barrier.
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // ------------------------------------------------------------------ k_step_begin
@@ -70,11 +84,17 @@ __global__ void k_step_begin(Layout lay, int retry_mode)
 }
 
 // ------------------------------------------------------------------ bitonic sort of (key, idx) in LDS
+// Blocks of 256 threads.  Pair p of a stage with distance j touches elements
+// 2j floor(p/j) + p%j and that plus j; for j <= 64 the pairs of one wave
+// (p in 64w + 256m .. +63) stay inside element blocks 128(w + 4m) .. +127,
+// so only stages with j >= 128 exchange data between waves.
 template <class Less>
 __device__ void bitonic_sort(double* key, uint32_t* idx, int n2, const Less& less)
 {
+    __syncthreads();
     for (int k = 2; k <= n2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 128) __syncthreads();
             for (int t = threadIdx.x; t < (n2 >> 1); t += blockDim.x) {
                 const int i = 2 * j * (t / j) + (t % j);
                 const int l = i + j;
@@ -85,9 +105,11 @@ __device__ void bitonic_sort(double* key, uint32_t* idx, int n2, const Less& les
                     const uint32_t ti = idx[i]; idx[i] = idx[l]; idx[l] = ti;
                 }
             }
-            __syncthreads();
+            if (j >= 128) __syncthreads();
+            else wave_sync();
         }
     }
+    __syncthreads();
 }
 
 struct PlainLess {
@@ -116,6 +138,100 @@ __device__ inline int pow2_at_least(int n)
 // pilots p, q are the same state iff x_p xor x_q equals the symmetric
 // difference of their flip sets, which is checked exactly from the pilots'
 // words, so the pool's M-th distinct energy is a valid cut.
+// Sorts by (value, index) the shortest prefix of the (value, index) order of
+// n elements that holds at least `need` of them, into key/idx[0..cnt), and
+// returns cnt.  A 256-bin histogram over [min, max] finds the prefix: every
+// value of a bin lies below every value of a later bin, so whole bins form a
+// prefix of the order.  get(k, v, id) yields element k.  Block of 256 threads.
+struct PrefixShared {
+    double red[8];
+    int hist[256];
+    int bstar, cnt, fill;
+};
+
+template <class Get>
+__device__ int sort_prefix(const Get& get, int n, int need, double* key, uint32_t* idx, PrefixShared& ps)
+{
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    double lo = INFINITY, hi = -INFINITY;
+    for (int k = t; k < n; k += blockDim.x) {
+        double v;
+        uint32_t id;
+        get(k, v, id);
+        lo = fmin(lo, v);
+        hi = fmax(hi, v);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, off, 64));
+        hi = fmax(hi, __shfl_xor(hi, off, 64));
+    }
+    if (lane == 0) {
+        ps.red[w] = lo;
+        ps.red[4 + w] = hi;
+    }
+    ps.hist[t] = 0;
+    if (t == 0) ps.fill = 0;
+    __syncthreads();
+    lo = fmin(fmin(ps.red[0], ps.red[1]), fmin(ps.red[2], ps.red[3]));
+    hi = fmax(fmax(ps.red[4], ps.red[5]), fmax(ps.red[6], ps.red[7]));
+    const double scale = hi > lo ? 256.0 / (hi - lo) : 0.0;
+    auto bin_of = [&](double v) -> int {
+        const int k = (int)((v - lo) * scale);
+        return k < 0 ? 0 : (k > 255 ? 255 : k);
+    };
+    for (int k = t; k < n; k += blockDim.x) {
+        double v;
+        uint32_t id;
+        get(k, v, id);
+        atomicAdd(&ps.hist[bin_of(v)], 1);
+    }
+    __syncthreads();
+    if (t < 64) {
+        // lane l holds bins 4l .. 4l+3 (lowest first)
+        int c[4], loc = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            c[u] = ps.hist[4 * t + u];
+            loc += c[u];
+        }
+        int incl = loc;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(incl, off, 64);
+            if (t >= off) incl += v;
+        }
+        int run = incl - loc;
+        if (run < need && need <= incl) {
+            for (int u = 0; u < 4; ++u) {
+                run += c[u];
+                if (run >= need) {
+                    ps.bstar = 4 * t + u;
+                    ps.cnt = run;
+                    break;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int bstar = ps.bstar, cnt = ps.cnt;
+    for (int k = t; k < n; k += blockDim.x) {
+        double v;
+        uint32_t id;
+        get(k, v, id);
+        if (bin_of(v) <= bstar) {
+            const int pos = atomicAdd(&ps.fill, 1);
+            key[pos] = v;
+            idx[pos] = id;
+        }
+    }
+    const int n2 = pow2_at_least(cnt < 2 ? 2 : cnt);
+    for (int k = cnt + t; k < n2; k += blockDim.x) {
+        key[k] = INFINITY;
+        idx[k] = 0xFFFFFFFFu;
+    }
+    bitonic_sort(key, idx, n2, PlainLess());
+    return cnt;
+}
+
 constexpr int NPILOT = 4;
 constexpr int PK = 32;                       // lightest sites per pilot
 constexpr int PCAND = PK * (PK + 1) / 2;     // candidates per pilot
@@ -139,6 +255,7 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
     __shared__ int dsites[NPILOT][NPILOT][5];   // [0] = count (5 = farther than 4 flips)
     __shared__ double aK[PK];
     __shared__ int iK[PK];
+    __shared__ PrefixShared ps;
     const int s = blockIdx.x;
     const int b = s / lay.L;
     const int M = lay.M;
@@ -221,17 +338,15 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
         dsites[p][q][0] = n;
     }
     const double* Jb = J4 + lay.joff[b];
-    const int n2 = pow2_at_least(N);
     for (int p = 0; p < np; ++p) {
         const uint64_t* xp = lay.bits + (q0 + pslot[p]) * lay.Wmax;
         const double* Fp = lay.F + (q0 + pslot[p]) * lay.Npmax;
         const double Ep = lay.E[q0 + pslot[p]];
-        for (int i = threadIdx.x; i < n2; i += blockDim.x) {
-            key[i] = i < N ? -2.0 * spin_of(xp, i) * Fp[i] : INFINITY;
-            idx[i] = (uint32_t)i;
-        }
-        __syncthreads();
-        bitonic_sort(key, idx, n2, PlainLess());
+        // the lightest sites (lowest a_i, then lowest i) in key/idx[0 ..)
+        sort_prefix([&](int i, double& v, uint32_t& id) {
+            v = -2.0 * spin_of(xp, i) * Fp[i];
+            id = (uint32_t)i;
+        }, N, ranked ? nc : K, key, idx, ps);
         if ((int)threadIdx.x < K) {
             aK[threadIdx.x] = key[threadIdx.x];
             iK[threadIdx.x] = (int)idx[threadIdx.x];
@@ -261,21 +376,22 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
         }
         __syncthreads();
     }
-    // pool: sort by energy, drop duplicates, take the M-th distinct
+    // pool: sort a prefix by energy, drop duplicates, take the M-th distinct
+    // (a prefix with fewer than M distinct states is widened)
     const int npool = np * nc;
-    const int n2p = pow2_at_least(npool);
-    for (int t = threadIdx.x; t < n2p; t += blockDim.x) {
-        key[t] = t < npool ? pE[t] : INFINITY;
-        idx[t] = t < npool ? pid[t] : 0xFFFFFFFFu;
-    }
-    __syncthreads();
-    bitonic_sort(key, idx, n2p, PlainLess());
     double theta = INFINITY;
     int seen = 0;
-    for (int c0 = 0; c0 < npool && seen < M; c0 += 256) {
+    for (int need = M + 64 < npool ? M + 64 : npool;; need = 2 * need < npool ? 2 * need : npool) {
+    const int cnt = sort_prefix([&](int k, double& v, uint32_t& id) {
+        v = pE[k];
+        id = pid[k];
+    }, npool, need, key, idx, ps);
+    theta = INFINITY;
+    seen = 0;
+    for (int c0 = 0; c0 < cnt && seen < M; c0 += 256) {
         const int t = c0 + threadIdx.x;
         int isnew = 0;
-        if (t < npool) {
+        if (t < cnt) {
             isnew = 1;
             const uint32_t id = idx[t];
             int fa[2], na;
@@ -318,6 +434,8 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
         if (seen < M && seen + tot >= M) theta = key[tmp[0]];
         __syncthreads();
         seen += tot;
+    }
+    if (seen >= M || cnt == npool) break;
     }
     if (threadIdx.x == 0) lay.cut[s] = theta < ecut ? theta : ecut;
 }
@@ -629,9 +747,10 @@ __global__ __launch_bounds__(64) void k_scan(Layout lay, const double* __restric
 #pragma unroll
                         for (int u = 0; u < 8; ++u) a8[u] = aj[g + u];
                         // running minimum over the group (two chains); NaN pairs drop out of fmin
-                        double mn0 = INFINITY, mn1 = INFINITY;
+                        double mn0 = fma(si, __longlong_as_double((long long)Jb[g]), a8[0]);
+                        double mn1 = fma(si, __longlong_as_double((long long)Jb[g + 1]), a8[1]);
 #pragma unroll
-                        for (int u = 0; u < 8; ++u) {
+                        for (int u = 2; u < 8; ++u) {
                             const double x = fma(si, __longlong_as_double((long long)Jb[g + u]), a8[u]);
                             if (u & 1) mn1 = fmin(mn1, x);
                             else mn0 = fmin(mn0, x);
@@ -746,8 +865,10 @@ struct StateLess {
 template <class Less>
 __device__ void bitonic_sort3(double* key, uint32_t* idx, uint64_t* zk, int n2, const Less& less)
 {
+    __syncthreads();
     for (int k = 2; k <= n2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 128) __syncthreads();
             for (int t = threadIdx.x; t < (n2 >> 1); t += blockDim.x) {
                 const int i = 2 * j * (t / j) + (t % j);
                 const int l = i + j;
@@ -760,9 +881,11 @@ __device__ void bitonic_sort3(double* key, uint32_t* idx, uint64_t* zk, int n2, 
                     const uint64_t tz = zk[i]; zk[i] = zk[l]; zk[l] = tz;
                 }
             }
-            __syncthreads();
+            if (j >= 128) __syncthreads();
+            else wave_sync();
         }
     }
+    __syncthreads();
 }
 
 template <class Src>
