@@ -7,9 +7,10 @@
 // The single flips of ranked states are offered here too, under the same
 // per-state bound (below).
 //
-// k_learn: one block (4 waves) per ranked state.  A wave scores 16 pairs
-// (row i, columns j..j+15) per pass of the network on the bf16 matrix cores
-// (v_mfma_f32_16x16x32_bf16, FP32 accumulation):
+// k_learn: one block (4 waves) per ranked state.  A wave scores four blocks of
+// 16 pairs (row i, columns j..j+15) per pass, one block per lane group, with
+// the network on the bf16 matrix cores (v_mfma_f32_16x16x32_bf16, FP32
+// accumulation), per block:
 //   layer 1  4 MFMAs: rows = 64 hidden units, K = 8 feature slots
 //            (f_i, f_j, Jn, ss, 1 for the bias, zeros), columns = 16 pairs
 //   layer 2  8 MFMAs: 64 x 64, the bias in the accumulator
@@ -59,44 +60,55 @@ __device__ inline uint32_t ord_score(float z)
 
 __device__ inline __bf16 bfb(uint16_t u) { return __builtin_bit_cast(__bf16, u); }
 
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+// two floats to one packed bf16 pair (one v_cvt_pk_bf16_f32, nearest even)
+__device__ inline unsigned int pack_bf16(float a, float b)
+{
+    const v2f f = {a, b};
+    return __builtin_bit_cast(unsigned int, __builtin_convertvector(f, v2bf));
+}
+
 __device__ inline v8bf relu_pack(v4f a, v4f b)
 {
-    v8bf x;
-    x[0] = (__bf16)a[0];
-    x[1] = (__bf16)a[1];
-    x[2] = (__bf16)a[2];
-    x[3] = (__bf16)a[3];
-    x[4] = (__bf16)b[0];
-    x[5] = (__bf16)b[1];
-    x[6] = (__bf16)b[2];
-    x[7] = (__bf16)b[3];
+    const v4u u = {pack_bf16(a[0], a[1]), pack_bf16(a[2], a[3]), pack_bf16(b[0], b[1]), pack_bf16(b[2], b[3])};
     // relu on the bf16 bit patterns: a set sign bit is a negative int16
-    v8s s = __builtin_bit_cast(v8s, x);
+    v8s s = __builtin_bit_cast(v8s, u);
     const v8s zero = {0, 0, 0, 0, 0, 0, 0, 0};
     s = __builtin_elementwise_max(s, zero);
     return __builtin_bit_cast(v8bf, s);
 }
 
+// The network's operands, laid out so that one pass scores four blocks of 16
+// pairs: lane group q (lanes 16q .. 16q+15) holds the features of block q in
+// K slots 8q .. 8q+7, so layer 1 of block q uses a copy of W1 placed in those
+// slots (a1[q]), and the output of block q is written to row 4q (a3[q]),
+// which is register 0 of lane group q.
 struct Net {
-    v8bf a1[4];
-    v8bf a2[4][2];
-    v4f c2[4];
-    v8bf a3[2];
-    v4f c3;
+    v8bf a1[4][4];   // [q][m]: rows 16m .. 16m+15 of (W1 | b1), in lane group q
+    v8bf a2[4][2];   // [output tile][K-step], hidden index permuted
+    v4f c2[4];       // b2 in the accumulator layout
+    v8bf a3[4][2];   // [q][K-step]: w3 in row 4q
+    v4f c3;          // b3 in register 0 of every lane
 };
 
-// The network's operands in this lane's registers (bf16 rounded to nearest even).
+// bf16 copies (nearest even) of the parameters in this lane's registers.
 __device__ inline void load_net(const float* __restrict__ P, Net& n)
 {
-    const int l = (int)(lr_lane() & 63u), q = l >> 4, r = l & 15;
+    const int l = (int)(lr_lane() & 63u), g = l >> 4, r = l & 15;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+    for (int q = 0; q < 4; ++q) {
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            float v = 0.f;
-            if (q == 0 && t < 4) v = P[MLP_W1 + (16 * m + r) * 4 + t];
-            if (q == 0 && t == 4) v = P[MLP_B1 + 16 * m + r];
-            n.a1[m][t] = (__bf16)v;
+        for (int m = 0; m < 4; ++m) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                float v = 0.f;
+                if (g == q && t < 4) v = P[MLP_W1 + (16 * m + r) * 4 + t];
+                if (g == q && t == 4) v = P[MLP_B1 + 16 * m + r];
+                n.a1[q][m][t] = (__bf16)v;
+            }
         }
     }
 #pragma unroll
@@ -105,45 +117,53 @@ __device__ inline void load_net(const float* __restrict__ P, Net& n)
         for (int kk = 0; kk < 2; ++kk) {
 #pragma unroll
             for (int t = 0; t < 8; ++t)
-                n.a2[o][kk][t] = (__bf16)P[MLP_W2 + (16 * o + r) * MLP_H + 32 * kk + 16 * (t >> 2) + 4 * q + (t & 3)];
+                n.a2[o][kk][t] = (__bf16)P[MLP_W2 + (16 * o + r) * MLP_H + 32 * kk + 16 * (t >> 2) + 4 * g + (t & 3)];
         }
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) n.c2[o][rr] = P[MLP_B2 + 16 * o + 4 * q + rr];
+        for (int rr = 0; rr < 4; ++rr) n.c2[o][rr] = P[MLP_B2 + 16 * o + 4 * g + rr];
     }
 #pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
+    for (int q = 0; q < 4; ++q) {
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const float w = P[MLP_W3 + 32 * kk + 16 * (t >> 2) + 4 * q + (t & 3)];
-            n.a3[kk][t] = (__bf16)(r == 0 ? w : 0.f);
+        for (int kk = 0; kk < 2; ++kk) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const float w = P[MLP_W3 + 32 * kk + 16 * (t >> 2) + 4 * g + (t & 3)];
+                n.a3[q][kk][t] = (__bf16)(r == 4 * q ? w : 0.f);
+            }
         }
     }
-    const float b3 = P[MLP_B3];
-    n.c3[0] = q == 0 ? b3 : 0.f;
+    n.c3[0] = P[MLP_B3];
     n.c3[1] = 0.f;
     n.c3[2] = 0.f;
     n.c3[3] = 0.f;
 }
 
-// Logit of the pair in column l%16 (valid in lanes 0..15).
-__device__ inline float net_score(const Net& n, v8bf x)
+// Logits of four blocks: lane l gets the logit of pair l%16 of block l/16.
+__device__ inline float net_score4(const Net& n, v8bf x)
 {
     const v4f z4 = {0.f, 0.f, 0.f, 0.f};
-    const v4f d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a1[0], x, z4, 0, 0, 0);
-    const v4f d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a1[1], x, z4, 0, 0, 0);
-    const v4f d2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a1[2], x, z4, 0, 0, 0);
-    const v4f d3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a1[3], x, z4, 0, 0, 0);
-    const v8bf h0 = relu_pack(d0, d1), h1 = relu_pack(d2, d3);
-    v4f e[4];
+    const int g = (int)(lr_lane() & 63u) >> 4;
+    float z = 0.f;
 #pragma unroll
-    for (int o = 0; o < 4; ++o) {
-        e[o] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a2[o][0], h0, n.c2[o], 0, 0, 0);
-        e[o] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a2[o][1], h1, e[o], 0, 0, 0);
+    for (int q = 0; q < 4; ++q) {
+        const v4f d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a1[q][0], x, z4, 0, 0, 0);
+        const v4f d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a1[q][1], x, z4, 0, 0, 0);
+        const v4f d2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a1[q][2], x, z4, 0, 0, 0);
+        const v4f d3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a1[q][3], x, z4, 0, 0, 0);
+        const v8bf h0 = relu_pack(d0, d1), h1 = relu_pack(d2, d3);
+        v4f e[4];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            e[o] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a2[o][0], h0, n.c2[o], 0, 0, 0);
+            e[o] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a2[o][1], h1, e[o], 0, 0, 0);
+        }
+        const v8bf g0 = relu_pack(e[0], e[1]), g1 = relu_pack(e[2], e[3]);
+        v4f out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a3[q][0], g0, n.c3, 0, 0, 0);
+        out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a3[q][1], g1, out, 0, 0, 0);
+        z = g == q ? out[0] : z;
     }
-    const v8bf g0 = relu_pack(e[0], e[1]), g1 = relu_pack(e[2], e[3]);
-    v4f out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a3[0], g0, n.c3, 0, 0, 0);
-    out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a3[1], g1, out, 0, 0, 0);
-    return out[0];
+    return z;
 }
 
 struct LrShared {
@@ -328,30 +348,46 @@ __global__ __launch_bounds__(256) void k_learn(Layout lay)
         const uint16_t* Jn = lay.Jn16 + lay.joff[b];
         for (long long r = 0; r < rounds; ++r) {
             const uint64_t thr = sh.thr;
-            for (int u = 0; u < LR_R; ++u) {
-                const long long g = (long long)LR_WAVES * (r * LR_R + u) + wave;
-                if (g >= NB) break;
-                const int j = gj + (int)(lane & 15u);
-                const bool valid = lane < 16 && j < N;
+            for (int u = 0; u < LR_R; u += 4) {
+                // this wave's next four blocks, one per lane group
+                const long long g0 = (long long)LR_WAVES * (r * LR_R + u) + wave;
+                if (g0 >= NB) break;
+                int bi[4], bj[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    bi[q] = gi;
+                    bj[q] = gj;
+                    for (int v = 0; v < LR_WAVES; ++v) {
+                        gj += 16;
+                        if (gj >= N) { ++gi; gj = gi + 1; }
+                    }
+                }
+                const int q = (int)(lane >> 4);
+                const bool inblk = g0 + (long long)LR_WAVES * q < NB;
+                int mgi = q == 0 ? bi[0] : q == 1 ? bi[1] : q == 2 ? bi[2] : bi[3];
+                int mgj = q == 0 ? bj[0] : q == 1 ? bj[1] : q == 2 ? bj[2] : bj[3];
+                if (!inblk) { mgi = 0; mgj = 1; }   // in range; its keys are dropped
+                const int j = mgj + (int)(lane & 15u);
+                const bool valid = inblk && j < N;
                 const int jc = j < N ? j : N - 1;
-                const uint32_t code = (uint32_t)gi | ((uint32_t)jc << 16);
+                const int ic = mgi < N ? mgi : 0;
+                const uint32_t code = (uint32_t)ic | ((uint32_t)jc << 16);
                 float z;
                 if (lay.scorer == 0) {
-                    const bool neg = (((sbits[gi >> 6] >> (gi & 63)) ^ (sbits[jc >> 6] >> (jc & 63))) & 1ull) != 0;
-                    const bool lo = lane < 16;
+                    const bool neg = (((sbits[ic >> 6] >> (ic & 63)) ^ (sbits[jc >> 6] >> (jc & 63))) & 1ull) != 0;
                     const __bf16 zb = bfb(0);
                     v8bf x;
-                    x[0] = lo ? bfb(f16s[gi]) : zb;
-                    x[1] = lo ? bfb(f16s[jc]) : zb;
-                    x[2] = lo ? bfb(Jn[(size_t)gi * Np + jc]) : zb;
-                    x[3] = lo ? bfb(neg ? (uint16_t)0xBF80 : (uint16_t)0x3F80) : zb;
-                    x[4] = lo ? bfb(0x3F80) : zb;
+                    x[0] = bfb(f16s[ic]);
+                    x[1] = bfb(f16s[jc]);
+                    x[2] = bfb(Jn[(size_t)ic * Np + jc]);
+                    x[3] = bfb(neg ? (uint16_t)0xBF80 : (uint16_t)0x3F80);
+                    x[4] = bfb(0x3F80);
                     x[5] = zb;
                     x[6] = zb;
                     x[7] = zb;
-                    z = net_score(net, x);
+                    z = net_score4(net, x);
                 } else if (lay.scorer == 1) {
-                    z = (float)(-0.5 * (A[gi] + A[jc]));
+                    z = (float)(-0.5 * (A[ic] + A[jc]));
                 } else {
                     z = (float)(mix64(zp + 0x9E3779B97F4A7C15ull * ((uint64_t)code + 1ull)) >> 40) *
                         5.9604644775390625e-08f;
@@ -364,10 +400,6 @@ __global__ __launch_bounds__(256) void k_learn(Layout lay)
                     if (lane == 0) base = atomicAdd(&sh.cnt, __popcll(m));
                     base = __shfl(base, 0, 64);
                     if (pass) cand[base + (int)lr_mbcnt(m)] = key;
-                }
-                for (int v = 0; v < LR_WAVES; ++v) {
-                    gj += 16;
-                    if (gj >= N) { ++gi; gj = gi + 1; }
                 }
             }
             __syncthreads();
