@@ -219,7 +219,9 @@ __device__ inline long long tiles64(int N)
     return nb * (nb + 1) / 2;
 }
 
-__global__ __launch_bounds__(64) void k_scan32(Layout lay, const float* __restrict__ J32,
+// At most 128 VGPRs, so that four waves share each SIMD: the loop is bound by
+// latency, and occupancy decides its speed.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_scan32(Layout lay, const float* __restrict__ J32,
                                                const double* __restrict__ J4,
                                                const float* __restrict__ A32,
                                                const float* __restrict__ RR32,
@@ -322,9 +324,10 @@ __global__ __launch_bounds__(64) void k_scan32(Layout lay, const float* __restri
                         float a8[8];
 #pragma unroll
                         for (int u = 0; u < 8; ++u) a8[u] = aj[g + u];
-                        float mn0 = INFINITY, mn1 = INFINITY;
+                        float mn0 = fmaf(si, __uint_as_float(Jb[g]), a8[0]);
+                        float mn1 = fmaf(si, __uint_as_float(Jb[g + 1]), a8[1]);
 #pragma unroll
-                        for (int u = 0; u < 8; ++u) {
+                        for (int u = 2; u < 8; ++u) {
                             const float x = fmaf(si, __uint_as_float(Jb[g + u]), a8[u]);
                             if (u & 1) mn1 = fminf(mn1, x);
                             else mn0 = fminf(mn0, x);
