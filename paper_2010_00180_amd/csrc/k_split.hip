@@ -158,7 +158,7 @@ __global__ __launch_bounds__(256) void k_prep32(Layout lay, const long long* __r
             double a = 0.0;
             if (i < N) a = -2.0 * spin_d(x, i) * F[i];
             amax = fmax(amax, fabs(a));
-            A[i] = a;
+            if (lay.tr_feat) A[i] = a;   // FP64 a is read back only by trace capture
             A32[i] = i < N ? (float)(from_ft ? -2.0 * spin_d(x, i) * (double)Ft[i] : a) : 0.f;
             const double Ec = Em + a;
             const bool hit = i < N && Ec <= c;
@@ -184,7 +184,8 @@ __global__ __launch_bounds__(256) void k_prep32(Layout lay, const long long* __r
         const double delta = 4.0 * u * (lay.ybound[b] + amax) + (from_ft ? 2.0 * lay.ebf[b] : 0.0);
         for (int i0 = 0; i0 < Np; i0 += 64) {
             const int i = i0 + lane;
-            RR[i] = i < N ? __double2float_ru(T - A[i] + delta) : -INFINITY;
+            const double a = i < N ? -2.0 * spin_d(x, i) * F[i] : 0.0;
+            RR[i] = i < N ? __double2float_ru(T - a + delta) : -INFINITY;
         }
     }
 }
@@ -225,7 +226,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                                                const double* __restrict__ J4,
                                                const float* __restrict__ A32,
                                                const float* __restrict__ RR32,
-                                               const double* __restrict__ A64,
+                                               const double* __restrict__ Fpool,
                                                const FrRec* __restrict__ recs,
                                                const uint64_t* __restrict__ fbits,
                                                const long long* __restrict__ iprefix)
@@ -334,11 +335,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                         }
                         if (__builtin_amdgcn_ballot_w64(fminf(mn0, mn1) <= rrt)) {
                             // admitted pairs: exact FP64 re-score, then record
-                            const size_t fe = (size_t)b * lay.fmax + g0 + k;
                             const double Tm = sT[k];
-                            const double* Arow = A64 + fe * Npm;
-                            const double ai = row < N ? Arow[row] : 0.0;
+                            // exact a = -2 s F from the state's local fields
+                            const double* Frow = Fpool + (size_t)sCode[k] * lay.Npmax;
                             const double sid = (double)si;
+                            const double ai = row < N ? -2.0 * sid * Frow[row] : 0.0;
 #pragma unroll
                             for (int u = 0; u < 8; ++u) {
                                 const float xt = fmaf(si, __uint_as_float(Jb[g + u]), a8[u]);
@@ -348,7 +349,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                                 if (adm) {
                                     const int col = col0 + g + u;
                                     const double sj = ((wj >> (g + u)) & 1ull) ? -1.0 : 1.0;
-                                    x = Arow[col] + sid * sj * J4[lay.joff[b] + (size_t)row * Np + col];
+                                    x = -2.0 * sj * Frow[col] + sid * sj * J4[lay.joff[b] + (size_t)row * Np + col];
                                     keep = ai + x <= Tm;
                                     if (!keep) ++rejected;
                                 }
@@ -428,7 +429,7 @@ hipError_t launch_scan32(const Layout& lay, int scan_grid, hipStream_t st)
     long long* iprefix = lay.item_prefix + 2 * (lay.B + 1);
     hipLaunchKernelGGL(k_plan32, dim3(1), dim3(1024), 0, st, lay, iprefix);
     hipLaunchKernelGGL(k_scan32, dim3(scan_grid), dim3(64), 0, st, lay, lay.J32, lay.J4, (const float*)lay.A32,
-                       (const float*)lay.RR32, (const double*)lay.A, (const FrRec*)lay.rec,
+                       (const float*)lay.RR32, (const double*)lay.F, (const FrRec*)lay.rec,
                        (const uint64_t*)lay.fbits, (const long long*)iprefix);
     return hipGetLastError();
 }
