@@ -348,13 +348,14 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     ALLOC(hd->d_scb, n_inst);
     float* dJ32 = nullptr;
     uint16_t *dJhi = nullptr, *dJlo = nullptr;
-    double *dyb = nullptr, *debf = nullptr;
+    double *dyb = nullptr, *debf = nullptr, *dab = nullptr;
     if (cfg->form == ISING_FORM_SPLIT_BF16) {
         ALLOC(dJ32, (size_t)jtot);
         ALLOC(dJhi, (size_t)jtot);
         ALLOC(dJlo, (size_t)jtot);
         ALLOC(dyb, n_inst);
         ALLOC(debf, n_inst);
+        ALLOC(dab, n_inst);
         ALLOC(lay.Ft, S * lay.Npmax);
         ALLOC(lay.A32, (size_t)n_inst * lay.fmax * lay.Npmax);
         ALLOC(lay.RR32, (size_t)n_inst * lay.fmax * lay.Npmax);
@@ -399,6 +400,7 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     lay.Jlo = dJlo;
     lay.ybound = dyb;
     lay.ebf = debf;
+    lay.abound = dab;
     lay.Jn16 = dJn;
     lay.mlp = hd->d_mlp;
     lay.scorer = 0;
@@ -456,7 +458,7 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
         cp(hd->d_scb, hd->sc_h.data(), sizeof(int) * n_inst);
         std::vector<float> J32h;
         std::vector<uint16_t> hih, loh;
-        std::vector<double> ybh, ebfh;
+        std::vector<double> ybh, ebfh, abh;
         if (cfg->form == ISING_FORM_SPLIT_BF16) {
             // fl32(4J), bf16 hi = RN(4J), lo = RN(4J - hi); per instance max |4J| and the
             // bound on |F~ - F|: split residual |4J - hi - lo| <= 2^-15 |4J| (two roundings to 8
@@ -479,6 +481,7 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
             loh.assign((size_t)jtot, 0);
             ybh.assign(n_inst, 0.0);
             ebfh.assign(n_inst, 0.0);
+            abh.assign(n_inst, 0.0);
             for (int b = 0; b < n_inst; ++b) {
                 const int n = N[b], np = hd->Npad[b];
                 double emax = 0.0;
@@ -497,6 +500,8 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
                     const double e = (std::ldexp(1.0, -15) * 4.0 * 0.25 + 2.1 * n * std::ldexp(1.0, -24)) * R +
                                      std::ldexp(1.0, -23) * (std::fabs(h[b][i]) + R);
                     emax = std::max(emax, e);
+                    // |a_i| = 2 |F_i| and |F_i| <= |h_i| + sum_j |J_ij| in every state
+                    abh[b] = std::max(abh[b], 2.0 * (std::fabs(h[b][i]) + R));
                 }
                 ebfh[b] = emax;
             }
@@ -505,6 +510,7 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
             cp(dJlo, loh.data(), sizeof(uint16_t) * loh.size());
             cp(dyb, ybh.data(), sizeof(double) * n_inst);
             cp(debf, ebfh.data(), sizeof(double) * n_inst);
+            cp(dab, abh.data(), sizeof(double) * n_inst);
         }
         std::vector<uint16_t> jnh;
         if (cfg->form == ISING_FORM_LEARNED) {

@@ -101,6 +101,7 @@ struct Layout {
     const uint16_t* Jlo;     // per instance, bf16(4J - hi)
     const double* ybound;    // [B] max |4J_ij|
     const double* ebf;       // [B] bound on |F~ - F| of the bf16 hi+lo fields
+    const double* abound;    // [B] bound on |a_i| = 2 |F_i| <= 2 (|h_i| + sum_j |J_ij|) over all states
     float* Ft;               // [S][Npmax] F~ of the initial states (bf16 hi+lo GEMM, FP32 sums)
     float* A32;              // [B][fmax][Npmax] fl32(a_i)
     float* RR32;             // [B][fmax][Npmax] T - a_i + slack, rounded up to FP32

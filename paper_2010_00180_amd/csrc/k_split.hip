@@ -94,8 +94,9 @@ hipError_t launch_init_split(const Layout& lay, const uint64_t* d_x0, double* d_
 // ------------------------------------------------------------------ k_prep32
 // As the FP64 preparation, and also: fl32(a_i) for the FP32 scan (in the
 // first step from F~ of the bf16 GEMM) and the FP32 threshold
-// RR_i = round_up(T - a_i + delta), with delta = 4u (max|4J| + max|a|)
-// (+ 2 max|F~ - F| in the first step), u = 2^-24.  Then every pair with
+// RR_i = round_up(T - a_i + delta), with delta = 4u (max|4J| + A)
+// (+ 2 max|F~ - F| in the first step), u = 2^-24, where A bounds |a| over
+// every state of the instance (the proof needs only an upper bound).  Then every pair with
 // a_i + a_j + s_i s_j 4J_ij <= T also has fl32(fma(s_i, s_j fl32(4J_ij), fl32(a_j))) <= RR_i.
 __device__ inline double wave_max(double v)
 {
@@ -152,14 +153,16 @@ __global__ __launch_bounds__(256) void k_prep32(Layout lay, const long long* __r
             atomicAdd(&lay.ctr[CTR_PAIRS], (unsigned long long)N * (N - 1) / 2);
             atomicAdd(&lay.ctr[CTR_SINGLES], (unsigned long long)N);
         }
-        double amax = 0.0;
+        // slack of the FP32 threshold, from the instance's bound on |a|
+        const double u = 5.9604644775390625e-08;   // 2^-24
+        const double delta = 4.0 * u * (lay.ybound[b] + lay.abound[b]) + (from_ft ? 2.0 * lay.ebf[b] : 0.0);
         for (int i0 = 0; i0 < Np; i0 += 64) {
             const int i = i0 + lane;
             double a = 0.0;
             if (i < N) a = -2.0 * spin_d(x, i) * F[i];
-            amax = fmax(amax, fabs(a));
             if (lay.tr_feat) A[i] = a;   // FP64 a is read back only by trace capture
             A32[i] = i < N ? (float)(from_ft ? -2.0 * spin_d(x, i) * (double)Ft[i] : a) : 0.f;
+            RR[i] = i < N ? __double2float_ru(T - a + delta) : -INFINITY;
             const double Ec = Em + a;
             const bool hit = i < N && Ec <= c;
             const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
@@ -178,14 +181,6 @@ __global__ __launch_bounds__(256) void k_prep32(Layout lay, const long long* __r
                     }
                 }
             }
-        }
-        amax = wave_max(amax);
-        const double u = 5.9604644775390625e-08;   // 2^-24
-        const double delta = 4.0 * u * (lay.ybound[b] + amax) + (from_ft ? 2.0 * lay.ebf[b] : 0.0);
-        for (int i0 = 0; i0 < Np; i0 += 64) {
-            const int i = i0 + lane;
-            const double a = i < N ? -2.0 * spin_d(x, i) * F[i] : 0.0;
-            RR[i] = i < N ? __double2float_ru(T - a + delta) : -INFINITY;
         }
     }
 }

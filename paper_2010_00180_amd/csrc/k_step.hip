@@ -1050,42 +1050,61 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             lo = fmin(lo, e);
             hi = fmax(hi, e);
         }
-        lo = block_reduce(lo, red, false);
-        hi = block_reduce(hi, red, true);
+        for (int off = 32; off > 0; off >>= 1) {
+            lo = fmin(lo, __shfl_xor(lo, off, 64));
+            hi = fmax(hi, __shfl_xor(hi, off, 64));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            red[threadIdx.x >> 6] = lo;
+            red[4 + (threadIdx.x >> 6)] = hi;
+        }
+        for (int k = threadIdx.x; k < NBIN; k += blockDim.x) hist[k] = 0;
+        if (threadIdx.x == 0) tmp[1] = 0;
+        __syncthreads();
+        lo = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+        hi = fmax(fmax(red[4], red[5]), fmax(red[6], red[7]));
         const double scale = hi > lo ? (double)NBIN / (hi - lo) : 0.0;
         auto bin_of = [&](double e) -> int {
             const int k = (int)((e - lo) * scale);
             return k < 0 ? 0 : (k >= NBIN ? NBIN - 1 : k);
         };
-        for (int k = threadIdx.x; k < NBIN; k += blockDim.x) hist[k] = 0;
-        __syncthreads();
         for (int c = threadIdx.x; c < n; c += blockDim.x) atomicAdd(&hist[bin_of(candE(c))], 1);
         __syncthreads();
-        // first bin at which the running count reaches the target (4 bins per thread)
-        int local = 0;
-        for (int k = 0; k < NBIN / 256; ++k) local += hist[threadIdx.x * (NBIN / 256) + k];
-        int excl;
-        block_exclusive_scan(local, tmp, excl);
-        int run = excl, found = -1;
-        for (int k = 0; k < NBIN / 256 && found < 0; ++k) {
-            run += hist[threadIdx.x * (NBIN / 256) + k];
-            if (run >= target && run - hist[threadIdx.x * (NBIN / 256) + k] < target)
-                found = threadIdx.x * (NBIN / 256) + k;
+        // the first bin at which the running count reaches the target
+        // (wave 0, 16 bins per lane, lowest first)
+        if (threadIdx.x < 64) {
+            constexpr int PER = NBIN / 64;
+            const int l = threadIdx.x;
+            int loc = 0;
+            for (int k = 0; k < PER; ++k) loc += hist[PER * l + k];
+            int incl = loc;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int v = __shfl_up(incl, off, 64);
+                if (l >= off) incl += v;
+            }
+            int run = incl - loc;
+            if (run < target && target <= incl) {
+                for (int k = 0; k < PER; ++k) {
+                    run += hist[PER * l + k];
+                    if (run >= target) {
+                        tmp[0] = PER * l + k;
+                        break;
+                    }
+                }
+            }
         }
-        if (found >= 0) tmp[0] = found;
         __syncthreads();
         const int bmax = tmp[0];
-        __syncthreads();
-        // compact the candidates of bins <= bmax (if they fit the sort arrays)
-        int np = 0;
-        for (int c0 = 0; c0 < n; c0 += 256) {
-            const int c = c0 + threadIdx.x;
-            const int in = (c < n && bin_of(candE(c)) <= bmax) ? 1 : 0;
-            int ex;
-            const int tot = block_exclusive_scan(in, tmp, ex);
-            if (in && np + ex < MERGE_CH) load_cand(c, np + ex);
-            np += tot;
+        // the candidates of bins <= bmax, in any order (they are sorted next),
+        // if they fit the sort arrays
+        for (int c = threadIdx.x; c < n; c += blockDim.x) {
+            if (bin_of(candE(c)) <= bmax) {
+                const int pos = atomicAdd(&tmp[1], 1);
+                if (pos < MERGE_CH) load_cand(c, pos);
+            }
         }
+        __syncthreads();
+        const int np = tmp[1];
         __syncthreads();
         if (np <= MERGE_CH) {
             nrun = sort_dedupe_keep(src, W, key, ref, zk, np, M, tmp, keep);
