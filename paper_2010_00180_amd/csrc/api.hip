@@ -205,6 +205,7 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     if ((long long)n_inst * L > (1 << 24)) return fail(ISING_ERR_INVALID_ARG, "too many searches");
 
     int Nmax = 0;
+    bool j32_exact = true;   // every 4J_ij exactly representable in FP32
     for (int b = 0; b < n_inst; ++b) {
         if (N[b] < 1 || N[b] > MAX_N) return fail(ISING_ERR_INVALID_ARG, "N[%d]=%d outside [1, %d]", b, N[b], MAX_N);
         if (!J[b] || !h[b] || !init_bits[b]) return fail(ISING_ERR_INVALID_ARG, "NULL pointer for instance %d", b);
@@ -223,6 +224,7 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
                     return fail(ISING_ERR_INVALID_ARG, "J[%d][%d,%d]=%g is not a finite multiple of 2^-24", b, i, j, v);
                 if (v != J[b][(size_t)j * n + i])
                     return fail(ISING_ERR_INVALID_ARG, "J[%d] is not symmetric at (%d,%d)", b, i, j);
+                if ((double)(float)(4.0 * v) != 4.0 * v) j32_exact = false;
                 bound += std::fabs(v);
             }
         }
@@ -349,8 +351,9 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     float* dJ32 = nullptr;
     uint16_t *dJhi = nullptr, *dJlo = nullptr;
     double *dyb = nullptr, *debf = nullptr, *dab = nullptr;
+    const bool need_j32 = cfg->form == ISING_FORM_SPLIT_BF16 || j32_exact;
+    if (need_j32) ALLOC(dJ32, (size_t)jtot);
     if (cfg->form == ISING_FORM_SPLIT_BF16) {
-        ALLOC(dJ32, (size_t)jtot);
         ALLOC(dJhi, (size_t)jtot);
         ALLOC(dJlo, (size_t)jtot);
         ALLOC(dyb, n_inst);
@@ -396,6 +399,7 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     lay.scb = hd->d_scb;
     lay.form = cfg->form;
     lay.J32 = dJ32;
+    lay.J4f = j32_exact ? dJ32 : nullptr;
     lay.Jhi = dJhi;
     lay.Jlo = dJlo;
     lay.ybound = dyb;
@@ -458,6 +462,17 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
         cp(hd->d_scb, hd->sc_h.data(), sizeof(int) * n_inst);
         std::vector<float> J32h;
         std::vector<uint16_t> hih, loh;
+        if (need_j32) {
+            // fl32(4J): the FP32 scan's couplings, and an exact copy when j32_exact
+            J32h.assign((size_t)jtot, 0.f);
+            for (int b = 0; b < n_inst; ++b) {
+                const int n = N[b], np = hd->Npad[b];
+                for (int i = 0; i < n; ++i)
+                    for (int j = 0; j < n; ++j)
+                        J32h[joff[b] + (size_t)i * np + j] = (float)(4.0 * J[b][(size_t)i * n + j]);
+            }
+            cp(dJ32, J32h.data(), sizeof(float) * J32h.size());
+        }
         std::vector<double> ybh, ebfh, abh;
         if (cfg->form == ISING_FORM_SPLIT_BF16) {
             // fl32(4J), bf16 hi = RN(4J), lo = RN(4J - hi); per instance max |4J| and the
@@ -476,7 +491,6 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
                 std::memcpy(&f, &u, 4);
                 return f;
             };
-            J32h.assign((size_t)jtot, 0.f);
             hih.assign((size_t)jtot, 0);
             loh.assign((size_t)jtot, 0);
             ybh.assign(n_inst, 0.0);
@@ -490,7 +504,6 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
                     for (int j = 0; j < n; ++j) {
                         const double x = 4.0 * J[b][(size_t)i * n + j];
                         const size_t o = joff[b] + (size_t)i * np + j;
-                        J32h[o] = (float)x;
                         const uint16_t hb = bf16_rn((float)x);
                         hih[o] = hb;
                         loh[o] = bf16_rn((float)(x - (double)bf16_to_f(hb)));
@@ -505,7 +518,6 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
                 }
                 ebfh[b] = emax;
             }
-            cp(dJ32, J32h.data(), sizeof(float) * J32h.size());
             cp(dJhi, hih.data(), sizeof(uint16_t) * hih.size());
             cp(dJlo, loh.data(), sizeof(uint16_t) * loh.size());
             cp(dyb, ybh.data(), sizeof(double) * n_inst);

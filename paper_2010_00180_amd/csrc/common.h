@@ -97,6 +97,7 @@ struct Layout {
     // split-bf16 form
     int form;                // 0 plain, 1 split-bf16
     const float* J32;        // per instance, fl32(4J) (same layout as J4)
+    const float* J4f;        // the same buffer when every 4J_ij is exact in FP32 (else null)
     const uint16_t* Jhi;     // per instance, bf16(4J)
     const uint16_t* Jlo;     // per instance, bf16(4J - hi)
     const double* ybound;    // [B] max |4J_ij|

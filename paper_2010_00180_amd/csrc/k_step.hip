@@ -1246,10 +1246,22 @@ __global__ __launch_bounds__(256) void k_fupdate(Layout lay, const double* __res
     const bool pairf = j != (int)SINGLE;
     const double cj = pairf ? -0.5 * spin_of(xp, j) : 0.0;
     const double* Jb = J4 + lay.joff[b];
-    const double* Ji = Jb + (size_t)i * Np;
-    const double* Jj = Jb + (size_t)(pairf ? j : i) * Np;
     const double* Fp = lay.F + (size_t)code * lay.Npmax;
     double* Fn = lay.F + ((size_t)s * 2 * lay.M + slot) * lay.Npmax;
+    if (lay.J4f) {
+        // 4J exact in FP32: half the coupling bytes, the same sums
+        const float* Jf = lay.J4f + lay.joff[b];
+        const float* Ji = Jf + (size_t)i * Np;
+        const float* Jj = Jf + (size_t)(pairf ? j : i) * Np;
+        for (int k = lane; k < Np; k += 64) {
+            double v = Fp[k] + ci * (double)Ji[k];
+            if (pairf) v += cj * (double)Jj[k];
+            Fn[k] = k < N ? v : 0.0;
+        }
+        return;
+    }
+    const double* Ji = Jb + (size_t)i * Np;
+    const double* Jj = Jb + (size_t)(pairf ? j : i) * Np;
     for (int k = lane; k < Np; k += 64) {
         double v = Fp[k] + ci * Ji[k];
         if (pairf) v += cj * Jj[k];
