@@ -994,16 +994,66 @@ __device__ double block_reduce(double v, double* red, bool take_max)
     return r;
 }
 
+// The first histogram bin at which the running count (lowest bins first)
+// reaches want, written to *out; wave 0 scans, 16 bins per lane.  The caller
+// synchronises before reading *out.
+__device__ void first_bin_reaching(const int* hist, int want, int* out)
+{
+    if (threadIdx.x < 64) {
+        constexpr int PER = NBIN / 64;
+        const int l = threadIdx.x;
+        int loc = 0;
+        for (int k = 0; k < PER; ++k) loc += hist[PER * l + k];
+        int incl = loc;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(incl, off, 64);
+            if (l >= off) incl += v;
+        }
+        int run = incl - loc;
+        if (run < want && want <= incl) {
+            for (int k = 0; k < PER; ++k) {
+                run += hist[PER * l + k];
+                if (run >= want) {
+                    *out = PER * l + k;
+                    break;
+                }
+            }
+        }
+    }
+}
+
+// Dedupe table of k_merge: 4096 slots of 64 bits, the high 52 bits of a mix
+// of (E, Zobrist hash) above a 12-bit candidate index; the low 12 bits of the
+// mix give the home slot.
+constexpr int HASH_T = 4096;
+constexpr int HASH_PER = 12;                  // candidates per thread: n <= 3072
+constexpr uint64_t HASH_EMPTY = ~0ull;
+static_assert(HASH_T == 2 * MERGE_CH, "the table spans the key and zk arrays");
+static_assert(HASH_PER * 256 <= 3 * HASH_T / 4, "load factor at most 3/4");
+
+__device__ inline uint64_t mix_state(uint64_t z, double e)
+{
+    // splitmix64 finalizer (Steele, Lea and Flood) of the hash xor the scaled energy bits
+    uint64_t x = z ^ ((uint64_t)__double_as_longlong(e) * 0x9E3779B97F4A7C15ull);
+    x ^= x >> 30;
+    x *= 0xBF58476D1CE4E5B9ull;
+    x ^= x >> 27;
+    x *= 0x94D049BB133111EBull;
+    x ^= x >> 31;
+    return x;
+}
+
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_merge(Layout lay, const double* __restrict__ J4)
 {
-    __shared__ double key[MERGE_CH];
+    __shared__ uint64_t kz[2 * MERGE_CH];   // key then zk; the dedupe table before them
     __shared__ uint32_t ref[MERGE_CH];
-    __shared__ uint64_t zk[MERGE_CH];
     __shared__ uint8_t keep[MERGE_CH];
     __shared__ int tmp[256];
     __shared__ double red[256];
     __shared__ int hist[NBIN];
     __shared__ int freeslot[2048];
+    double* const key = reinterpret_cast<double*>(kz);
+    uint64_t* const zk = kz + MERGE_CH;
     __shared__ int kslot[1024];
     __shared__ uint8_t used[2048];
     const int s = blockIdx.x;
@@ -1023,27 +1073,157 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     SearchSrc src{&lay, s, b};
     const int n = nk + cnt;
     auto candE = [&](int c) -> double { return c < nk ? lay.E[q0 + keptl[c]] : sv[c - nk].E; };
-    // candidate c (0..n) into position p of the sort arrays
-    auto load_cand = [&](int c, int p) {
+    auto ref_of = [&](int c) -> uint32_t { return c < nk ? (uint32_t)c : REF_SURV | (uint32_t)(c - nk); };
+    // energy and Zobrist hash of candidate c (0..n)
+    auto cand_key = [&](int c, double& e, uint64_t& z) {
         if (c < nk) {
             const int slot = keptl[c];
-            key[p] = lay.E[q0 + slot];
-            ref[p] = (uint32_t)c;
-            zk[p] = lay.zob[q0 + slot];
+            e = lay.E[q0 + slot];
+            z = lay.zob[q0 + slot];
         } else {
             const Surv r = sv[c - nk];
             const int i = (int)(r.pair & 0xFFFFu), j = (int)(r.pair >> 16);
-            uint64_t z = lay.zob[r.code] ^ lay.zkey[i];
+            z = lay.zob[r.code] ^ lay.zkey[i];
             if (j != (int)SINGLE) z ^= lay.zkey[j];
-            key[p] = r.E;
-            ref[p] = REF_SURV | (uint32_t)(c - nk);
-            zk[p] = z;
+            e = r.E;
         }
+    };
+    // candidate c into position p of the sort arrays
+    auto load_cand = [&](int c, int p) {
+        double e;
+        uint64_t z;
+        cand_key(c, e, z);
+        key[p] = e;
+        ref[p] = ref_of(c);
+        zk[p] = z;
     };
 
     int nrun = -1;
     const int target = 2 * M + 64;
-    if (n > target + 256) {
+    if (n > 256 && n <= HASH_PER * 256) {
+        // Copies first.  Copies of one state share (E, Zobrist hash): the table
+        // keeps per key the lowest candidate index, which is the copy the sort
+        // would keep (kept states precede survivors, survivors are in order).
+        // Only the distinct representatives are ranked.  Every copy that could
+        // reach the cut is then compared word by word with its representative;
+        // a mismatch (two states whose mixes agree) falls back to sorting all.
+        uint64_t* const tab = kz;
+        for (int k = threadIdx.x; k < HASH_T; k += blockDim.x) tab[k] = HASH_EMPTY;
+        if (threadIdx.x == 0) {
+            tmp[1] = 0;
+            tmp[2] = 0;
+        }
+        __syncthreads();
+        double ce[HASH_PER];
+        uint64_t cz[HASH_PER];
+        int cslot[HASH_PER];
+#pragma unroll
+        for (int m = 0; m < HASH_PER; ++m) {
+            const int c = (int)threadIdx.x + 256 * m;
+            cslot[m] = -1;
+            ce[m] = 0.0;
+            cz[m] = 0;
+            if (c < n) cand_key(c, ce[m], cz[m]);
+        }
+#pragma unroll
+        for (int m = 0; m < HASH_PER; ++m) {
+            const int c = (int)threadIdx.x + 256 * m;
+            if (c < n) {
+                const uint64_t h = mix_state(cz[m], ce[m]);
+                const uint64_t mine = (h & ~(uint64_t)(HASH_T - 1)) | (uint64_t)c;
+                int slot = (int)(h & (HASH_T - 1));
+                for (;;) {
+                    uint64_t v = tab[slot];
+                    if (v == HASH_EMPTY) {
+                        v = atomicCAS(&tab[slot], HASH_EMPTY, mine);
+                        if (v == HASH_EMPTY) break;
+                    }
+                    if ((v >> 12) == (mine >> 12)) {
+                        atomicMin(&tab[slot], mine);
+                        break;
+                    }
+                    slot = (slot + 1) & (HASH_T - 1);
+                }
+                cslot[m] = slot;
+            }
+        }
+        __syncthreads();
+        int crep[HASH_PER];
+        int nmine = 0;
+        double lo = INFINITY, hi = -INFINITY;
+#pragma unroll
+        for (int m = 0; m < HASH_PER; ++m) {
+            const int c = (int)threadIdx.x + 256 * m;
+            crep[m] = cslot[m] >= 0 ? (int)(tab[cslot[m]] & (uint64_t)(HASH_T - 1)) : -1;
+            if (crep[m] == c) {
+                ++nmine;
+                lo = fmin(lo, ce[m]);
+                hi = fmax(hi, ce[m]);
+            }
+        }
+        atomicAdd(&tmp[1], nmine);
+        for (int off = 32; off > 0; off >>= 1) {
+            lo = fmin(lo, __shfl_xor(lo, off, 64));
+            hi = fmax(hi, __shfl_xor(hi, off, 64));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            red[threadIdx.x >> 6] = lo;
+            red[4 + (threadIdx.x >> 6)] = hi;
+        }
+        for (int k = threadIdx.x; k < NBIN; k += blockDim.x) hist[k] = 0;
+        __syncthreads();   // the table is no longer read: key and zk are the sort arrays again
+        const int nrep = tmp[1];
+        // representatives to rank: all of them, or the lowest bins holding M
+        int bmax = NBIN;
+        lo = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+        hi = fmax(fmax(red[4], red[5]), fmax(red[6], red[7]));
+        const double scale = hi > lo ? (double)NBIN / (hi - lo) : 0.0;
+        auto bin_of = [&](double e) -> int {
+            const int k = (int)((e - lo) * scale);
+            return k < 0 ? 0 : (k >= NBIN ? NBIN - 1 : k);
+        };
+        if (nrep > 512) {
+#pragma unroll
+            for (int m = 0; m < HASH_PER; ++m)
+                if (crep[m] == (int)threadIdx.x + 256 * m) atomicAdd(&hist[bin_of(ce[m])], 1);
+            __syncthreads();
+            first_bin_reaching(hist, nrep < M ? nrep : M, tmp);
+            __syncthreads();
+            bmax = tmp[0];
+        }
+#pragma unroll
+        for (int m = 0; m < HASH_PER; ++m) {
+            const int c = (int)threadIdx.x + 256 * m;
+            if (crep[m] == c && (bmax == NBIN || bin_of(ce[m]) <= bmax)) {
+                const int pos = atomicAdd(&tmp[2], 1);
+                if (pos < MERGE_CH) {
+                    key[pos] = ce[m];
+                    ref[pos] = ref_of(c);
+                    zk[pos] = cz[m];
+                }
+            }
+        }
+        __syncthreads();
+        const int np = tmp[2];
+        __syncthreads();
+        if (np <= MERGE_CH) {
+            nrun = sort_dedupe_keep(src, W, key, ref, zk, np, M, tmp, keep);
+            const double cut = nrun >= M ? key[M - 1] : INFINITY;
+            int bad = 0;
+#pragma unroll
+            for (int m = 0; m < HASH_PER; ++m) {
+                const int c = (int)threadIdx.x + 256 * m;
+                if (crep[m] >= 0 && crep[m] != c && ce[m] <= cut) {
+                    const int r = crep[m];
+                    double er;
+                    uint64_t zr;
+                    cand_key(r, er, zr);
+                    if (er != ce[m] || zr != cz[m] || !same_words(src, W, ref_of(c), ref_of(r))) bad = 1;
+                }
+            }
+            if (__syncthreads_or(bad)) nrun = -1;
+        }
+    } else if (n > target + 256) {
         double lo = INFINITY, hi = -INFINITY;
         for (int c = threadIdx.x; c < n; c += blockDim.x) {
             const double e = candE(c);
@@ -1070,29 +1250,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         };
         for (int c = threadIdx.x; c < n; c += blockDim.x) atomicAdd(&hist[bin_of(candE(c))], 1);
         __syncthreads();
-        // the first bin at which the running count reaches the target
-        // (wave 0, 16 bins per lane, lowest first)
-        if (threadIdx.x < 64) {
-            constexpr int PER = NBIN / 64;
-            const int l = threadIdx.x;
-            int loc = 0;
-            for (int k = 0; k < PER; ++k) loc += hist[PER * l + k];
-            int incl = loc;
-            for (int off = 1; off < 64; off <<= 1) {
-                const int v = __shfl_up(incl, off, 64);
-                if (l >= off) incl += v;
-            }
-            int run = incl - loc;
-            if (run < target && target <= incl) {
-                for (int k = 0; k < PER; ++k) {
-                    run += hist[PER * l + k];
-                    if (run >= target) {
-                        tmp[0] = PER * l + k;
-                        break;
-                    }
-                }
-            }
-        }
+        first_bin_reaching(hist, target, tmp);
         __syncthreads();
         const int bmax = tmp[0];
         // the candidates of bins <= bmax, in any order (they are sorted next),
