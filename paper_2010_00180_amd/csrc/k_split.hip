@@ -117,7 +117,7 @@ __device__ inline int find_inst(const long long* prefix, int B, long long e)
 __global__ __launch_bounds__(256) void k_prep32(Layout lay, const long long* __restrict__ fr_prefix)
 {
     const long long total = fr_prefix[lay.B];
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63;
     const int retry_mode = lay.flags[FLAG_RETRY_MODE];
     const int first = lay.flags[FLAG_FIRST];
@@ -156,6 +156,7 @@ __global__ __launch_bounds__(256) void k_prep32(Layout lay, const long long* __r
         // slack of the FP32 threshold, from the instance's bound on |a|
         const double u = 5.9604644775390625e-08;   // 2^-24
         const double delta = 4.0 * u * (lay.ybound[b] + lay.abound[b]) + (from_ft ? 2.0 * lay.ebf[b] : 0.0);
+        int nhit = 0;
         for (int i0 = 0; i0 < Np; i0 += 64) {
             const int i = i0 + lane;
             double a = 0.0;
@@ -163,13 +164,21 @@ __global__ __launch_bounds__(256) void k_prep32(Layout lay, const long long* __r
             if (lay.tr_feat) A[i] = a;   // FP64 a is read back only by trace capture
             A32[i] = i < N ? (float)(from_ft ? -2.0 * spin_d(x, i) * (double)Ft[i] : a) : 0.f;
             RR[i] = i < N ? __double2float_ru(T - a + delta) : -INFINITY;
+            nhit += __builtin_popcountll(__builtin_amdgcn_ballot_w64(i < N && Em + a <= c));
+        }
+        int base = 0;
+        if (nhit) {
+            if (lane == 0) base = atomicAdd(&lay.surv_count[s], nhit);
+            base = __shfl(base, 0, 64);
+        }
+        for (int i0 = 0; nhit && i0 < Np; i0 += 64) {
+            const int i = i0 + lane;
+            double a = 0.0;
+            if (i < N) a = -2.0 * spin_d(x, i) * F[i];
             const double Ec = Em + a;
             const bool hit = i < N && Ec <= c;
             const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
             if (m) {
-                int base = 0;
-                if (lane == 0) base = atomicAdd(&lay.surv_count[s], __builtin_popcountll(m));
-                base = __shfl(base, 0, 64);
                 if (hit) {
                     const int pos = base + (int)mbcnt64s(m);
                     if (pos < lay.cap_surv) {
@@ -180,6 +189,7 @@ __global__ __launch_bounds__(256) void k_prep32(Layout lay, const long long* __r
                         lay.surv[(size_t)s * lay.cap_surv + pos] = r;
                     }
                 }
+                base += __builtin_popcountll(m);
             }
         }
     }
@@ -190,8 +200,10 @@ __global__ __launch_bounds__(256) void k_prep32(Layout lay, const long long* __r
 // block).  Lane = row i; registers hold y_j = s_j fl32(4J_ij) for 64 columns
 // (column signs re-applied per group of 8 when they change between states);
 // per pair one v_fma_f32 and one v_min_f32, one compare per group against
-// RR_i.  Admitted pairs are re-scored in FP64 (a_i + a_j + s_i s_j 4J_ij
-// against T, all exact) and only then recorded; the rest are counted.
+// RR_i.  Admitted pairs are queued in LDS and re-scored in FP64 (a_i + a_j +
+// s_i s_j 4J_ij against T, all exact) a wave's worth at a time, so the global
+// reads of the re-score overlap; only then are they recorded, and the rest are
+// counted.
 constexpr int T32 = 64;
 
 __device__ inline void flush32(const Layout& lay, Surv* stage, int& n, int s)
@@ -231,6 +243,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     __shared__ double sT[64], sE[64];
     __shared__ int sS[64], sCode[64];
     __shared__ uint64_t sWi[64], sWj[64];
+    constexpr int PEND = 768;
+    __shared__ uint32_t pend[PEND];   // admitted pairs awaiting the FP64 re-score: k << 12 | row << 6 | col
     const uint32_t lane = lane_id32();
     const long long total = iprefix[lay.B];
     const int retry_mode = lay.flags[FLAG_RETRY_MODE];
@@ -270,6 +284,41 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         }
         uint64_t prev_wj = 0;
         int nstage = 0, sstage = -1;
+        int npend = 0;
+        // exact FP64 re-score of the admitted pairs, survivors to the stage
+        auto rescore = [&]() {
+            for (int p0 = 0; p0 < npend; p0 += 64) {
+                const int p = p0 + (int)lane;
+                bool keep = false;
+                Surv rec;
+                rec.E = 0.0;
+                rec.code = 0;
+                rec.pair = 0;
+                if (p < npend) {
+                    const uint32_t pr = pend[p];
+                    const int k = (int)(pr >> 12), rl = (int)((pr >> 6) & 63u), cl = (int)(pr & 63u);
+                    const int prow = bi * TILE + rl, pcol = col0 + cl;
+                    const int cd = sCode[k];
+                    const double* Frow = Fpool + (size_t)cd * lay.Npmax;
+                    const double sid = ((sWi[k] >> rl) & 1ull) ? -1.0 : 1.0;
+                    const double sj = ((sWj[k] >> cl) & 1ull) ? -1.0 : 1.0;
+                    const double ai = -2.0 * sid * Frow[prow];
+                    const double x = -2.0 * sj * Frow[pcol] + sid * sj * J4[lay.joff[b] + (size_t)prow * Np + pcol];
+                    keep = ai + x <= sT[k];
+                    if (!keep) ++rejected;
+                    rec.E = (sE[k] + ai) + x;
+                    rec.code = (uint32_t)cd;
+                    rec.pair = (uint32_t)prow | ((uint32_t)pcol << 16);
+                }
+                const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
+                if (m) {
+                    if (nstage > STAGE - 64) flush32(lay, stage, nstage, sstage);
+                    if (keep) stage[nstage + (int)mbcnt64s(m)] = rec;
+                    nstage += __builtin_popcountll(m);
+                }
+            }
+            npend = 0;
+        };
         for (int g0 = f0; g0 < f1; g0 += 64) {
             const int ns = min(64, f1 - g0);
             const size_t fe0 = (size_t)b * lay.fmax + g0;
@@ -300,6 +349,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 const bool skip = retry_mode && !lay.retry[s];
                 if (!skip) {
                     if (s != sstage) {
+                        rescore();
                         flush32(lay, stage, nstage, sstage);
                         sstage = s;
                     }
@@ -311,15 +361,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     const uint64_t dw = wj ^ prev_wj;
                     prev_wj = wj;
                     const float* aj = abuf[cur];
+                    float a8n[8];   // the next group's a_j, read one group ahead
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) a8n[u] = aj[u];
 #pragma unroll
                     for (int g = 0; g < T32; g += 8) {
+                        float a8[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) a8[u] = a8n[u];
+                        if (g + 8 < T32) {
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) a8n[u] = aj[g + 8 + u];
+                        }
                         if ((dw >> g) & 0xFFull) {
 #pragma unroll
                             for (int u = 0; u < 8; ++u) Jb[g + u] ^= (uint32_t)((dw >> (g + u)) & 1ull) << 31;
                         }
-                        float a8[8];
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) a8[u] = aj[g + u];
                         float mn0 = fmaf(si, __uint_as_float(Jb[g]), a8[0]);
                         float mn1 = fmaf(si, __uint_as_float(Jb[g + 1]), a8[1]);
 #pragma unroll
@@ -329,38 +386,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                             else mn0 = fminf(mn0, x);
                         }
                         if (__builtin_amdgcn_ballot_w64(fminf(mn0, mn1) <= rrt)) {
-                            // admitted pairs: exact FP64 re-score, then record
-                            const double Tm = sT[k];
-                            // exact a = -2 s F from the state's local fields
-                            const double* Frow = Fpool + (size_t)sCode[k] * lay.Npmax;
-                            const double sid = (double)si;
-                            const double ai = row < N ? -2.0 * sid * Frow[row] : 0.0;
+                            // admitted pairs wait for the exact re-score
+                            if (npend > PEND - 512) rescore();
 #pragma unroll
                             for (int u = 0; u < 8; ++u) {
                                 const float xt = fmaf(si, __uint_as_float(Jb[g + u]), a8[u]);
                                 const bool adm = xt <= rrt;
-                                bool keep = false;
-                                double x = 0.0;
-                                if (adm) {
-                                    const int col = col0 + g + u;
-                                    const double sj = ((wj >> (g + u)) & 1ull) ? -1.0 : 1.0;
-                                    x = -2.0 * sj * Frow[col] + sid * sj * J4[lay.joff[b] + (size_t)row * Np + col];
-                                    keep = ai + x <= Tm;
-                                    if (!keep) ++rejected;
-                                }
-                                const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
+                                const uint64_t m = __builtin_amdgcn_ballot_w64(adm);
                                 if (m) {
-                                    if (nstage > STAGE - 64) flush32(lay, stage, nstage, s);
-                                    if (keep) {
-                                        uint32_t rowv = (uint32_t)row;
-                                        asm volatile("" : "+v"(rowv));
-                                        Surv rec;
-                                        rec.E = (sE[k] + ai) + x;
-                                        rec.code = (uint32_t)sCode[k];
-                                        rec.pair = rowv | ((uint32_t)(col0 + g + u) << 16);
-                                        stage[nstage + (int)mbcnt64s(m)] = rec;
-                                    }
-                                    nstage += __builtin_popcountll(m);
+                                    if (adm) pend[npend + (int)mbcnt64s(m)] = ((uint32_t)k << 12) | (lane << 6) | (uint32_t)(g + u);
+                                    npend += __builtin_popcountll(m);
                                 }
                             }
                         }
@@ -370,6 +405,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 cur ^= 1;
                 __syncthreads();
             }
+            rescore();   // before the next 64 states replace the records
         }
         flush32(lay, stage, nstage, sstage);
         __syncthreads();

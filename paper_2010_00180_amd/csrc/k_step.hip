@@ -540,7 +540,7 @@ __device__ inline int find_instance(const long long* prefix, int B, long long e)
 __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __restrict__ fr_prefix)
 {
     const long long total = fr_prefix[lay.B];
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63;
     const int retry_mode = lay.flags[FLAG_RETRY_MODE];
     for (long long e = (long long)blockIdx.x * 4 + wave; e < total; e += (long long)gridDim.x * 4) {
@@ -574,18 +574,30 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
             atomicAdd(&lay.ctr[CTR_SINGLES], (unsigned long long)N);
             if (ranked) atomicAdd(&lay.ctr[CTR_SCORED], all);
         }
+        // a_i, and the single flips below the cut: counted first, so that one
+        // atomic reserves their places, then recorded
+        int nhit = 0;
         for (int i0 = 0; i0 < Np; i0 += 64) {
             const int i = i0 + lane;
             double a = 0.0;
             if (i < N) a = -2.0 * spin_of(x, i) * F[i];
             A[i] = a;
+            // a ranked state's singles go with its pairs
+            nhit += __builtin_popcountll(__builtin_amdgcn_ballot_w64(!ranked && i < N && Em + a <= c));
+        }
+        int base = 0;
+        if (nhit) {
+            if (lane == 0) base = atomicAdd(&lay.surv_count[s], nhit);
+            base = __shfl(base, 0, 64);
+        }
+        for (int i0 = 0; nhit && i0 < Np; i0 += 64) {
+            const int i = i0 + lane;
+            double a = 0.0;
+            if (i < N) a = -2.0 * spin_of(x, i) * F[i];
             const double Ec = Em + a;
-            const bool hit = !ranked && i < N && Ec <= c;   // a ranked state's singles go with its pairs
+            const bool hit = i < N && Ec <= c;
             const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
             if (m) {
-                int base = 0;
-                if (lane == 0) base = atomicAdd(&lay.surv_count[s], __builtin_popcountll(m));
-                base = __shfl(base, 0, 64);
                 if (hit) {
                     const int pos = base + (int)mbcnt64(m);
                     if (pos < lay.cap_surv) {
@@ -596,6 +608,7 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
                         lay.surv[(size_t)s * lay.cap_surv + pos] = r;
                     }
                 }
+                base += __builtin_popcountll(m);
             }
         }
     }
@@ -1182,7 +1195,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             const int k = (int)((e - lo) * scale);
             return k < 0 ? 0 : (k >= NBIN ? NBIN - 1 : k);
         };
-        if (nrep > 512) {
+        if (nrep > M + 32) {
 #pragma unroll
             for (int m = 0; m < HASH_PER; ++m)
                 if (crep[m] == (int)threadIdx.x + 256 * m) atomicAdd(&hist[bin_of(ce[m])], 1);
@@ -1214,11 +1227,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             for (int m = 0; m < HASH_PER; ++m) {
                 const int c = (int)threadIdx.x + 256 * m;
                 if (crep[m] >= 0 && crep[m] != c && ce[m] <= cut) {
+                    // equal words imply equal hashes; equal energies are checked
+                    // as the sort's dedupe requires them
                     const int r = crep[m];
-                    double er;
-                    uint64_t zr;
-                    cand_key(r, er, zr);
-                    if (er != ce[m] || zr != cz[m] || !same_words(src, W, ref_of(c), ref_of(r))) bad = 1;
+                    const double er = candE(r);
+                    if (er != ce[m] || !same_words(src, W, ref_of(c), ref_of(r))) bad = 1;
                 }
             }
             if (__syncthreads_or(bad)) nrun = -1;
