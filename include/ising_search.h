@@ -58,9 +58,24 @@ typedef enum {
 } ising_form_t;
 
 enum {
-    ISING_FLAG_RECORD_PROPOSALS = 1   /* learned form: keep each step's proposals for
+    ISING_FLAG_RECORD_PROPOSALS = 1,  /* learned form: keep each step's proposals for
                                          ising_search_get_proposals (B*L*M*K*4 bytes) */
+    ISING_FLAG_SITE_BOUND = 2         /* plain and split forms: skip pair flips that a bound proves
+                                         cannot enter (not in the paper; see below) */
 };
+
+/*
+ * Site bound (ISING_FLAG_SITE_BOUND).  The pair flip (i, j) of a state with
+ * single-flip changes a_i = -2 s_i F_i changes the energy by
+ * a_i + a_j + s_i s_j 4J_ij >= a_i + min_k a_k - max_k |4J_ik|, so it can pass
+ * the step's cut T only if both of its sites satisfy
+ * a_i + min_k a_k - max_k |4J_ik| <= T.  A state with at most 256 such sites has
+ * exactly the pairs among them evaluated (FP64, the same arithmetic as the
+ * scan) by the preparation kernel and leaves the scan; the others are scanned
+ * in full.  The kept sets are identical with and without the flag (every value
+ * involved is exact on the 2^-24 grid); pair_evals then counts the pairs
+ * actually evaluated and bounded_states the states resolved this way.
+ */
 
 typedef struct {
     int32_t M;                 /* states kept per search, >= 1 */
@@ -94,6 +109,8 @@ typedef struct {
     uint64_t ranked_states;    /* learned form: states expanded with ranked pairs */
     uint64_t trace_samples;    /* samples offered to the trace buffer since ising_search_set_trace */
     double learn_ms;           /* learned form: device time of the ranking kernel, summed */
+    uint64_t bounded_states;   /* site bound: expanded states whose pairs were evaluated among their
+                                  bounded sites only */
 } ising_stats_t;
 
 /*

@@ -29,6 +29,7 @@ FORM_PLAIN = 0
 FORM_SPLIT_BF16 = 1
 FORM_LEARNED = 2
 FLAG_RECORD_PROPOSALS = 1
+FLAG_SITE_BOUND = 2
 SCORER_NETWORK = 0
 SCORER_FIELDS = 1
 SCORER_UNIFORM = 2
@@ -95,6 +96,7 @@ class IsingStats(ctypes.Structure):
         ("ranked_states", ctypes.c_uint64),
         ("trace_samples", ctypes.c_uint64),
         ("learn_ms", ctypes.c_double),
+        ("bounded_states", ctypes.c_uint64),
     ]
 
     def as_dict(self):

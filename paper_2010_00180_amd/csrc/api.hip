@@ -192,9 +192,12 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     if (cfg->M < 1 || cfg->M > 1024) return fail(ISING_ERR_INVALID_ARG, "M=%d outside [1, 1024]", cfg->M);
     if (cfg->form != ISING_FORM_PLAIN && cfg->form != ISING_FORM_SPLIT_BF16 && cfg->form != ISING_FORM_LEARNED)
         return fail(ISING_ERR_INVALID_ARG, "form %d is not available in this build", cfg->form);
-    if (cfg->flags & ~ISING_FLAG_RECORD_PROPOSALS) return fail(ISING_ERR_INVALID_ARG, "unknown flag bits 0x%x", cfg->flags);
+    if (cfg->flags & ~(ISING_FLAG_RECORD_PROPOSALS | ISING_FLAG_SITE_BOUND))
+        return fail(ISING_ERR_INVALID_ARG, "unknown flag bits 0x%x", cfg->flags);
     if ((cfg->flags & ISING_FLAG_RECORD_PROPOSALS) && cfg->form != ISING_FORM_LEARNED)
         return fail(ISING_ERR_INVALID_ARG, "proposals are recorded by the learned form only");
+    if ((cfg->flags & ISING_FLAG_SITE_BOUND) && cfg->form == ISING_FORM_LEARNED)
+        return fail(ISING_ERR_INVALID_ARG, "the site bound is available for the plain and split forms only");
     if (cfg->topk_factor < 0 || cfg->topk_factor > 64)
         return fail(ISING_ERR_INVALID_ARG, "topk_factor=%d outside [0, 64]", cfg->topk_factor);
     if (cfg->states_per_item < 0 || cfg->states_per_item > 4096)
@@ -376,6 +379,14 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
             ALLOC(lay.prop_n, (size_t)n_inst * lay.fmax);
         }
     }
+    const bool sb = (cfg->flags & ISING_FLAG_SITE_BOUND) != 0;
+    double* drm = nullptr;
+    if (sb) {
+        ALLOC(drm, (size_t)n_inst * lay.Npmax);
+        ALLOC(lay.fr_bound, (size_t)n_inst * lay.fmax);
+        ALLOC(lay.full_list, (size_t)n_inst * lay.fmax);
+        ALLOC(lay.full_count, n_inst);
+    }
     ALLOC(lay.lr_count, n_inst);
     ALLOC(lay.nm_count, S);
     ALLOC(lay.nm_code, S * lay.M);
@@ -406,6 +417,8 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     lay.ebf = debf;
     lay.abound = dab;
     lay.Jn16 = dJn;
+    lay.sb = sb ? 1 : 0;
+    lay.rmax4 = drm;
     lay.mlp = hd->d_mlp;
     lay.scorer = 0;
     lay.seed = 0;
@@ -523,6 +536,20 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
             cp(dyb, ybh.data(), sizeof(double) * n_inst);
             cp(debf, ebfh.data(), sizeof(double) * n_inst);
             cp(dab, abh.data(), sizeof(double) * n_inst);
+        }
+        std::vector<double> rmh;
+        if (sb) {
+            // site bound: max_j |4J_ij| per row
+            rmh.assign((size_t)n_inst * lay.Npmax, 0.0);
+            for (int b = 0; b < n_inst; ++b) {
+                const int n = N[b];
+                for (int i = 0; i < n; ++i) {
+                    double m = 0.0;
+                    for (int j = 0; j < n; ++j) m = std::max(m, std::fabs(4.0 * J[b][(size_t)i * n + j]));
+                    rmh[(size_t)b * lay.Npmax + i] = m;
+                }
+            }
+            cp(drm, rmh.data(), sizeof(double) * rmh.size());
         }
         std::vector<uint16_t> jnh;
         if (cfg->form == ISING_FORM_LEARNED) {
@@ -722,11 +749,11 @@ extern "C" int ising_search_autotune(ising_search_t* s, int32_t* n_active)
     sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
     hipError_t e = launch_step_begin(lay, false, st);
     if (e == hipSuccess) e = launch_frontier_plan(lay, st);
-    auto scan_ms = [&](float& ms) -> hipError_t {
+    auto scan_ms = [&](float& ms, bool count) -> hipError_t {
         hipError_t r = hipMemcpyAsync(s->d_scb, s->sc_h.data(), sizeof(int) * lay.B, hipMemcpyHostToDevice, st);
         if (r == hipSuccess) r = launch_plan_only(lay, st);
         if (r == hipSuccess) r = launch_clear_survivors(lay, st);
-        if (r == hipSuccess) r = launch_prep(lay, st);
+        if (r == hipSuccess) r = launch_prep(lay, st, count);
         if (r == hipSuccess) r = hipEventRecord(e0, st);
         if (r == hipSuccess) r = launch_scan(lay, s->scan_grid, st);
         if (r == hipSuccess) r = hipEventRecord(e1, st);
@@ -741,7 +768,7 @@ extern "C" int ising_search_autotune(ising_search_t* s, int32_t* n_active)
             for (int b = 0; b < lay.B; ++b)
                 if (s->N[b] == sizes[k]) s->sc_h[b] = c;
             float ms = 0.f;
-            e = scan_ms(ms);
+            e = scan_ms(ms, false);
             if (e != hipSuccess) break;
             if (best < 0 || ms < best_ms) {
                 best = c;
@@ -753,7 +780,7 @@ extern "C" int ising_search_autotune(ising_search_t* s, int32_t* n_active)
     }
     // the step itself with the chosen tiles
     float ms = 0.f;
-    if (e == hipSuccess) e = scan_ms(ms);
+    if (e == hipSuccess) e = scan_ms(ms, true);
     if (e == hipSuccess && lay.form == ISING_FORM_LEARNED) e = launch_learn(lay, s->learn_grid, st);
     if (e == hipSuccess) e = launch_merge(lay, st);
     if (e == hipSuccess) e = launch_fupdate(lay, st);
@@ -1026,6 +1053,7 @@ extern "C" int ising_search_get_stats(ising_search_t* s, ising_stats_t* out)
     out->ranked_states = c[CTR_LEARNED];
     out->trace_samples = c[CTR_TRACE];
     out->learn_ms = s->t_learn;
+    out->bounded_states = c[CTR_BOUNDED];
     return ISING_OK;
 }
 

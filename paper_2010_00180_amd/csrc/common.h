@@ -82,6 +82,13 @@ struct Layout {
     double* A;               // [B][fmax][Npmax]
     FrRec* rec;              // [B][fmax]
     uint64_t* fbits;         // [B][fmax][Wmax] : copy of the state's words
+    // site bound (forms 0 and 1, on request): a state whose pairs can only
+    // involve a few sites has them evaluated in the preparation kernel
+    int sb;                  // 1 = site bound on
+    const double* rmax4;     // [B][Npmax] max_j |4J_ij| of row i
+    uint16_t* fr_bound;      // [B][fmax] 0 = scanned in full, else 1 + the sites kept by the bound
+    int* full_list;          // [B][fmax] entries left to the scan, in frontier order
+    int* full_count;         // [B]
     // survivors
     int* surv_count;         // [S]
     Surv* surv;              // [S][cap_surv]
@@ -134,7 +141,8 @@ struct Layout {
 };
 
 enum { CTR_PAIRS = 0, CTR_SINGLES = 1, CTR_FRONTIER = 2, CTR_SURV = 3, CTR_RETRY = 4, CTR_STEPS = 5,
-       CTR_FALLBACK = 6, CTR_SCORED = 7, CTR_LEARNED = 8, CTR_TRACE = 9 };
+       CTR_FALLBACK = 6, CTR_SCORED = 7, CTR_LEARNED = 8, CTR_TRACE = 9, CTR_BOUNDED = 10 };
+constexpr int SB_CAP = 256;          // most sites a state may keep for the site-bound evaluation
 enum { FLAG_ACTIVE = 0, FLAG_OVERFLOW = 1, FLAG_STUCK = 2, FLAG_RETRY_MODE = 3, FLAG_FIRST = 4 };
 
 __host__ __device__ inline int words_of(int N) { return (N + 63) >> 6; }
@@ -146,13 +154,141 @@ __host__ __device__ inline long long tiles_of(int N) {
     return nb * nc - nb * (nb - 1);
 }
 
+// Site bound of one frontier state, evaluated by one wave.  The pair (i, j)
+// changes the energy by a_i + a_j + s_i s_j 4J_ij >= a_i + min_k a_k - max_k |4J_ik|,
+// so it can pass the cut T only if both sites satisfy
+// a_i + min_k a_k - max_k |4J_ik| <= T (all terms on the 2^-24 grid: exact).
+// With at most SB_CAP such sites, every pair among them is evaluated with the
+// scan's arithmetic (x = fma(s_i, s_j 4J_ij, a_j) <= T - a_i, E = (E + a_i) + x)
+// and its survivors recorded; returns the number r of such sites (r (r - 1) / 2
+// pairs evaluated), or -1 when there are too many and the state must be scanned
+// in full.  sidx and sa are this wave's LDS arrays of SB_CAP entries.
+// The loads are batched for latency: a is held in registers (N <= 640), and
+// the pairs are taken in 8 x 8 blocks (lane = 8 p + q), four blocks per batch.
+constexpr int SB_AREG = 10;   // a held in registers when N <= 640
+__device__ inline int site_bound_pairs(const Layout& lay, int b, int s, int code, double Em, double T,
+                                       const uint64_t* __restrict__ x, const double* __restrict__ F,
+                                       int N, int Np, uint16_t* sidx, double* sa)
+{
+    const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    auto spin = [&](int i) -> double { return ((x[i >> 6] >> (i & 63)) & 1ull) ? -1.0 : 1.0; };
+    auto lane_rank = [&](uint64_t m) -> int {
+        return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    };
+    const double* rm = lay.rmax4 + (size_t)b * lay.Npmax;
+    int r = 0;
+    if (N <= 64 * SB_AREG) {
+        double areg[SB_AREG];
+        double amin = INFINITY;
+#pragma unroll
+        for (int k = 0; k < SB_AREG; ++k) {
+            const int i = 64 * k + (int)lane;
+            areg[k] = i < N ? -2.0 * spin(i) * F[i] : 0.0;
+            if (i < N) amin = fmin(amin, areg[k]);
+        }
+        for (int off = 32; off > 0; off >>= 1) amin = fmin(amin, __shfl_xor(amin, off, 64));
+        // count and list in one pass; entries past SB_CAP are only counted
+#pragma unroll
+        for (int k = 0; k < SB_AREG; ++k) {
+            const int i = 64 * k + (int)lane;
+            const bool in = i < N && (areg[k] + amin) - rm[i] <= T;
+            const uint64_t m = __builtin_amdgcn_ballot_w64(in);
+            const int pos = r + lane_rank(m);
+            if (in && pos < SB_CAP) {
+                sidx[pos] = (uint16_t)i;
+                sa[pos] = areg[k];
+            }
+            r += __builtin_popcountll(m);
+        }
+        if (r > SB_CAP) return -1;
+    } else {
+        double amin = INFINITY;
+        for (int i = (int)lane; i < N; i += 64) amin = fmin(amin, -2.0 * spin(i) * F[i]);
+        for (int off = 32; off > 0; off >>= 1) amin = fmin(amin, __shfl_xor(amin, off, 64));
+        for (int i0 = 0; i0 < N; i0 += 64) {
+            const int i = i0 + (int)lane;
+            const bool in = i < N && (-2.0 * spin(i) * F[i] + amin) - rm[i] <= T;
+            r += __builtin_popcountll(__builtin_amdgcn_ballot_w64(in));
+        }
+        if (r > SB_CAP) return -1;
+        int base = 0;
+        for (int i0 = 0; i0 < N && base < r; i0 += 64) {
+            const int i = i0 + (int)lane;
+            const double a = i < N ? -2.0 * spin(i) * F[i] : 0.0;
+            const bool in = i < N && (a + amin) - rm[i] <= T;
+            const uint64_t m = __builtin_amdgcn_ballot_w64(in);
+            if (in) {
+                sidx[base + lane_rank(m)] = (uint16_t)i;
+                sa[base + lane_rank(m)] = a;
+            }
+            base += __builtin_popcountll(m);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const double* J4 = lay.J4 + lay.joff[b];
+    const int pp = (int)(lane >> 3), qq = (int)(lane & 7);
+    for (int P0 = 0; P0 + 1 < r; P0 += 8) {
+        const int p = P0 + pp;
+        const int i = p < r ? sidx[p] : 0;
+        const double ai = p < r ? sa[p] : 0.0;
+        const double si = spin(i);
+        const double rr = T - ai;
+        const double Ea = Em + ai;
+        const double* Jrow = J4 + (size_t)i * Np;
+        for (int Q0 = P0; Q0 < r; Q0 += 32) {
+            double xv[4];
+            bool keep[4];
+            int jj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = Q0 + 8 * u + qq;
+                keep[u] = false;
+                xv[u] = 0.0;
+                jj[u] = 0;
+                if (p < q && q < r) {
+                    const int j = sidx[q];
+                    jj[u] = j;
+                    xv[u] = fma(si, spin(j) * Jrow[j], sa[q]);
+                    keep[u] = xv[u] <= rr;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint64_t m = __builtin_amdgcn_ballot_w64(keep[u]);
+                if (m) {
+                    int pos0 = 0;
+                    if (lane == 0) pos0 = atomicAdd(&lay.surv_count[s], __builtin_popcountll(m));
+                    pos0 = __shfl(pos0, 0, 64);
+                    if (keep[u]) {
+                        const int pos = pos0 + lane_rank(m);
+                        if (pos < lay.cap_surv) {
+                            Surv rec;
+                            rec.E = Ea + xv[u];
+                            rec.code = (uint32_t)code;
+                            rec.pair = (uint32_t)i | ((uint32_t)jj[u] << 16);
+                            lay.surv[(size_t)s * lay.cap_surv + pos] = rec;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    // the list is rewritten by this wave's next state
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return r;
+}
+
 // Host launchers (defined next to their kernels).
 hipError_t launch_init_fields(const Layout& lay, const uint64_t* d_x0, hipStream_t st);
 hipError_t launch_fields_for(const Layout& lay, int search, int count, hipStream_t st);
 hipError_t launch_frontier_plan(const Layout& lay, hipStream_t st);
 hipError_t launch_plan_only(const Layout& lay, hipStream_t st);      // re-plan without counting
 hipError_t launch_clear_survivors(const Layout& lay, hipStream_t st);
-hipError_t launch_prep(const Layout& lay, hipStream_t st);
+hipError_t launch_prep(const Layout& lay, hipStream_t st, bool count = true);
 hipError_t launch_scan(const Layout& lay, int scan_grid, hipStream_t st);
 hipError_t launch_merge(const Layout& lay, hipStream_t st);
 hipError_t launch_fupdate(const Layout& lay, hipStream_t st);

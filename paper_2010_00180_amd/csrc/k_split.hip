@@ -116,6 +116,8 @@ __device__ inline int find_inst(const long long* prefix, int B, long long e)
 
 __global__ __launch_bounds__(256) void k_prep32(Layout lay, const long long* __restrict__ fr_prefix)
 {
+    __shared__ uint16_t sb_idx[4][SB_CAP];
+    __shared__ double sb_a[4][SB_CAP];
     const long long total = fr_prefix[lay.B];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63;
@@ -150,8 +152,17 @@ __global__ __launch_bounds__(256) void k_prep32(Layout lay, const long long* __r
         }
         if ((int)lane < lay.Wmax) lay.fbits[fe * lay.Wmax + lane] = x[lane];
         if (retry_mode && lane == 0) {
-            atomicAdd(&lay.ctr[CTR_PAIRS], (unsigned long long)N * (N - 1) / 2);
+            // with the site bound the pairs are counted once the entries are sorted out
+            if (!lay.sb) atomicAdd(&lay.ctr[CTR_PAIRS], (unsigned long long)N * (N - 1) / 2);
             atomicAdd(&lay.ctr[CTR_SINGLES], (unsigned long long)N);
+        }
+        // site bound: the pairs of a state with few candidate sites are evaluated
+        // here, exactly in FP64, and its FP32 rows are not needed
+        bool full = true;
+        if (lay.sb) {
+            const int r = site_bound_pairs(lay, b, s, code, Em, T, x, F, N, Np, sb_idx[wave], sb_a[wave]);
+            full = r < 0;
+            if (lane == 0) lay.fr_bound[fe] = (uint16_t)(r + 1);
         }
         // slack of the FP32 threshold, from the instance's bound on |a|
         const double u = 5.9604644775390625e-08;   // 2^-24
@@ -162,8 +173,10 @@ __global__ __launch_bounds__(256) void k_prep32(Layout lay, const long long* __r
             double a = 0.0;
             if (i < N) a = -2.0 * spin_d(x, i) * F[i];
             if (lay.tr_feat) A[i] = a;   // FP64 a is read back only by trace capture
-            A32[i] = i < N ? (float)(from_ft ? -2.0 * spin_d(x, i) * (double)Ft[i] : a) : 0.f;
-            RR[i] = i < N ? __double2float_ru(T - a + delta) : -INFINITY;
+            if (full) {
+                A32[i] = i < N ? (float)(from_ft ? -2.0 * spin_d(x, i) * (double)Ft[i] : a) : 0.f;
+                RR[i] = i < N ? __double2float_ru(T - a + delta) : -INFINITY;
+            }
             nhit += __builtin_popcountll(__builtin_amdgcn_ballot_w64(i < N && Em + a <= c));
         }
         int base = 0;
@@ -243,7 +256,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     __shared__ double sT[64], sE[64];
     __shared__ int sS[64], sCode[64];
     __shared__ uint64_t sWi[64], sWj[64];
-    constexpr int PEND = 768;
+    __shared__ size_t sFe[64];
+    constexpr int PEND = 640;
     __shared__ uint32_t pend[PEND];   // admitted pairs awaiting the FP64 re-score: k << 12 | row << 6 | col
     const uint32_t lane = lane_id32();
     const long long total = iprefix[lay.B];
@@ -267,10 +281,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         while (t >= nb - bi) { t -= nb - bi; ++bi; }
         bi = __builtin_amdgcn_readfirstlane(bi);
         const int bj = __builtin_amdgcn_readfirstlane(bi + t);
-        const int P = lay.fr_count[b];
+        const int P = lay.sb ? lay.full_count[b] : lay.fr_count[b];
         const int sc = lay.scb[b];
         const int f0 = c * sc;
         const int f1 = min(f0 + sc, P);
+        const size_t fb = (size_t)b * lay.fmax;
         const int row = bi * TILE + (int)lane;
         const int col0 = bj * T32;
         const float* Jt = J32 + lay.joff[b];
@@ -321,29 +336,32 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         };
         for (int g0 = f0; g0 < f1; g0 += 64) {
             const int ns = min(64, f1 - g0);
-            const size_t fe0 = (size_t)b * lay.fmax + g0;
+            // the records of states g0 .. g0+ns-1 (with the site bound, the
+            // entries left to the scan)
             if ((int)lane < ns) {
-                const FrRec rc = recs[fe0 + lane];
+                const size_t fe = fb + (lay.sb ? lay.full_list[fb + g0 + lane] : g0 + (int)lane);
+                const FrRec rc = recs[fe];
                 sT[lane] = rc.T;
                 sE[lane] = rc.E;
                 sS[lane] = rc.s;
                 sCode[lane] = rc.code;
-                const uint64_t* fw = fbits + (fe0 + lane) * Wm;
+                sFe[lane] = fe;
+                const uint64_t* fw = fbits + fe * Wm;
                 sWi[lane] = fw[bi];
                 sWj[lane] = fw[bj];
             }
-            const float* A0 = A32 + fe0 * Npm;
-            const float* R0 = RR32 + fe0 * Npm;
-            float nrr = R0[row];
-            float naj = A0[col0 + lane];
+            __syncthreads();
+            float nrr = RR32[sFe[0] * Npm + row];
+            float naj = A32[sFe[0] * Npm + col0 + lane];
             int cur = 0;
             abuf[0][lane] = naj;
             __syncthreads();
             for (int k = 0; k < ns; ++k) {
                 const float rrt = nrr;
                 if (k + 1 < ns) {
-                    nrr = R0[(size_t)(k + 1) * Npm + row];
-                    naj = A0[(size_t)(k + 1) * Npm + col0 + lane];
+                    const size_t fn = sFe[k + 1] * Npm;
+                    nrr = RR32[fn + row];
+                    naj = A32[fn + col0 + lane];
                 }
                 const int s = __builtin_amdgcn_readfirstlane(sS[k]);
                 const bool skip = retry_mode && !lay.retry[s];
@@ -429,7 +447,7 @@ __global__ __launch_bounds__(1024) void k_plan32(Layout lay, long long* __restri
     const int b0 = t * per;
     long long items = 0;
     for (int b = b0; b < b0 + per && b < lay.B; ++b) {
-        const long long P = lay.fr_count[b];
+        const long long P = lay.sb ? lay.full_count[b] : lay.fr_count[b];
         items += (P + lay.scb[b] - 1) / lay.scb[b] * tiles64(lay.N[b]);
     }
     part[t] = items;
@@ -443,7 +461,8 @@ __global__ __launch_bounds__(1024) void k_plan32(Layout lay, long long* __restri
     long long run = part[t] - items;
     for (int b = b0; b < b0 + per && b < lay.B; ++b) {
         iprefix[b] = run;
-        run += (lay.fr_count[b] + lay.scb[b] - 1) / lay.scb[b] * tiles64(lay.N[b]);
+        const long long P = lay.sb ? lay.full_count[b] : lay.fr_count[b];
+        run += (P + lay.scb[b] - 1) / lay.scb[b] * tiles64(lay.N[b]);
     }
     if (t == 1023) iprefix[lay.B] = part[1023];
 }

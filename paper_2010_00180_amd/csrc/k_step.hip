@@ -469,7 +469,8 @@ __global__ __launch_bounds__(1024) void k_plan(Layout lay, long long* __restrict
         items += (P + sc - 1) / sc * tiles_of((int)N);
         fr += P + Q;
         lr += Q;
-        pairs += P * (N * (N - 1) / 2) + Q * proposals_of(lay, N);
+        // with the site bound the pairs are counted once the entries are sorted out
+        pairs += (lay.sb ? 0 : P * (N * (N - 1) / 2)) + Q * proposals_of(lay, N);
         scored += Q * (N * (N - 1) / 2);
         singles += (P + Q) * N;
     }
@@ -539,6 +540,8 @@ __device__ inline int find_instance(const long long* prefix, int B, long long e)
 // state's words next to it, and the single flips below the cut.
 __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __restrict__ fr_prefix)
 {
+    __shared__ uint16_t sb_idx[4][SB_CAP];
+    __shared__ double sb_a[4][SB_CAP];
     const long long total = fr_prefix[lay.B];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63;
@@ -570,9 +573,17 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
         if ((int)lane < lay.Wmax) lay.fbits[fe * lay.Wmax + lane] = x[lane];
         if (retry_mode && lane == 0) {
             const unsigned long long all = (unsigned long long)N * (N - 1) / 2;
-            atomicAdd(&lay.ctr[CTR_PAIRS], ranked ? (unsigned long long)proposals_of(lay, N) : all);
+            // with the site bound the pairs are counted once the entries are sorted out
+            if (!lay.sb) atomicAdd(&lay.ctr[CTR_PAIRS], ranked ? (unsigned long long)proposals_of(lay, N) : all);
             atomicAdd(&lay.ctr[CTR_SINGLES], (unsigned long long)N);
             if (ranked) atomicAdd(&lay.ctr[CTR_SCORED], all);
+        }
+        // site bound: the pairs of a state with few candidate sites are evaluated here
+        bool full = true;
+        if (lay.sb) {
+            const int r = site_bound_pairs(lay, b, s, code, Em, c - Em, x, F, N, Np, sb_idx[wave], sb_a[wave]);
+            full = r < 0;
+            if (lane == 0) lay.fr_bound[fe] = (uint16_t)(r + 1);
         }
         // a_i, and the single flips below the cut: counted first, so that one
         // atomic reserves their places, then recorded
@@ -581,7 +592,7 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
             const int i = i0 + lane;
             double a = 0.0;
             if (i < N) a = -2.0 * spin_of(x, i) * F[i];
-            A[i] = a;
+            if (full) A[i] = a;
             // a ranked state's singles go with its pairs
             nhit += __builtin_popcountll(__builtin_amdgcn_ballot_w64(!ranked && i < N && Em + a <= c));
         }
@@ -646,7 +657,7 @@ __device__ inline void flush_stage(const Layout& lay, Surv* stage, int& n, int s
     n = 0;
 }
 
-__global__ __launch_bounds__(64) void k_scan(Layout lay, const double* __restrict__ J4,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_scan(Layout lay, const double* __restrict__ J4,
                                              const double* __restrict__ Abuf,
                                              const FrRec* __restrict__ recs,
                                              const uint64_t* __restrict__ fbits)
@@ -658,6 +669,7 @@ __global__ __launch_bounds__(64) void k_scan(Layout lay, const double* __restric
     __shared__ int sS[64], sCode[64];
     __shared__ uint32_t sWj[64];
     __shared__ uint64_t sWi[64];
+    __shared__ size_t sFe[64];
     const uint32_t lane = lane_id();
     const long long total = lay.item_prefix[lay.B];
     const int retry_mode = lay.flags[FLAG_RETRY_MODE];
@@ -683,10 +695,11 @@ __global__ __launch_bounds__(64) void k_scan(Layout lay, const double* __restric
         while (t >= nc - 2 * bi) { t -= nc - 2 * bi; ++bi; }
         bi = uniform_int(bi);
         const int bc = uniform_int(2 * bi + t);
-        const int P = lay.fr_count[b];
+        const int P = lay.sb ? lay.full_count[b] : lay.fr_count[b];
         const int sc = lay.scb[b];
         const int f0 = c * sc;
         const int f1 = min(f0 + sc, P);
+        const size_t fb = (size_t)b * lay.fmax;
 
         // the tile: row i = bi*64 + lane, columns j = bc*32 + 0..31, unsigned
         const int row = bi * TILE + (int)lane;
@@ -705,19 +718,22 @@ __global__ __launch_bounds__(64) void k_scan(Layout lay, const double* __restric
         int nstage = 0, sstage = -1;
         for (int g0 = f0; g0 < f1; g0 += 64) {
             const int ns = min(64, f1 - g0);
-            const size_t fe0 = (size_t)b * lay.fmax + g0;
-            // stage the records of states g0 .. g0+ns-1
+            // stage the records of states g0 .. g0+ns-1 (with the site bound, the
+            // entries left to the scan)
             if ((int)lane < ns) {
-                const FrRec rc = recs[fe0 + lane];
+                const size_t fe = fb + (lay.sb ? lay.full_list[fb + g0 + lane] : g0 + (int)lane);
+                const FrRec rc = recs[fe];
                 sT[lane] = rc.T;
                 sE[lane] = rc.E;
                 sS[lane] = rc.s;
                 sCode[lane] = rc.code;
-                const uint64_t* fw = fbits + (fe0 + lane) * Wm;
+                sFe[lane] = fe;
+                const uint64_t* fw = fbits + fe * Wm;
                 sWi[lane] = fw[wrow];
                 sWj[lane] = (uint32_t)(fw[wcol] >> shcol);
             }
-            const double* A0 = Abuf + fe0 * Npm;   // a values of state g0
+            __syncthreads();
+            const double* A0 = Abuf + sFe[0] * Npm;   // a values of state g0
             double nai = A0[row];
             double naj = lane < TCOL ? A0[col0 + lane] : 0.0;
             int cur = 0;
@@ -726,7 +742,7 @@ __global__ __launch_bounds__(64) void k_scan(Layout lay, const double* __restric
             for (int k = 0; k < ns; ++k) {
                 const double ai = nai;
                 if (k + 1 < ns) {
-                    const double* An = A0 + (size_t)(k + 1) * Npm;
+                    const double* An = Abuf + sFe[k + 1] * Npm;
                     nai = An[row];
                     if (lane < TCOL) naj = An[col0 + lane];
                 }
@@ -1518,11 +1534,88 @@ hipError_t launch_clear_survivors(const Layout& lay, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_prep(const Layout& lay, hipStream_t st)
+// Site bound: the entries of instance b that the preparation left to the scan,
+// in frontier order (consecutive states of a search stay together, so a scan
+// item re-signs few columns between them), and the pair count of the step.
+__global__ __launch_bounds__(256) void k_sb_list(Layout lay, int count)
 {
-    if (lay.form == 1) return launch_prep32(lay, st);
+    __shared__ int tmp[256];
+    const int b = blockIdx.x;
+    const int P = lay.fr_count[b];
+    const size_t fb = (size_t)b * lay.fmax;
+    const int retry_mode = lay.flags[FLAG_RETRY_MODE];
+    const unsigned long long N = (unsigned long long)lay.N[b];
+    unsigned long long pairs = 0, bounded = 0;
+    int nfull = 0;
+    for (int f0 = 0; f0 < P; f0 += 256) {
+        const int f = f0 + (int)threadIdx.x;
+        int isfull = 0;
+        if (f < P) {
+            const int v = lay.fr_bound[fb + f];
+            isfull = v == 0;
+            const int s = lay.fr_list[fb + f] / (2 * lay.M);
+            if (!retry_mode || lay.retry[s]) {
+                pairs += isfull ? N * (N - 1) / 2 : (unsigned long long)(v - 1) * (v - 2) / 2;
+                bounded += isfull ? 0 : 1;
+            }
+        }
+        int excl;
+        const int tot = block_exclusive_scan(isfull, tmp, excl);
+        if (isfull) lay.full_list[fb + nfull + excl] = f;
+        nfull += tot;
+    }
+    if (threadIdx.x == 0) lay.full_count[b] = nfull;
+    if (count) {
+        for (int off = 32; off > 0; off >>= 1) {
+            pairs += __shfl_xor(pairs, off, 64);
+            bounded += __shfl_xor(bounded, off, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            if (pairs) atomicAdd(&lay.ctr[CTR_PAIRS], pairs);
+            if (bounded) atomicAdd(&lay.ctr[CTR_BOUNDED], bounded);
+        }
+    }
+}
+
+// Scan items of the FP64 scan over the entries left to it.
+__global__ __launch_bounds__(1024) void k_sb_items(Layout lay)
+{
+    __shared__ long long part[1024];
+    const int t = threadIdx.x;
+    const int per = (lay.B + 1023) / 1024;
+    const int b0 = t * per;
+    long long items = 0;
+    for (int b = b0; b < b0 + per && b < lay.B; ++b)
+        items += ((long long)lay.full_count[b] + lay.scb[b] - 1) / lay.scb[b] * tiles_of(lay.N[b]);
+    part[t] = items;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const long long a = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += a;
+        __syncthreads();
+    }
+    long long run = part[t] - items;
+    for (int b = b0; b < b0 + per && b < lay.B; ++b) {
+        lay.item_prefix[b] = run;
+        run += ((long long)lay.full_count[b] + lay.scb[b] - 1) / lay.scb[b] * tiles_of(lay.N[b]);
+    }
+    if (t == 1023) lay.item_prefix[lay.B] = part[1023];
+}
+
+hipError_t launch_prep(const Layout& lay, hipStream_t st, bool count)
+{
+    if (lay.form == 1) {
+        hipError_t e = launch_prep32(lay, st);
+        if (e == hipSuccess && lay.sb) hipLaunchKernelGGL(k_sb_list, dim3(lay.B), dim3(256), 0, st, lay, count ? 1 : 0);
+        return e == hipSuccess ? hipGetLastError() : e;
+    }
     const long long* fr_prefix = lay.item_prefix + (lay.B + 1);
     hipLaunchKernelGGL(k_prep, dim3(4096), dim3(256), 0, st, lay, fr_prefix);
+    if (lay.sb) {
+        hipLaunchKernelGGL(k_sb_list, dim3(lay.B), dim3(256), 0, st, lay, count ? 1 : 0);
+        hipLaunchKernelGGL(k_sb_items, dim3(1), dim3(1024), 0, st, lay);
+    }
     return hipGetLastError();
 }
 

@@ -315,3 +315,100 @@ def test_split_form_matches_plain_full_c2():
     assert 0.0 < st["split_field_err"] <= max(ebf_bound(i) for i in w.instances)
     a.destroy()
     s.destroy()
+
+
+# ---------------------------------------------------------------- site bound
+# Pair flips whose two sites cannot both satisfy a_i + min a - max_k |4J_ik| <= T
+# are skipped; the kept sets must stay those of the full scan (and the oracle's).
+@pytest.mark.parametrize("form", [binding.FORM_PLAIN, binding.FORM_SPLIT_BF16])
+@pytest.mark.parametrize("N,M,L,dist", [(24, 8, 4, "sk"), (65, 40, 2, "sk"), (130, 60, 2, "sk"),
+                                        (200, 120, 1, "sk"), (70, 50, 2, "pmj"), (90, 30, 2, "sk_h0")])
+def test_site_bound_stepwise(form, N, M, L, dist):
+    w = wl.custom([N], L=L, M=M, config=23, dist=dist, seed_offset=N + 3 * M)
+    st = stepwise_parity(w, f"site bound form={form} N={N} {dist}", form=form, flags=binding.FLAG_SITE_BOUND)
+    note(f"  bounded {st['bounded_states']} of {st['frontier_states']} states, pairs {st['pair_evals']}")
+    assert st["bounded_states"] > 0
+    assert st["pair_evals"] < st["frontier_states"] * N * (N - 1) // 2
+
+
+def test_site_bound_uneven_and_tiles():
+    w = wl.custom([5, 64, 65, 100, 129], L=2, M=30, config=24)
+    stepwise_parity(w, "site bound uneven sc=7", flags=binding.FLAG_SITE_BOUND, states_per_item=7)
+
+
+def test_site_bound_matches_full_scan_c2():
+    """120 instances, N=200, L=16, M=120: every search and every merged set equal
+    with and without the bound, for both forms; fewer pairs evaluated."""
+    w = wl.c2_n200()
+    for form in (binding.FORM_PLAIN, binding.FORM_SPLIT_BF16):
+        note(f"[site bound c2] form {form}")
+        a = binding.IsingSearch.from_workload(w, form=form)
+        s = binding.IsingSearch.from_workload(w, form=form, flags=binding.FLAG_SITE_BOUND)
+        ia, _ = a.run()
+        is_, stable = s.run()
+        assert stable and ia == is_
+        for sid in range(w.n_searches):
+            assert_same_set(s.get_search(sid), a.get_search(sid), f"site bound c2 search {sid}")
+        for b in range(len(w.instances)):
+            ab, aE = a.get_states(b)
+            sb, sE = s.get_states(b)
+            assert np.array_equal(ab, sb) and np.array_equal(aE, sE)
+        sa, ss = a.stats(), s.stats()
+        note(f"  pairs {sa['pair_evals']:.3e} -> {ss['pair_evals']:.3e}, bounded {ss['bounded_states']} of "
+             f"{ss['frontier_states']}")
+        assert ss["frontier_states"] == sa["frontier_states"]
+        assert ss["pair_evals"] < sa["pair_evals"]
+        a.destroy()
+        s.destroy()
+
+
+def test_site_bound_persistent_and_autotune():
+    w = wl.custom([100, 200, 300, 64, 129, 600], L=3, M=40, config=25)
+    note("[site bound] graph replay and autotune vs eager")
+    a = binding.IsingSearch.from_workload(w)
+    g = binding.IsingSearch.from_workload(w, persistent=1, flags=binding.FLAG_SITE_BOUND)
+    a.step()
+    g.step()
+    g.autotune()
+    a.step()
+    for t in range(400):
+        na = a.step()
+        ng = g.step()
+        assert na == ng, f"step {t + 3}: active {na} vs {ng}"
+        for sid in range(a.B * a.L):
+            assert_same_set(g.get_search(sid), a.get_search(sid), f"site bound graph search {sid} step {t + 3}")
+        if na == 0:
+            break
+    assert na == 0
+    a.destroy()
+    g.destroy()
+
+
+def test_site_bound_n600_sampled():
+    """N=600, M=120, L=64 instances (4 of them): the split form with the bound
+    against the split form without it (whose smaller cases are checked against
+    the oracle step by step), energies of sampled kept states by Eq. 1."""
+    w = wl.c3_n600(n_instances=4)
+    note("[site bound n600] 4 instances")
+    a = binding.IsingSearch.from_workload(w, form=binding.FORM_SPLIT_BF16)
+    s = binding.IsingSearch.from_workload(w, form=binding.FORM_SPLIT_BF16, flags=binding.FLAG_SITE_BOUND)
+    ia, _ = a.run()
+    is_, stable = s.run()
+    assert stable and ia == is_
+    for sid in range(w.n_searches):
+        assert_same_set(s.get_search(sid), a.get_search(sid), f"site bound n600 search {sid}")
+    for b in range(len(w.instances)):
+        ab, aE = a.get_states(b)
+        sb, sE = s.get_states(b)
+        assert np.array_equal(ab, sb) and np.array_equal(aE, sE)
+    rng = np.random.default_rng(6)
+    for b in range(len(w.instances)):
+        inst = w.instances[b]
+        gb, gE = s.get_states(b)
+        assert len(gE) == w.M and np.all(np.diff(gE) >= 0)
+        for k in rng.choice(len(gE), 3, replace=False):
+            assert oracle.energy(inst.J, inst.h, gb[k]) == gE[k]
+    st = s.stats()
+    note(f"  steps {is_}, bounded {st['bounded_states']} of {st['frontier_states']}, pairs {st['pair_evals']:.3e}")
+    a.destroy()
+    s.destroy()
