@@ -253,7 +253,8 @@ int ising_search_set_scorer(ising_search_t *s, int32_t scorer, const float *para
  * k < capacity.  feat and label are device pointers owned by the caller and
  * must stay valid while tracing; NULL, NULL, 0 stops tracing.  The count of
  * samples offered (possibly above capacity) is reset here and read with
- * ising_search_get_trace_count.
+ * ising_search_get_trace_count.  Errors: BAD_STATE (a handle made with
+ * ISING_FLAG_SITE_BOUND, which does not keep every expanded state's a row).
  */
 int ising_search_set_trace(ising_search_t *s, float *feat, uint8_t *label, int64_t capacity,
                            int32_t pairs_per_state, float rate, uint64_t seed);

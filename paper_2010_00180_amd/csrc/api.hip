@@ -1099,6 +1099,8 @@ extern "C" int ising_search_set_trace(ising_search_t* s, float* feat, uint8_t* l
     g_err.clear();
     int rc = check_handle(s);
     if (rc != ISING_OK) return rc;
+    if (s->lay.sb && feat)
+        return fail(ISING_ERR_BAD_STATE, "trace capture reads every expanded state's a row, which the site bound skips");
     Layout& lay = s->lay;
     if (!feat || !label || capacity <= 0) {
         if (feat || label || capacity != 0) return fail(ISING_ERR_INVALID_ARG, "trace buffers: all NULL / 0 to stop");

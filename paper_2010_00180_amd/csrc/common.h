@@ -156,34 +156,55 @@ __host__ __device__ inline long long tiles_of(int N) {
 
 // Site bound of one frontier state, evaluated by one wave.  The pair (i, j)
 // changes the energy by a_i + a_j + s_i s_j 4J_ij >= a_i + min_k a_k - max_k |4J_ik|,
-// so it can pass the cut T only if both sites satisfy
-// a_i + min_k a_k - max_k |4J_ik| <= T (all terms on the 2^-24 grid: exact).
+// so it can pass the cut c only if both sites satisfy
+// a_i + min_k a_k - max_k |4J_ik| <= T = c - E (all terms on the 2^-24 grid: exact).
 // With at most SB_CAP such sites, every pair among them is evaluated with the
-// scan's arithmetic (x = fma(s_i, s_j 4J_ij, a_j) <= T - a_i, E = (E + a_i) + x)
-// and its survivors recorded; returns the number r of such sites (r (r - 1) / 2
-// pairs evaluated), or -1 when there are too many and the state must be scanned
-// in full.  sidx and sa are this wave's LDS arrays of SB_CAP entries.
-// The loads are batched for latency: a is held in registers (N <= 640), and
-// the pairs are taken in 8 x 8 blocks (lane = 8 p + q), four blocks per batch.
-constexpr int SB_AREG = 10;   // a held in registers when N <= 640
-__device__ inline int site_bound_pairs(const Layout& lay, int b, int s, int code, double Em, double T,
+// scan's arithmetic (x = fma(s_i, s_j 4J_ij, a_j) <= T - a_i, E' = (E + a_i) + x)
+// and its survivors recorded, and so are the single flips below the cut
+// (E + a_i <= c); returns the number r of such sites (r (r - 1) / 2 pairs
+// evaluated), or -1, having recorded nothing, when there are too many and the
+// state must be prepared for the full scan.  sidx (site | sign << 15) and sa
+// are this wave's LDS arrays of SB_CAP entries.  The loads are batched for
+// latency: a is held in registers (N <= 640), and the pairs are taken in 8 x 8
+// blocks (lane = 8 p + q), all ten blocks at once when r <= 32.
+constexpr int SB_AREG = 10;
+__device__ inline int site_bound_pairs(const Layout& lay, int b, int s, int code, double Em, double c,
                                        const uint64_t* __restrict__ x, const double* __restrict__ F,
                                        int N, int Np, uint16_t* sidx, double* sa)
 {
     const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
-    auto spin = [&](int i) -> double { return ((x[i >> 6] >> (i & 63)) & 1ull) ? -1.0 : 1.0; };
+    const double T = c - Em;
+    auto bit = [&](int i) -> uint32_t { return (uint32_t)((x[i >> 6] >> (i & 63)) & 1ull); };
     auto lane_rank = [&](uint64_t m) -> int {
         return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
     };
+    auto record = [&](bool keep, double E, uint32_t pair) {
+        const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
+        if (m) {
+            int pos0 = 0;
+            if (lane == 0) pos0 = atomicAdd(&lay.surv_count[s], __builtin_popcountll(m));
+            pos0 = __shfl(pos0, 0, 64);
+            const int pos = pos0 + lane_rank(m);
+            if (keep && pos < lay.cap_surv) {
+                Surv rec;
+                rec.E = E;
+                rec.code = (uint32_t)code;
+                rec.pair = pair;
+                lay.surv[(size_t)s * lay.cap_surv + pos] = rec;
+            }
+        }
+    };
     const double* rm = lay.rmax4 + (size_t)b * lay.Npmax;
     int r = 0;
+    uint32_t hits = 0;       // singles below the cut not yet recorded (register path, r <= 32)
+    bool any_hit = false;
+    double areg[SB_AREG];
     if (N <= 64 * SB_AREG) {
-        double areg[SB_AREG];
         double amin = INFINITY;
 #pragma unroll
         for (int k = 0; k < SB_AREG; ++k) {
             const int i = 64 * k + (int)lane;
-            areg[k] = i < N ? -2.0 * spin(i) * F[i] : 0.0;
+            areg[k] = i < N ? (bit(i) ? 2.0 : -2.0) * F[i] : 0.0;
             if (i < N) amin = fmin(amin, areg[k]);
         }
         for (int off = 32; off > 0; off >>= 1) amin = fmin(amin, __shfl_xor(amin, off, 64));
@@ -195,83 +216,171 @@ __device__ inline int site_bound_pairs(const Layout& lay, int b, int s, int code
             const uint64_t m = __builtin_amdgcn_ballot_w64(in);
             const int pos = r + lane_rank(m);
             if (in && pos < SB_CAP) {
-                sidx[pos] = (uint16_t)i;
+                sidx[pos] = (uint16_t)(i | (bit(i) << 15));
                 sa[pos] = areg[k];
             }
             r += __builtin_popcountll(m);
         }
         if (r > SB_CAP) return -1;
+        // single flips below the cut, as a bit mask of the lane's sites
+#pragma unroll
+        for (int k = 0; k < SB_AREG; ++k) {
+            const int i = 64 * k + (int)lane;
+            if (i < N && Em + areg[k] <= c) hits |= 1u << k;
+            if (__builtin_amdgcn_ballot_w64((hits >> k) & 1u)) any_hit = true;
+        }
+        if (r > 32) {
+#pragma unroll
+            for (int k = 0; k < SB_AREG; ++k) {
+                const int i = 64 * k + (int)lane;
+                record((hits >> k) & 1u, Em + areg[k], (uint32_t)i | (SINGLE << 16));
+            }
+            hits = 0;
+            any_hit = false;
+        }
     } else {
         double amin = INFINITY;
-        for (int i = (int)lane; i < N; i += 64) amin = fmin(amin, -2.0 * spin(i) * F[i]);
+        for (int i = (int)lane; i < N; i += 64) amin = fmin(amin, (bit(i) ? 2.0 : -2.0) * F[i]);
         for (int off = 32; off > 0; off >>= 1) amin = fmin(amin, __shfl_xor(amin, off, 64));
         for (int i0 = 0; i0 < N; i0 += 64) {
             const int i = i0 + (int)lane;
-            const bool in = i < N && (-2.0 * spin(i) * F[i] + amin) - rm[i] <= T;
+            const bool in = i < N && ((bit(i) ? 2.0 : -2.0) * F[i] + amin) - rm[i] <= T;
             r += __builtin_popcountll(__builtin_amdgcn_ballot_w64(in));
         }
         if (r > SB_CAP) return -1;
         int base = 0;
-        for (int i0 = 0; i0 < N && base < r; i0 += 64) {
+        for (int i0 = 0; i0 < N; i0 += 64) {
             const int i = i0 + (int)lane;
-            const double a = i < N ? -2.0 * spin(i) * F[i] : 0.0;
+            const double a = i < N ? (bit(i) ? 2.0 : -2.0) * F[i] : 0.0;
             const bool in = i < N && (a + amin) - rm[i] <= T;
             const uint64_t m = __builtin_amdgcn_ballot_w64(in);
             if (in) {
-                sidx[base + lane_rank(m)] = (uint16_t)i;
+                sidx[base + lane_rank(m)] = (uint16_t)(i | (bit(i) << 15));
                 sa[base + lane_rank(m)] = a;
             }
             base += __builtin_popcountll(m);
+            const double Ec = Em + a;
+            record(i < N && Ec <= c, Ec, (uint32_t)i | (SINGLE << 16));
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // 4J_ij from the exact FP32 copy when there is one (half the bytes per gather)
     const double* J4 = lay.J4 + lay.joff[b];
+    const float* J4f = lay.J4f ? lay.J4f + lay.joff[b] : nullptr;
+    auto coupling = [&](int i, int j) -> double {
+        return J4f ? (double)J4f[(size_t)i * Np + j] : J4[(size_t)i * Np + j];
+    };
     const int pp = (int)(lane >> 3), qq = (int)(lane & 7);
-    for (int P0 = 0; P0 + 1 < r; P0 += 8) {
-        const int p = P0 + pp;
-        const int i = p < r ? sidx[p] : 0;
-        const double ai = p < r ? sa[p] : 0.0;
-        const double si = spin(i);
-        const double rr = T - ai;
-        const double Ea = Em + ai;
-        const double* Jrow = J4 + (size_t)i * Np;
-        for (int Q0 = P0; Q0 < r; Q0 += 32) {
-            double xv[4];
-            bool keep[4];
-            int jj[4];
+    if (r <= 32) {
+        // rows p = 8 P + pp of the four row blocks
+        int iv[4];
+        double av[4], sv4[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int q = Q0 + 8 * u + qq;
-                keep[u] = false;
-                xv[u] = 0.0;
-                jj[u] = 0;
-                if (p < q && q < r) {
-                    const int j = sidx[q];
-                    jj[u] = j;
-                    xv[u] = fma(si, spin(j) * Jrow[j], sa[q]);
-                    keep[u] = xv[u] <= rr;
+        for (int P = 0; P < 4; ++P) {
+            const int p = 8 * P + pp;
+            const uint32_t e = p < r ? sidx[p] : 0u;
+            iv[P] = (int)(e & 0x7FFFu);
+            sv4[P] = (e >> 15) ? -1.0 : 1.0;
+            av[P] = p < r ? sa[p] : 0.0;
+        }
+        // the ten 8 x 8 blocks (P, Q), P <= Q
+        constexpr int BP[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
+        constexpr int BQ[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
+        double xv[10];
+        bool kp[10];
+        int jv[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            const int p = 8 * BP[k] + pp, q = 8 * BQ[k] + qq;
+            kp[k] = false;
+            xv[k] = 0.0;
+            jv[k] = 0;
+            if (p < q && q < r) {
+                const uint32_t e = sidx[q];
+                const int j = (int)(e & 0x7FFFu);
+                const double sj = (e >> 15) ? -1.0 : 1.0;
+                jv[k] = j;
+                xv[k] = fma(sv4[BP[k]], sj * coupling(iv[BP[k]], j), sa[q]);
+                kp[k] = xv[k] <= T - av[BP[k]];
+            }
+        }
+        // one atomic reserves the places of the state's singles and pairs
+        int cnt = __builtin_popcount(hits);
+#pragma unroll
+        for (int k = 0; k < 10; ++k) cnt += kp[k] ? 1 : 0;
+        bool any = any_hit;
+#pragma unroll
+        for (int k = 0; k < 10; ++k) any = any || __builtin_amdgcn_ballot_w64(kp[k]) != 0;
+        if (any) {
+            int excl = cnt;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int v = __shfl_up(excl, off, 64);
+                if ((int)lane >= off) excl += v;
+            }
+            const int tot = __shfl(excl, 63, 64);
+            excl -= cnt;
+            int pos0 = 0;
+            if (lane == 0) pos0 = atomicAdd(&lay.surv_count[s], tot);
+            int pos = __shfl(pos0, 0, 64) + excl;
+            Surv* out = lay.surv + (size_t)s * lay.cap_surv;
+#pragma unroll
+            for (int k = 0; k < SB_AREG; ++k) {
+                if ((hits >> k) & 1u) {
+                    if (pos < lay.cap_surv) {
+                        Surv rec;
+                        rec.E = Em + areg[k];
+                        rec.code = (uint32_t)code;
+                        rec.pair = (uint32_t)(64 * k + (int)lane) | (SINGLE << 16);
+                        out[pos] = rec;
+                    }
+                    ++pos;
                 }
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint64_t m = __builtin_amdgcn_ballot_w64(keep[u]);
-                if (m) {
-                    int pos0 = 0;
-                    if (lane == 0) pos0 = atomicAdd(&lay.surv_count[s], __builtin_popcountll(m));
-                    pos0 = __shfl(pos0, 0, 64);
-                    if (keep[u]) {
-                        const int pos = pos0 + lane_rank(m);
-                        if (pos < lay.cap_surv) {
-                            Surv rec;
-                            rec.E = Ea + xv[u];
-                            rec.code = (uint32_t)code;
-                            rec.pair = (uint32_t)i | ((uint32_t)jj[u] << 16);
-                            lay.surv[(size_t)s * lay.cap_surv + pos] = rec;
-                        }
+            for (int k = 0; k < 10; ++k) {
+                if (kp[k]) {
+                    if (pos < lay.cap_surv) {
+                        Surv rec;
+                        rec.E = (Em + av[BP[k]]) + xv[k];
+                        rec.code = (uint32_t)code;
+                        rec.pair = (uint32_t)iv[BP[k]] | ((uint32_t)jv[k] << 16);
+                        out[pos] = rec;
+                    }
+                    ++pos;
+                }
+            }
+        }
+    } else {
+        for (int P0 = 0; P0 + 1 < r; P0 += 8) {
+            const int p = P0 + pp;
+            const uint32_t ei = p < r ? sidx[p] : 0u;
+            const int i = (int)(ei & 0x7FFFu);
+            const double ai = p < r ? sa[p] : 0.0;
+            const double si = (ei >> 15) ? -1.0 : 1.0;
+            const double rr = T - ai;
+            const double Ea = Em + ai;
+            for (int Q0 = P0; Q0 < r; Q0 += 32) {
+                double xv[4];
+                bool keep[4];
+                int jj[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int q = Q0 + 8 * u + qq;
+                    keep[u] = false;
+                    xv[u] = 0.0;
+                    jj[u] = 0;
+                    if (p < q && q < r) {
+                        const uint32_t e = sidx[q];
+                        const int j = (int)(e & 0x7FFFu);
+                        jj[u] = j;
+                        xv[u] = fma(si, ((e >> 15) ? -1.0 : 1.0) * coupling(i, j), sa[q]);
+                        keep[u] = xv[u] <= rr;
                     }
                 }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) record(keep[u], Ea + xv[u], (uint32_t)i | ((uint32_t)jj[u] << 16));
             }
         }
     }

@@ -114,17 +114,27 @@ __device__ inline int find_inst(const long long* prefix, int B, long long e)
     return lo;
 }
 
-__global__ __launch_bounds__(256) void k_prep32(Layout lay, const long long* __restrict__ fr_prefix)
+template <bool SB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_prep32(Layout lay, const long long* __restrict__ fr_prefix)
 {
-    __shared__ uint16_t sb_idx[4][SB_CAP];
-    __shared__ double sb_a[4][SB_CAP];
+    __shared__ uint16_t sb_idx[SB ? 4 : 1][SB ? SB_CAP : 1];
+    __shared__ double sb_a[SB ? 4 : 1][SB ? SB_CAP : 1];
     const long long total = fr_prefix[lay.B];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63;
     const int retry_mode = lay.flags[FLAG_RETRY_MODE];
     const int first = lay.flags[FLAG_FIRST];
-    for (long long e = (long long)blockIdx.x * 4 + wave; e < total; e += (long long)gridDim.x * 4) {
-        const int b = find_inst(fr_prefix, lay.B, e);
+    // XCD x (blocks x, x + 8, ...) takes the x-th contiguous eighth of the
+    // entries, so the states it prepares at once share one L2 for their
+    // couplings
+    const int nx = gridDim.x >= 8 ? 8 : 1;
+    const int xcd = blockIdx.x % nx;
+    const long long seg1 = total * (xcd + 1) / nx;
+    const long long stride = (long long)(gridDim.x / nx) * 4;
+    int b = -1;   // instance of entry e: found once, then advanced (e only grows)
+    for (long long e = total * xcd / nx + (long long)(blockIdx.x / nx) * 4 + wave; e < seg1; e += stride) {
+        if (b < 0) b = find_inst(fr_prefix, lay.B, e);
+        while (fr_prefix[b + 1] <= e) ++b;
         const int f = (int)(e - fr_prefix[b]);
         const size_t fe = (size_t)b * lay.fmax + f;
         const int code = lay.fr_list[fe];
@@ -156,13 +166,12 @@ __global__ __launch_bounds__(256) void k_prep32(Layout lay, const long long* __r
             if (!lay.sb) atomicAdd(&lay.ctr[CTR_PAIRS], (unsigned long long)N * (N - 1) / 2);
             atomicAdd(&lay.ctr[CTR_SINGLES], (unsigned long long)N);
         }
-        // site bound: the pairs of a state with few candidate sites are evaluated
-        // here, exactly in FP64, and its FP32 rows are not needed
-        bool full = true;
-        if (lay.sb) {
-            const int r = site_bound_pairs(lay, b, s, code, Em, T, x, F, N, Np, sb_idx[wave], sb_a[wave]);
-            full = r < 0;
+        // site bound: the single and pair flips of a state with few candidate
+        // sites are evaluated here, exactly in FP64, and its FP32 rows are not needed
+        if (SB) {
+            const int r = site_bound_pairs(lay, b, s, code, Em, c, x, F, N, Np, sb_idx[wave], sb_a[wave]);
             if (lane == 0) lay.fr_bound[fe] = (uint16_t)(r + 1);
+            if (r >= 0) continue;
         }
         // slack of the FP32 threshold, from the instance's bound on |a|
         const double u = 5.9604644775390625e-08;   // 2^-24
@@ -173,10 +182,8 @@ __global__ __launch_bounds__(256) void k_prep32(Layout lay, const long long* __r
             double a = 0.0;
             if (i < N) a = -2.0 * spin_d(x, i) * F[i];
             if (lay.tr_feat) A[i] = a;   // FP64 a is read back only by trace capture
-            if (full) {
-                A32[i] = i < N ? (float)(from_ft ? -2.0 * spin_d(x, i) * (double)Ft[i] : a) : 0.f;
-                RR[i] = i < N ? __double2float_ru(T - a + delta) : -INFINITY;
-            }
+            A32[i] = i < N ? (float)(from_ft ? -2.0 * spin_d(x, i) * (double)Ft[i] : a) : 0.f;
+            RR[i] = i < N ? __double2float_ru(T - a + delta) : -INFINITY;
             nhit += __builtin_popcountll(__builtin_amdgcn_ballot_w64(i < N && Em + a <= c));
         }
         int base = 0;
@@ -470,7 +477,8 @@ __global__ __launch_bounds__(1024) void k_plan32(Layout lay, long long* __restri
 hipError_t launch_prep32(const Layout& lay, hipStream_t st)
 {
     const long long* fr_prefix = lay.item_prefix + (lay.B + 1);
-    hipLaunchKernelGGL(k_prep32, dim3(4096), dim3(256), 0, st, lay, fr_prefix);
+    if (lay.sb) hipLaunchKernelGGL(k_prep32<true>, dim3(4096), dim3(256), 0, st, lay, fr_prefix);
+    else hipLaunchKernelGGL(k_prep32<false>, dim3(4096), dim3(256), 0, st, lay, fr_prefix);
     return hipGetLastError();
 }
 

@@ -538,16 +538,26 @@ __device__ inline int find_instance(const long long* prefix, int B, long long e)
 // One wave per frontier entry: a_i = -2 s_i F_i, the per-state record the
 // scan reads (threshold T = cut - E, energy, search, slot), a copy of the
 // state's words next to it, and the single flips below the cut.
+template <bool SB>
 __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __restrict__ fr_prefix)
 {
-    __shared__ uint16_t sb_idx[4][SB_CAP];
-    __shared__ double sb_a[4][SB_CAP];
+    __shared__ uint16_t sb_idx[SB ? 4 : 1][SB ? SB_CAP : 1];
+    __shared__ double sb_a[SB ? 4 : 1][SB ? SB_CAP : 1];
     const long long total = fr_prefix[lay.B];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63;
     const int retry_mode = lay.flags[FLAG_RETRY_MODE];
-    for (long long e = (long long)blockIdx.x * 4 + wave; e < total; e += (long long)gridDim.x * 4) {
-        const int b = find_instance(fr_prefix, lay.B, e);
+    // XCD x (blocks x, x + 8, ...) takes the x-th contiguous eighth of the
+    // entries, so the states it prepares at once share one L2 for their
+    // couplings
+    const int nx = gridDim.x >= 8 ? 8 : 1;
+    const int xcd = blockIdx.x % nx;
+    const long long seg1 = total * (xcd + 1) / nx;
+    const long long stride = (long long)(gridDim.x / nx) * 4;
+    int b = -1;   // instance of entry e: found once, then advanced (e only grows)
+    for (long long e = total * xcd / nx + (long long)(blockIdx.x / nx) * 4 + wave; e < seg1; e += stride) {
+        if (b < 0) b = find_instance(fr_prefix, lay.B, e);
+        while (fr_prefix[b + 1] <= e) ++b;
         const int f = (int)(e - fr_prefix[b]);
         const int P = lay.fr_count[b];
         const bool ranked = f >= P;   // learned form: a ranked entry, listed from the back
@@ -578,12 +588,12 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
             atomicAdd(&lay.ctr[CTR_SINGLES], (unsigned long long)N);
             if (ranked) atomicAdd(&lay.ctr[CTR_SCORED], all);
         }
-        // site bound: the pairs of a state with few candidate sites are evaluated here
-        bool full = true;
-        if (lay.sb) {
-            const int r = site_bound_pairs(lay, b, s, code, Em, c - Em, x, F, N, Np, sb_idx[wave], sb_a[wave]);
-            full = r < 0;
+        // site bound: the single and pair flips of a state with few candidate
+        // sites are evaluated here, and the scan does not need its a row
+        if (SB) {
+            const int r = site_bound_pairs(lay, b, s, code, Em, c, x, F, N, Np, sb_idx[wave], sb_a[wave]);
             if (lane == 0) lay.fr_bound[fe] = (uint16_t)(r + 1);
+            if (r >= 0) continue;
         }
         // a_i, and the single flips below the cut: counted first, so that one
         // atomic reserves their places, then recorded
@@ -592,7 +602,7 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
             const int i = i0 + lane;
             double a = 0.0;
             if (i < N) a = -2.0 * spin_of(x, i) * F[i];
-            if (full) A[i] = a;
+            A[i] = a;
             // a ranked state's singles go with its pairs
             nhit += __builtin_popcountll(__builtin_amdgcn_ballot_w64(!ranked && i < N && Em + a <= c));
         }
@@ -1611,7 +1621,8 @@ hipError_t launch_prep(const Layout& lay, hipStream_t st, bool count)
         return e == hipSuccess ? hipGetLastError() : e;
     }
     const long long* fr_prefix = lay.item_prefix + (lay.B + 1);
-    hipLaunchKernelGGL(k_prep, dim3(4096), dim3(256), 0, st, lay, fr_prefix);
+    if (lay.sb) hipLaunchKernelGGL(k_prep<true>, dim3(4096), dim3(256), 0, st, lay, fr_prefix);
+    else hipLaunchKernelGGL(k_prep<false>, dim3(4096), dim3(256), 0, st, lay, fr_prefix);
     if (lay.sb) {
         hipLaunchKernelGGL(k_sb_list, dim3(lay.B), dim3(256), 0, st, lay, count ? 1 : 0);
         hipLaunchKernelGGL(k_sb_items, dim3(1), dim3(1024), 0, st, lay);

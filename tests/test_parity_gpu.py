@@ -412,3 +412,15 @@ def test_site_bound_n600_sampled():
     note(f"  steps {is_}, bounded {st['bounded_states']} of {st['frontier_states']}, pairs {st['pair_evals']:.3e}")
     a.destroy()
     s.destroy()
+
+
+def test_site_bound_rejects_trace_capture():
+    import torch
+    w = wl.custom([40], L=2, M=8, config=26)
+    s = binding.IsingSearch.from_workload(w, flags=binding.FLAG_SITE_BOUND)
+    feat = torch.zeros((16, 4), dtype=torch.float32, device="cuda")
+    lab = torch.zeros(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(binding.IsingError):
+        s.set_trace(feat.data_ptr(), lab.data_ptr(), 16)
+    assert "site bound" in binding.last_error()
+    s.destroy()
