@@ -13,8 +13,10 @@ FP32 pair scan with a proven slack, FP64 re-score; kept sets identical to the
 FP64 form); the plain FP64 form runs the same workload for comparison; the
 learned-proposal form (network trained first on traces of other instances of
 the same shape) runs a bounded sample of it, next to the plain form on the
-same sample, and its miss rate is judged against full enumeration.  Prints
-one JSON line.
+same sample, and its miss rate is judged against full enumeration.  The
+*_bound forms run the plain and split forms with the site bound (only pair
+flips that can pass the cut are evaluated, kept sets identical): they give the
+shortest time to solution, not an evaluation rate.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
@@ -35,7 +37,7 @@ METRIC = "pair-flip ΔE evals/s + time-to-solution/instance at N=600,M=120 vs pl
 # not use, so the FP32 scan can reach half of its peak).
 VALU_LANE_OPS_PER_S = {"f64": 256 * 4 * 16 * 2.4e9, "f32": 2 * 256 * 4 * 16 * 2.4e9}
 OPS_PER_PAIR = 2          # fma(s_i, s_j 4J_ij, a_j) and the compare with T - a_i (a running minimum)
-FORM_DTYPE = {"plain": "f64", "split_bf16": "f32", "learned": "f64"}
+FORM_DTYPE = {"plain": "f64", "split_bf16": "f32", "learned": "f64", "plain_bound": "f64", "split_bf16_bound": "f64"}
 
 
 def log(msg):
@@ -99,7 +101,12 @@ def cpu_baseline(w, budget_s):
     }
 
 
-FORM_CODES = {"plain": 0, "split_bf16": 1, "learned": 2}
+FORM_CODES = {"plain": 0, "split_bf16": 1, "learned": 2, "plain_bound": 0, "split_bf16_bound": 1}
+# the *_bound forms run with the site bound (only the pairs that can pass the
+# cut are evaluated; identical kept sets): a time-to-solution figure, not an
+# evaluation rate
+FORM_FLAGS = {"plain_bound": 2, "split_bf16_bound": 2}
+HBM_PEAK_GBS = 8000.0
 # multiply-adds of the scoring network per pair, counted as 2 flops each:
 # layer 1 (4 x 64), layer 2 (64 x 64), output (64)
 NET_FLOP_PER_PAIR = 2 * (4 * 64 + 64 * 64 + 64)
@@ -233,7 +240,7 @@ def measure_learned(binding, torch, w, params, steps):
 def measure(binding, torch, w, form, steps, warmup, batching, copy_gib):
     """Complete passes of the method over the batch with one form; device-timed."""
     s = binding.IsingSearch.from_workload(w, timing=1, persistent=1 if batching else 0,
-                                          form=FORM_CODES[form])
+                                          form=FORM_CODES[form], flags=FORM_FLAGS.get(form, 0))
     torch.cuda.synchronize()
     tuned = [False]
 
@@ -280,6 +287,31 @@ def measure(binding, torch, w, form, steps, warmup, batching, copy_gib):
         log(f"calibration copy: {n * 8} bytes read, {n * 8} bytes written")
     s.destroy()
     torch.cuda.synchronize()
+    if form in FORM_FLAGS:
+        # the preparation kernel evaluates the bounded states: its algorithmic
+        # bytes are the F row of each expanded state (8N) and one FP32 coupling
+        # per evaluated pair (4)
+        prep_s = d["prep_ms"] / 1e3
+        N = w.instances[0].N
+        nbytes = d["frontier_states"] * 8 * N + 4 * pairs
+        gbs = nbytes / prep_s / 1e9 if prep_s > 0 else 0.0
+        roofline = {
+            "kernel": "k_prep32 (site bound)" if FORM_CODES[form] == 1 else "k_prep (site bound)",
+            "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "avg_launch_ms": d["prep_ms"] / launches,
+            "bytes_model": "8N per expanded state (its F row) + 4 per evaluated pair (an FP32 coupling)",
+        }
+    else:
+        roofline = {
+            "kernel": "k_scan32" if form == "split_bf16" else "k_scan",
+            "bound": "alu",
+            "achieved": ops_per_s / 1e12,
+            "peak": peak / 1e12,
+            "unit": "Tops/s",
+            "frac": ops_per_s / peak,
+            "avg_launch_ms": d["scan_ms"] / launches,
+            "ops_per_pair": OPS_PER_PAIR,
+        }
     return {
         "wall": wall, "steps": steps, "warmup": warmup, "pairs": pairs,
         "value": pairs / wall,
@@ -293,16 +325,9 @@ def measure(binding, torch, w, form, steps, warmup, batching, copy_gib):
         "survivors": d["survivors"], "retries": d["retries"], "fallbacks": d["fallbacks"],
         "split_field_err": st1.get("split_field_err"),
         "scan_states_per_item": sorted(set(zip([i.N for i in w.instances], tiles))),
-        "roofline": {
-            "kernel": "k_scan32" if form == "split_bf16" else "k_scan",
-            "bound": "alu",
-            "achieved": ops_per_s / 1e12,
-            "peak": peak / 1e12,
-            "unit": "Tops/s",
-            "frac": ops_per_s / peak,
-            "avg_launch_ms": d["scan_ms"] / launches,
-            "ops_per_pair": OPS_PER_PAIR,
-        },
+        "bounded_states": d.get("bounded_states", 0),
+        "expanded_states": d["frontier_states"],
+        "roofline": roofline,
     }
 
 
@@ -317,7 +342,7 @@ def main():
                          "L=32, run as the batching form (persistent graph, autotuned tiles)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--forms", default="split_bf16,plain,learned",
+    ap.add_argument("--forms", default="split_bf16,plain,split_bf16_bound,plain_bound,learned",
                     help="comma list of forms to time; the first gives the headline value")
     ap.add_argument("--learned-instances", type=int, default=2,
                     help="instances of the workload the learned form runs on (a bounded sample)")
@@ -423,6 +448,7 @@ def main():
         "roofline": roof,
         "forms": {f: {k: v for k, v in r.items() if k not in ("E1", "wall", "pairs")} for f, r in results.items()},
         "forms_same_E1": all(r["E1"] == head["E1"] for r in results.values()),
+        "tts_per_instance_s_by_form": {f: r["time_per_instance_s"] for f, r in results.items()},
         "learned": learned,
         "cpu_baseline": cpu,
     }

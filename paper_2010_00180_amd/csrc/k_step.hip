@@ -1082,19 +1082,25 @@ __device__ inline uint64_t mix_state(uint64_t z, double e)
     return x;
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_merge(Layout lay, const double* __restrict__ J4)
+static_assert(MERGE_CH == 2048, "the slot bookkeeping of k_merge lives in the upper halves of key and zk");
+
+// At most 52 KB of LDS: three blocks share a CU, which the merge, bound by the
+// latency of its gathers, needs.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_merge(Layout lay, const double* __restrict__ J4)
 {
     __shared__ uint64_t kz[2 * MERGE_CH];   // key then zk; the dedupe table before them
     __shared__ uint32_t ref[MERGE_CH];
     __shared__ uint8_t keep[MERGE_CH];
     __shared__ int tmp[256];
-    __shared__ double red[256];
+    __shared__ double red[8];
     __shared__ int hist[NBIN];
-    __shared__ int freeslot[2048];
     double* const key = reinterpret_cast<double*>(kz);
     uint64_t* const zk = kz + MERGE_CH;
-    __shared__ int kslot[1024];
-    __shared__ uint8_t used[2048];
+    // once the new set is chosen only its first M <= 1024 rows of key and zk
+    // are read; the slot bookkeeping takes the upper halves
+    int* const freeslot = reinterpret_cast<int*>(kz + MERGE_CH / 2);             // [2M]
+    int* const kslot = reinterpret_cast<int*>(kz + MERGE_CH + MERGE_CH / 2);     // [M]
+    uint8_t* const used = reinterpret_cast<uint8_t*>(kz + MERGE_CH + MERGE_CH / 2 + MERGE_CH / 4);   // [2M]
     const int s = blockIdx.x;
     const int b = s / lay.L;
     const int M = lay.M;
@@ -1246,7 +1252,46 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         const int np = tmp[2];
         __syncthreads();
         if (np <= MERGE_CH) {
-            nrun = sort_dedupe_keep(src, W, key, ref, zk, np, M, tmp, keep);
+            if (np <= 256) {
+                // few representatives: the rank of each in the (E, psi, ref)
+                // order is the count of those before it, and it moves there
+                // (ranks are distinct: the order is total)
+                const int t = (int)threadIdx.x;
+                double kt = 0.0;
+                uint32_t rt = 0;
+                uint64_t zt = 0;
+                if (t < np) {
+                    kt = key[t];
+                    rt = ref[t];
+                    zt = zk[t];
+                }
+                int rank = 0, same = 0;
+                const StateLess<SearchSrc> less{&src, W, false};
+                for (int j = 0; j < np; ++j) {
+                    const double kj = key[j];
+                    if (kj < kt) {
+                        ++rank;
+                    } else if (kj == kt && j != t && t < np) {
+                        // equal energies: the same state under two hash keys
+                        // (+0 and -0) is left to the sort; else psi decides
+                        if (zk[j] == zt) same = 1;
+                        else if (less(kj, ref[j], zk[j], kt, rt, zt)) ++rank;
+                    }
+                }
+                if (__syncthreads_or(same)) {
+                    nrun = sort_dedupe_keep(src, W, key, ref, zk, np, M, tmp, keep);
+                } else {
+                    if (t < np && rank < M) {
+                        key[rank] = kt;
+                        ref[rank] = rt;
+                        zk[rank] = zt;
+                    }
+                    __syncthreads();
+                    nrun = np < M ? np : M;
+                }
+            } else {
+                nrun = sort_dedupe_keep(src, W, key, ref, zk, np, M, tmp, keep);
+            }
             const double cut = nrun >= M ? key[M - 1] : INFINITY;
             int bad = 0;
 #pragma unroll
