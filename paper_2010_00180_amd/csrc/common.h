@@ -166,7 +166,8 @@ __host__ __device__ inline long long tiles_of(int N) {
 // state must be prepared for the full scan.  sidx (site | sign << 15) and sa
 // are this wave's LDS arrays of SB_CAP entries.  The loads are batched for
 // latency: a is held in registers (N <= 640), and the pairs are taken in 8 x 8
-// blocks (lane = 8 p + q), all ten blocks at once when r <= 32.
+// blocks (lane = 8 p + q), all ten blocks at once when r <= 32, else eight at
+// a time.
 constexpr int SB_AREG = 10;
 __device__ inline int site_bound_pairs(const Layout& lay, int b, int s, int code, double Em, double c,
                                        const uint64_t* __restrict__ x, const double* __restrict__ F,
@@ -353,34 +354,71 @@ __device__ inline int site_bound_pairs(const Layout& lay, int b, int s, int code
             }
         }
     } else {
-        for (int P0 = 0; P0 + 1 < r; P0 += 8) {
-            const int p = P0 + pp;
-            const uint32_t ei = p < r ? sidx[p] : 0u;
-            const int i = (int)(ei & 0x7FFFu);
-            const double ai = p < r ? sa[p] : 0.0;
-            const double si = (ei >> 15) ? -1.0 : 1.0;
-            const double rr = T - ai;
-            const double Ea = Em + ai;
-            for (int Q0 = P0; Q0 < r; Q0 += 32) {
-                double xv[4];
-                bool keep[4];
-                int jj[4];
+        // the 8 x 8 blocks (P, Q), P <= Q, in row order, eight per batch; one
+        // atomic reserves the places of a batch's survivors
+        const int nb = (r + 7) >> 3;
+        int P = 0, Q = 0;
+        while (P < nb) {
+            int bp[8], bq[8];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int q = Q0 + 8 * u + qq;
-                    keep[u] = false;
-                    xv[u] = 0.0;
-                    jj[u] = 0;
-                    if (p < q && q < r) {
-                        const uint32_t e = sidx[q];
-                        const int j = (int)(e & 0x7FFFu);
-                        jj[u] = j;
-                        xv[u] = fma(si, ((e >> 15) ? -1.0 : 1.0) * coupling(i, j), sa[q]);
-                        keep[u] = xv[u] <= rr;
+            for (int u = 0; u < 8; ++u) {
+                bp[u] = P;
+                bq[u] = Q;
+                if (P < nb && ++Q == nb) {
+                    ++P;
+                    Q = P;
+                }
+            }
+            double xv[8], ev[8];
+            bool kp[8];
+            uint32_t pr[8];
+            int cnt = 0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int p = 8 * bp[u] + pp, q = 8 * bq[u] + qq;
+                kp[u] = false;
+                xv[u] = 0.0;
+                ev[u] = 0.0;
+                pr[u] = 0;
+                if (bp[u] < nb && p < q && q < r) {
+                    const uint32_t ei = sidx[p], ej = sidx[q];
+                    const int i = (int)(ei & 0x7FFFu), j = (int)(ej & 0x7FFFu);
+                    const double ai = sa[p];
+                    xv[u] = fma((ei >> 15) ? -1.0 : 1.0, ((ej >> 15) ? -1.0 : 1.0) * coupling(i, j), sa[q]);
+                    kp[u] = xv[u] <= T - ai;
+                    ev[u] = (Em + ai) + xv[u];
+                    pr[u] = (uint32_t)i | ((uint32_t)j << 16);
+                    cnt += kp[u] ? 1 : 0;
+                }
+            }
+            bool any = false;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) any = any || __builtin_amdgcn_ballot_w64(kp[u]) != 0;
+            if (any) {
+                int excl = cnt;
+                for (int off = 1; off < 64; off <<= 1) {
+                    const int v = __shfl_up(excl, off, 64);
+                    if ((int)lane >= off) excl += v;
+                }
+                const int tot = __shfl(excl, 63, 64);
+                excl -= cnt;
+                int pos0 = 0;
+                if (lane == 0) pos0 = atomicAdd(&lay.surv_count[s], tot);
+                int pos = __shfl(pos0, 0, 64) + excl;
+                Surv* out = lay.surv + (size_t)s * lay.cap_surv;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    if (kp[u]) {
+                        if (pos < lay.cap_surv) {
+                            Surv rec;
+                            rec.E = ev[u];
+                            rec.code = (uint32_t)code;
+                            rec.pair = pr[u];
+                            out[pos] = rec;
+                        }
+                        ++pos;
                     }
                 }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) record(keep[u], Ea + xv[u], (uint32_t)i | ((uint32_t)jj[u] << 16));
             }
         }
     }
