@@ -836,13 +836,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 struct Cand {
     const uint64_t* base;
     int i, j;
-    __device__ uint64_t word(int w) const
+    __device__ uint64_t flips(int w) const
     {
-        uint64_t v = base[w];
+        uint64_t v = 0;
         if (i != (int)SINGLE && (i >> 6) == w) v ^= 1ull << (i & 63);
         if (j != (int)SINGLE && (j >> 6) == w) v ^= 1ull << (j & 63);
         return v;
     }
+    __device__ uint64_t word(int w) const { return base[w] ^ flips(w); }
 };
 
 // Candidates of one search: kept states (ref < REF_SURV, index into the kept
@@ -933,7 +934,15 @@ __device__ bool same_words(const Src& src, int W, uint32_t ia, uint32_t ib)
     const Cand A = src.decode(ia), B = src.decode(ib);
     if (A.base == B.base && A.i == B.i && A.j == B.j) return true;
     uint64_t diff = 0;
-    for (int w = 0; w < W; ++w) diff |= A.word(w) ^ B.word(w);
+    int w = 0;
+    for (; w + 4 <= W; w += 4) {
+        // four words of each state in flight at once
+        const uint64_t a0 = A.base[w], a1 = A.base[w + 1], a2 = A.base[w + 2], a3 = A.base[w + 3];
+        const uint64_t b0 = B.base[w], b1 = B.base[w + 1], b2 = B.base[w + 2], b3 = B.base[w + 3];
+        diff |= (a0 ^ b0 ^ A.flips(w) ^ B.flips(w)) | (a1 ^ b1 ^ A.flips(w + 1) ^ B.flips(w + 1)) |
+                (a2 ^ b2 ^ A.flips(w + 2) ^ B.flips(w + 2)) | (a3 ^ b3 ^ A.flips(w + 3) ^ B.flips(w + 3));
+    }
+    for (; w < W; ++w) diff |= A.word(w) ^ B.word(w);
     return diff == 0;
 }
 
@@ -1293,17 +1302,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                 nrun = sort_dedupe_keep(src, W, key, ref, zk, np, M, tmp, keep);
             }
             const double cut = nrun >= M ? key[M - 1] : INFINITY;
+            // the copies to confirm, as (copy, representative) in the slot
+            // arrays (unused until the new set is written); more than fit
+            // sends the merge to the exact sort of everything
+            uint32_t* const vlist = reinterpret_cast<uint32_t*>(freeslot);
+            constexpr int VCAP = 2048;
+            if (threadIdx.x == 0) tmp[3] = 0;
+            __syncthreads();
             int bad = 0;
 #pragma unroll
             for (int m = 0; m < HASH_PER; ++m) {
                 const int c = (int)threadIdx.x + 256 * m;
                 if (crep[m] >= 0 && crep[m] != c && ce[m] <= cut) {
-                    // equal words imply equal hashes; equal energies are checked
-                    // as the sort's dedupe requires them
-                    const int r = crep[m];
-                    const double er = candE(r);
-                    if (er != ce[m] || !same_words(src, W, ref_of(c), ref_of(r))) bad = 1;
+                    const int v = atomicAdd(&tmp[3], 1);
+                    if (v < VCAP) vlist[v] = (uint32_t)c | ((uint32_t)crep[m] << 16);
+                    else bad = 1;
                 }
+            }
+            __syncthreads();
+            const int nv = tmp[3] < VCAP ? tmp[3] : VCAP;
+            for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+                // equal words imply equal hashes; equal energies are checked
+                // as the sort's dedupe requires them
+                const int c = (int)(vlist[v] & 0xFFFFu), r = (int)(vlist[v] >> 16);
+                if (candE(c) != candE(r) || !same_words(src, W, ref_of(c), ref_of(r))) bad = 1;
             }
             if (__syncthreads_or(bad)) nrun = -1;
         }
