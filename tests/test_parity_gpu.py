@@ -424,3 +424,27 @@ def test_site_bound_rejects_trace_capture():
         s.set_trace(feat.data_ptr(), lab.data_ptr(), 16)
     assert "site bound" in binding.last_error()
     s.destroy()
+
+
+@pytest.mark.parametrize("form", [binding.FORM_PLAIN, binding.FORM_SPLIT_BF16])
+def test_site_bound_large_n_matches_full_scan(form):
+    """N above 640 takes the site bound's path without the register copy of a;
+    every search must end where the full scan ends, step by step."""
+    w = wl.custom([700, 1000], L=2, M=40, config=27)
+    note(f"[site bound large N] form {form}")
+    a = binding.IsingSearch.from_workload(w, form=form)
+    s = binding.IsingSearch.from_workload(w, form=form, flags=binding.FLAG_SITE_BOUND)
+    for t in range(2000):
+        na = a.step()
+        ns = s.step()
+        assert na == ns, f"step {t + 1}: active {na} vs {ns}"
+        for sid in range(a.B * a.L):
+            assert_same_set(s.get_search(sid), a.get_search(sid), f"large N search {sid} step {t + 1}")
+        if na == 0:
+            break
+    assert na == 0
+    st = s.stats()
+    note(f"  bounded {st['bounded_states']} of {st['frontier_states']}")
+    assert st["bounded_states"] > 0
+    a.destroy()
+    s.destroy()
