@@ -60,8 +60,12 @@ typedef enum {
 enum {
     ISING_FLAG_RECORD_PROPOSALS = 1,  /* learned form: keep each step's proposals for
                                          ising_search_get_proposals (B*L*M*K*4 bytes) */
-    ISING_FLAG_SITE_BOUND = 2         /* plain and split forms: skip pair flips that a bound proves
+    ISING_FLAG_SITE_BOUND = 2,        /* plain and split forms: skip pair flips that a bound proves
                                          cannot enter (not in the paper; see below) */
+    ISING_FLAG_FP16_SCAN = 4          /* split form: the pair scan in packed FP16 (two pairs per
+                                         instruction) with a slack for FP16 rounding; every admitted
+                                         pair is still re-scored in FP64, so the kept sets are the
+                                         same (see the split-form section below) */
 };
 
 /*

@@ -30,6 +30,7 @@ FORM_SPLIT_BF16 = 1
 FORM_LEARNED = 2
 FLAG_RECORD_PROPOSALS = 1
 FLAG_SITE_BOUND = 2
+FLAG_FP16_SCAN = 4
 SCORER_NETWORK = 0
 SCORER_FIELDS = 1
 SCORER_UNIFORM = 2

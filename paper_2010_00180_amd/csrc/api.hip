@@ -192,8 +192,10 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     if (cfg->M < 1 || cfg->M > 1024) return fail(ISING_ERR_INVALID_ARG, "M=%d outside [1, 1024]", cfg->M);
     if (cfg->form != ISING_FORM_PLAIN && cfg->form != ISING_FORM_SPLIT_BF16 && cfg->form != ISING_FORM_LEARNED)
         return fail(ISING_ERR_INVALID_ARG, "form %d is not available in this build", cfg->form);
-    if (cfg->flags & ~(ISING_FLAG_RECORD_PROPOSALS | ISING_FLAG_SITE_BOUND))
+    if (cfg->flags & ~(ISING_FLAG_RECORD_PROPOSALS | ISING_FLAG_SITE_BOUND | ISING_FLAG_FP16_SCAN))
         return fail(ISING_ERR_INVALID_ARG, "unknown flag bits 0x%x", cfg->flags);
+    if ((cfg->flags & ISING_FLAG_FP16_SCAN) && cfg->form != ISING_FORM_SPLIT_BF16)
+        return fail(ISING_ERR_INVALID_ARG, "the FP16 scan belongs to the split form");
     if ((cfg->flags & ISING_FLAG_RECORD_PROPOSALS) && cfg->form != ISING_FORM_LEARNED)
         return fail(ISING_ERR_INVALID_ARG, "proposals are recorded by the learned form only");
     if ((cfg->flags & ISING_FLAG_SITE_BOUND) && cfg->form == ISING_FORM_LEARNED)
@@ -356,6 +358,9 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     double *dyb = nullptr, *debf = nullptr, *dab = nullptr;
     const bool need_j32 = cfg->form == ISING_FORM_SPLIT_BF16 || j32_exact;
     if (need_j32) ALLOC(dJ32, (size_t)jtot);
+    const bool h16 = (cfg->flags & ISING_FLAG_FP16_SCAN) != 0;
+    uint16_t* dJ16 = nullptr;
+    if (h16) ALLOC(dJ16, (size_t)jtot);
     if (cfg->form == ISING_FORM_SPLIT_BF16) {
         ALLOC(dJhi, (size_t)jtot);
         ALLOC(dJlo, (size_t)jtot);
@@ -418,6 +423,8 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     lay.abound = dab;
     lay.Jn16 = dJn;
     lay.sb = sb ? 1 : 0;
+    lay.h16 = h16 ? 1 : 0;
+    lay.J16 = dJ16;
     lay.rmax4 = drm;
     lay.mlp = hd->d_mlp;
     lay.scorer = 0;
@@ -530,6 +537,26 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
                     abh[b] = std::max(abh[b], 2.0 * (std::fabs(h[b][i]) + R));
                 }
                 ebfh[b] = emax;
+            }
+            if (h16) {
+                // fl16(4J), nearest even; every |a| and |4J| must stay far inside the FP16 range
+                std::vector<uint16_t> j16((size_t)jtot, 0);
+                for (int b = 0; b < n_inst; ++b) {
+                    if (abh[b] + ybh[b] > 16384.0) {
+                        r2 = fail(ISING_ERR_INVALID_ARG, "instance %d: |a| can reach %g, too large for the FP16 scan",
+                                  b, abh[b]);
+                        break;
+                    }
+                    const int n = N[b], np = hd->Npad[b];
+                    for (int i = 0; i < n; ++i)
+                        for (int j = 0; j < n; ++j) {
+                            const _Float16 v = (_Float16)(4.0 * J[b][(size_t)i * n + j]);
+                            uint16_t u;
+                            std::memcpy(&u, &v, 2);
+                            j16[joff[b] + (size_t)i * np + j] = u;
+                        }
+                }
+                cp(dJ16, j16.data(), sizeof(uint16_t) * j16.size());
             }
             cp(dJhi, hih.data(), sizeof(uint16_t) * hih.size());
             cp(dJlo, loh.data(), sizeof(uint16_t) * loh.size());

@@ -113,6 +113,8 @@ struct Layout {
     float* Ft;               // [S][Npmax] F~ of the initial states (bf16 hi+lo GEMM, FP32 sums)
     float* A32;              // [B][fmax][Npmax] fl32(a_i)
     float* RR32;             // [B][fmax][Npmax] T - a_i + slack, rounded up to FP32
+    int h16;                 // 1 = the split scan runs in packed FP16 (A32 rows then hold fl16(a))
+    const uint16_t* J16;     // per instance, fl16(4J) (same layout as J4), or null
     // learned-proposal form
     uint8_t* xfull;          // [S][2M] 1 = every pair flip of the state was evaluated exactly
     int* mode;               // [S] 0 = the next step ranks pairs, 1 = it enumerates all pairs

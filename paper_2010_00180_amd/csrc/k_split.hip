@@ -175,14 +175,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         }
         // slack of the FP32 threshold, from the instance's bound on |a|
         const double u = 5.9604644775390625e-08;   // 2^-24
-        const double delta = 4.0 * u * (lay.ybound[b] + lay.abound[b]) + (from_ft ? 2.0 * lay.ebf[b] : 0.0);
+        double delta = 4.0 * u * (lay.ybound[b] + lay.abound[b]) + (from_ft ? 2.0 * lay.ebf[b] : 0.0);
+        if (lay.h16) {
+            // packed FP16 scan: the row holds fl16(a_j), and the slack covers FP16
+            // rounding of a_j, of 4J_ij and of the fma, each at most 2^-11 of its
+            // magnitude (2^-25 absolute below the normal range), taken with this
+            // state's own max |a_j|
+            _Float16* A16 = reinterpret_cast<_Float16*>(A32);
+            double amax = 0.0;
+            for (int i0 = 0; i0 < Np; i0 += 64) {
+                const int i = i0 + lane;
+                double av = 0.0;
+                if (i < N) av = -2.0 * spin_d(x, i) * (from_ft ? (double)Ft[i] : F[i]);
+                A16[i] = (_Float16)av;
+                amax = fmax(amax, fabs(av));
+            }
+            for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+            const double u16 = 4.8828125e-04;   // 2^-11
+            delta = 2.01 * u16 * (lay.ybound[b] + amax) + 2.384185791015625e-07 + (from_ft ? 2.0 * lay.ebf[b] : 0.0);
+        }
         int nhit = 0;
         for (int i0 = 0; i0 < Np; i0 += 64) {
             const int i = i0 + lane;
             double a = 0.0;
             if (i < N) a = -2.0 * spin_d(x, i) * F[i];
             if (lay.tr_feat) A[i] = a;   // FP64 a is read back only by trace capture
-            A32[i] = i < N ? (float)(from_ft ? -2.0 * spin_d(x, i) * (double)Ft[i] : a) : 0.f;
+            if (!lay.h16) A32[i] = i < N ? (float)(from_ft ? -2.0 * spin_d(x, i) * (double)Ft[i] : a) : 0.f;
             RR[i] = i < N ? __double2float_ru(T - a + delta) : -INFINITY;
             nhit += __builtin_popcountll(__builtin_amdgcn_ballot_w64(i < N && Em + a <= c));
         }
@@ -411,17 +429,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                             else mn0 = fminf(mn0, x);
                         }
                         if (__builtin_amdgcn_ballot_w64(fminf(mn0, mn1) <= rrt)) {
-                            // admitted pairs wait for the exact re-score
-                            if (npend > PEND - 512) rescore();
+                            // admitted pairs wait for the exact re-score: a mask of the lane's
+                            // 8 columns, then rounds that queue each lane's lowest admitted
+                            // column (admitted pairs are sparse: usually one round)
+                            uint32_t am = 0;
 #pragma unroll
-                            for (int u = 0; u < 8; ++u) {
-                                const float xt = fmaf(si, __uint_as_float(Jb[g + u]), a8[u]);
-                                const bool adm = xt <= rrt;
-                                const uint64_t m = __builtin_amdgcn_ballot_w64(adm);
-                                if (m) {
-                                    if (adm) pend[npend + (int)mbcnt64s(m)] = ((uint32_t)k << 12) | (lane << 6) | (uint32_t)(g + u);
-                                    npend += __builtin_popcountll(m);
+                            for (int u = 0; u < 8; ++u)
+                                am |= (fmaf(si, __uint_as_float(Jb[g + u]), a8[u]) <= rrt ? 1u : 0u) << u;
+                            for (uint64_t m = __builtin_amdgcn_ballot_w64(am != 0); m;
+                                 m = __builtin_amdgcn_ballot_w64(am != 0)) {
+                                if (npend > PEND - 64) rescore();
+                                if (am) {
+                                    pend[npend + (int)mbcnt64s(m)] = ((uint32_t)k << 12) | (lane << 6) |
+                                                                     (uint32_t)(g + __builtin_ctz(am));
+                                    am &= am - 1u;
                                 }
+                                npend += __builtin_popcountll(m);
                             }
                         }
                     }
@@ -442,6 +465,308 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         rejected += ((uint64_t)hi << 32) | lo;
     }
     if (lane == 0 && rejected) atomicAdd(&lay.ctr[CTR_FALLBACK], rejected);
+}
+
+// ------------------------------------------------------------------ k_scan16
+// The split scan in packed FP16 (on request): one wave per (instance, chunk of
+// states, tile of 64 rows x 128 columns with some column above the rows).
+// Lane = row i; 64 registers hold y_j = s_j fl16(4J_ij) for 128 columns as
+// pairs; per two pairs one v_pk_fma_f16 and one v_pk_min_f16, one compare per
+// group of 16 columns against RR_i rounded up to FP16.  RR_i carries the FP16
+// slack; admitted pairs are queued and re-scored in FP64 as in k_scan32.
+constexpr int T16 = 128;
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+
+__device__ inline long long tiles16(int N)
+{
+    const int Np = pad_of(N);
+    const int nb = Np / TILE, nc = (Np + T16 - 1) / T16;
+    long long t = 0;
+    for (int bi = 0; bi < nb; ++bi) t += nc - (bi >> 1);
+    return t;
+}
+
+// x rounded up to the next FP16 value at or above it
+__device__ inline _Float16 half_up(float x)
+{
+    _Float16 h = (_Float16)x;
+    if ((float)h < x) {
+        uint16_t u = __builtin_bit_cast(uint16_t, h);
+        u = (u & 0x8000u) ? (uint16_t)(u - 1u) : (uint16_t)(u + 1u);
+        if (u == 0x8000u) u = 0;   // from the smallest negative subnormal up to zero
+        h = __builtin_bit_cast(_Float16, u);
+    }
+    return h;
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_scan16(Layout lay, const uint16_t* __restrict__ J16,
+                                               const double* __restrict__ J4,
+                                               const uint16_t* __restrict__ A16,
+                                               const float* __restrict__ RR32,
+                                               const double* __restrict__ Fpool,
+                                               const FrRec* __restrict__ recs,
+                                               const uint64_t* __restrict__ fbits,
+                                               const long long* __restrict__ iprefix)
+{
+    __shared__ Surv stage[STAGE];
+    __shared__ uint32_t abuf[2][T16 / 2];   // fl16(a_j) pairs of the current and the next state
+    __shared__ double sT[64], sE[64];
+    __shared__ int sS[64], sCode[64];
+    __shared__ uint64_t sWi[64], sWj0[64], sWj1[64];
+    __shared__ size_t sFe[64];
+    constexpr int PEND = 512;
+    __shared__ uint32_t pend[PEND];   // admitted pairs awaiting the FP64 re-score: k << 13 | row << 7 | col
+    const uint32_t lane = lane_id32();
+    const long long total = iprefix[lay.B];
+    const int retry_mode = lay.flags[FLAG_RETRY_MODE];
+    const int Wm = lay.Wmax;
+    const int Npm = lay.Npmax;
+    const int nx = gridDim.x >= 8 ? 8 : 1;
+    const int xcd = blockIdx.x % nx;
+    const long long seg0 = total * xcd / nx, seg1 = total * (xcd + 1) / nx;
+    const long long stride = gridDim.x / nx;
+    unsigned long long rejected = 0;
+    for (long long item = seg0 + blockIdx.x / nx; item < seg1; item += stride) {
+        const int b = __builtin_amdgcn_readfirstlane(find_inst(iprefix, lay.B, item));
+        const long long r = item - iprefix[b];
+        const int N = lay.N[b], Np = lay.Npad[b];
+        const int nb = Np / TILE, nc = (Np + T16 - 1) / T16;
+        const long long T = tiles16(N);
+        const int c = (int)(r / T);
+        int t = (int)(r % T);
+        int bi = 0;
+        while (t >= nc - (bi >> 1)) { t -= nc - (bi >> 1); ++bi; }
+        bi = __builtin_amdgcn_readfirstlane(bi);
+        const int bj = __builtin_amdgcn_readfirstlane((bi >> 1) + t);
+        const int P = lay.sb ? lay.full_count[b] : lay.fr_count[b];
+        const int sc = lay.scb[b];
+        const int f0 = c * sc;
+        const int f1 = min(f0 + sc, P);
+        const size_t fb = (size_t)b * lay.fmax;
+        const int row = bi * TILE + (int)lane;
+        const int col0 = bj * T16;
+        const int w0 = 2 * bj, w1 = 2 * bj + 1 < Wm ? 2 * bj + 1 : -1;   // words of the tile's columns
+        // row i of the (symmetric) couplings, four columns per 8-byte load;
+        // columns at or past Np are not read
+        const uint64_t* Jrow = reinterpret_cast<const uint64_t*>(J16 + lay.joff[b] + (size_t)row * Np);
+        uint32_t Jb[T16 / 2];   // columns col0 + 2v (low half) and col0 + 2v + 1 (high half)
+#pragma unroll
+        for (int q = 0; q < T16 / 4; ++q) {
+            const int c4 = col0 + 4 * q;
+            uint64_t v = (row < N && c4 < Np) ? Jrow[c4 >> 2] : 0ull;
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int col = c4 + h;
+                if (!(row < N && col < N && col > row))   // NaN: fmin drops it
+                    v = (v & ~(0xFFFFull << (16 * h))) | (0x7E00ull << (16 * h));
+            }
+            Jb[2 * q] = (uint32_t)v;
+            Jb[2 * q + 1] = (uint32_t)(v >> 32);
+        }
+        (void)nb;
+        uint64_t prev0 = 0, prev1 = 0;
+        int nstage = 0, sstage = -1;
+        int npend = 0;
+        // exact FP64 re-score of the admitted pairs, survivors to the stage
+        auto rescore = [&]() {
+            for (int p0 = 0; p0 < npend; p0 += 64) {
+                const int p = p0 + (int)lane;
+                bool keep = false;
+                Surv rec;
+                rec.E = 0.0;
+                rec.code = 0;
+                rec.pair = 0;
+                if (p < npend) {
+                    const uint32_t pr = pend[p];
+                    const int k = (int)(pr >> 13), rl = (int)((pr >> 7) & 63u), cl = (int)(pr & 127u);
+                    const int prow = bi * TILE + rl, pcol = col0 + cl;
+                    const int cd = sCode[k];
+                    const double* Frow = Fpool + (size_t)cd * lay.Npmax;
+                    const double sid = ((sWi[k] >> rl) & 1ull) ? -1.0 : 1.0;
+                    const uint64_t wj = cl < 64 ? sWj0[k] : sWj1[k];
+                    const double sj = ((wj >> (cl & 63)) & 1ull) ? -1.0 : 1.0;
+                    const double ai = -2.0 * sid * Frow[prow];
+                    const double x = -2.0 * sj * Frow[pcol] + sid * sj * J4[lay.joff[b] + (size_t)prow * Np + pcol];
+                    keep = ai + x <= sT[k];
+                    if (!keep) ++rejected;
+                    rec.E = (sE[k] + ai) + x;
+                    rec.code = (uint32_t)cd;
+                    rec.pair = (uint32_t)prow | ((uint32_t)pcol << 16);
+                }
+                const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
+                if (m) {
+                    if (nstage > STAGE - 64) flush32(lay, stage, nstage, sstage);
+                    if (keep) stage[nstage + (int)mbcnt64s(m)] = rec;
+                    nstage += __builtin_popcountll(m);
+                }
+            }
+            npend = 0;
+        };
+        for (int g0 = f0; g0 < f1; g0 += 64) {
+            const int ns = min(64, f1 - g0);
+            // the records of states g0 .. g0+ns-1 (with the site bound, the
+            // entries left to the scan)
+            if ((int)lane < ns) {
+                const size_t fe = fb + (lay.sb ? lay.full_list[fb + g0 + lane] : g0 + (int)lane);
+                const FrRec rc = recs[fe];
+                sT[lane] = rc.T;
+                sE[lane] = rc.E;
+                sS[lane] = rc.s;
+                sCode[lane] = rc.code;
+                sFe[lane] = fe;
+                const uint64_t* fw = fbits + fe * Wm;
+                sWi[lane] = fw[bi];
+                sWj0[lane] = fw[w0];
+                sWj1[lane] = w1 >= 0 ? fw[w1] : 0ull;
+            }
+            __syncthreads();
+            // a row of state k: 2 Npmax halves per entry; the tile reads halves
+            // col0 .. col0+127 < Np + 64 <= 2 Npmax
+            const uint32_t* A0 = reinterpret_cast<const uint32_t*>(A16);
+            float nrr = RR32[sFe[0] * Npm + row];
+            uint32_t naj = A0[sFe[0] * Npm + (col0 >> 1) + lane];
+            int cur = 0;
+            abuf[0][lane] = naj;
+            __syncthreads();
+            for (int k = 0; k < ns; ++k) {
+                const _Float16 rr = half_up(nrr);
+                const h2v rr2 = {rr, rr};
+                if (k + 1 < ns) {
+                    const size_t fn = sFe[k + 1] * Npm;
+                    nrr = RR32[fn + row];
+                    naj = A0[fn + (col0 >> 1) + lane];
+                }
+                const int s = __builtin_amdgcn_readfirstlane(sS[k]);
+                const bool skip = retry_mode && !lay.retry[s];
+                if (!skip) {
+                    if (s != sstage) {
+                        rescore();
+                        flush32(lay, stage, nstage, sstage);
+                        sstage = s;
+                    }
+                    const _Float16 sh = ((sWi[k] >> lane) & 1ull) ? (_Float16)-1.0f : (_Float16)1.0f;
+                    const h2v si2 = {sh, sh};
+                    uint64_t wj[2];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const uint64_t wv = h == 0 ? sWj0[k] : sWj1[k];
+                        const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)wv);
+                        const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(wv >> 32));
+                        wj[h] = ((uint64_t)hi << 32) | lo;
+                    }
+                    const uint64_t dw[2] = {wj[0] ^ prev0, wj[1] ^ prev1};
+                    prev0 = wj[0];
+                    prev1 = wj[1];
+                    const uint32_t* aj = abuf[cur];
+                    uint32_t a8n[8];   // the next group's a_j pairs, read one group ahead
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) a8n[u] = aj[u];
+#pragma unroll
+                    for (int g = 0; g < T16 / 2; g += 8) {
+                        // group: registers g .. g+7, columns col0 + 2g .. col0 + 2g + 15
+                        uint32_t a8[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) a8[u] = a8n[u];
+                        if (g + 8 < T16 / 2) {
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) a8n[u] = aj[g + 8 + u];
+                        }
+                        const uint64_t dwg = dw[g >> 5] >> ((2 * g) & 63);
+                        if (dwg & 0xFFFFull) {
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                // the two sign bits of the pair, formed in one scalar register
+                                // so that the flip is a single v_xor_b32
+                                const uint32_t fl = (uint32_t)__builtin_amdgcn_readfirstlane(
+                                    (int)(((uint32_t)((dwg >> (2 * u)) & 1ull) << 15) |
+                                          ((uint32_t)((dwg >> (2 * u + 1)) & 1ull) << 31)));
+                                Jb[g + u] ^= fl;
+                            }
+                        }
+                        auto xf = [&](int u) {
+                            return __builtin_elementwise_fma(si2, __builtin_bit_cast(h2v, Jb[g + u]),
+                                                             __builtin_bit_cast(h2v, a8[u]));
+                        };
+                        h2v mm0 = __builtin_elementwise_min(xf(0), xf(1));
+                        h2v mm1 = __builtin_elementwise_min(xf(2), xf(3));
+                        mm0 = __builtin_elementwise_min(mm0, xf(4));
+                        mm1 = __builtin_elementwise_min(mm1, xf(5));
+                        mm0 = __builtin_elementwise_min(mm0, xf(6));
+                        mm1 = __builtin_elementwise_min(mm1, xf(7));
+                        const h2v mm = __builtin_elementwise_min(mm0, mm1);
+                        const bool any = mm[0] <= rr || mm[1] <= rr;
+                        if (__builtin_amdgcn_ballot_w64(any)) {
+                            // admitted pairs wait for the exact re-score; a mask of the
+                            // lane's 16 columns, walked column by column so that the
+                            // queue is drained whenever a column could overfill it
+                            uint32_t am = 0;
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                const h2v xu = __builtin_elementwise_fma(si2, __builtin_bit_cast(h2v, Jb[g + u]),
+                                                                         __builtin_bit_cast(h2v, a8[u]));
+#pragma unroll
+                                for (int h = 0; h < 2; ++h) am |= (xu[h] <= rr ? 1u : 0u) << (2 * u + h);
+                            }
+                            // each round queues the lowest admitted column of every lane that
+                            // has one (admitted pairs are sparse: usually one round)
+                            for (uint64_t m = __builtin_amdgcn_ballot_w64(am != 0); m;
+                                 m = __builtin_amdgcn_ballot_w64(am != 0)) {
+                                if (npend > PEND - 64) rescore();
+                                if (am) {
+                                    pend[npend + (int)mbcnt64s(m)] = ((uint32_t)k << 13) | (lane << 7) |
+                                                                     (uint32_t)(2 * g + __builtin_ctz(am));
+                                    am &= am - 1u;
+                                }
+                                npend += __builtin_popcountll(m);
+                            }
+                        }
+                    }
+                }
+                if (k + 1 < ns) abuf[cur ^ 1][lane] = naj;
+                cur ^= 1;
+                __syncthreads();
+            }
+            rescore();   // before the next 64 states replace the records
+        }
+        flush32(lay, stage, nstage, sstage);
+        __syncthreads();
+    }
+    // count re-scored pairs that the exact test rejected
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)rejected, off, 64);
+        const uint32_t hi = __shfl_xor((uint32_t)(rejected >> 32), off, 64);
+        rejected += ((uint64_t)hi << 32) | lo;
+    }
+    if (lane == 0 && rejected) atomicAdd(&lay.ctr[CTR_FALLBACK], rejected);
+}
+
+// Work prefix over instances for the 64 x 128 tiles of the FP16 scan.
+__global__ __launch_bounds__(1024) void k_plan16(Layout lay, long long* __restrict__ iprefix)
+{
+    __shared__ long long part[1024];
+    const int t = threadIdx.x;
+    const int per = (lay.B + 1023) / 1024;
+    const int b0 = t * per;
+    long long items = 0;
+    for (int b = b0; b < b0 + per && b < lay.B; ++b) {
+        const long long P = lay.sb ? lay.full_count[b] : lay.fr_count[b];
+        items += (P + lay.scb[b] - 1) / lay.scb[b] * tiles16(lay.N[b]);
+    }
+    part[t] = items;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const long long a = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += a;
+        __syncthreads();
+    }
+    long long run = part[t] - items;
+    for (int b = b0; b < b0 + per && b < lay.B; ++b) {
+        iprefix[b] = run;
+        const long long P = lay.sb ? lay.full_count[b] : lay.fr_count[b];
+        run += (P + lay.scb[b] - 1) / lay.scb[b] * tiles16(lay.N[b]);
+    }
+    if (t == 1023) iprefix[lay.B] = part[1023];
 }
 
 // ------------------------------------------------------------------ k_plan32
@@ -485,6 +810,13 @@ hipError_t launch_prep32(const Layout& lay, hipStream_t st)
 hipError_t launch_scan32(const Layout& lay, int scan_grid, hipStream_t st)
 {
     long long* iprefix = lay.item_prefix + 2 * (lay.B + 1);
+    if (lay.h16) {
+        hipLaunchKernelGGL(k_plan16, dim3(1), dim3(1024), 0, st, lay, iprefix);
+        hipLaunchKernelGGL(k_scan16, dim3(scan_grid), dim3(64), 0, st, lay, lay.J16, lay.J4,
+                           (const uint16_t*)lay.A32, (const float*)lay.RR32, (const double*)lay.F,
+                           (const FrRec*)lay.rec, (const uint64_t*)lay.fbits, (const long long*)iprefix);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_plan32, dim3(1), dim3(1024), 0, st, lay, iprefix);
     hipLaunchKernelGGL(k_scan32, dim3(scan_grid), dim3(64), 0, st, lay, lay.J32, lay.J4, (const float*)lay.A32,
                        (const float*)lay.RR32, (const double*)lay.F, (const FrRec*)lay.rec,

@@ -112,7 +112,7 @@ def test_init_without_device_reports_no_device():
     assert rc == binding.ISING_ERR_NO_DEVICE, binding.last_error()
 
 
-@pytest.mark.parametrize("case", ["record_plain", "bound_learned", "topk_neg", "topk_big", "k_too_big"])
+@pytest.mark.parametrize("case", ["record_plain", "bound_learned", "fp16_plain", "topk_neg", "topk_big", "k_too_big"])
 def test_init_rejects_invalid_learned_configs(case):
     inst = _good(N=30)
     N, J, h, x = inst.N, inst.J, inst.h, inst.init_bits
@@ -122,6 +122,9 @@ def test_init_rejects_invalid_learned_configs(case):
         cfg.flags = binding.FLAG_RECORD_PROPOSALS
     elif case == "bound_learned":
         cfg.flags = binding.FLAG_SITE_BOUND
+    elif case == "fp16_plain":
+        cfg.form = binding.FORM_PLAIN
+        cfg.flags = binding.FLAG_FP16_SCAN
     elif case == "topk_neg":
         cfg.topk_factor = -1
     elif case == "topk_big":

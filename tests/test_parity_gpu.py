@@ -448,3 +448,71 @@ def test_site_bound_large_n_matches_full_scan(form):
     assert st["bounded_states"] > 0
     a.destroy()
     s.destroy()
+
+
+# ---------------------------------------------------------------- FP16 scan
+# The split form's pair scan in packed FP16 with its own slack; the FP64
+# re-score keeps the kept sets those of the oracle.
+@pytest.mark.parametrize("N,M,L,dist", [(24, 8, 4, "sk"), (65, 40, 2, "sk"), (130, 60, 2, "sk"),
+                                        (200, 120, 1, "sk"), (70, 50, 2, "pmj"), (90, 30, 2, "sk_h0"),
+                                        (150, 25, 2, "uniform")])
+def test_fp16_scan_stepwise(N, M, L, dist):
+    w = wl.custom([N], L=L, M=M, config=28, dist=dist, seed_offset=N + 5 * M)
+    st = stepwise_parity(w, f"fp16 scan N={N} {dist}", form=binding.FORM_SPLIT_BF16, flags=binding.FLAG_FP16_SCAN)
+    note(f"  admitted and rejected by the FP64 re-score: {st['fallbacks']}")
+
+
+def test_fp16_scan_with_site_bound_and_tiles():
+    w = wl.custom([5, 64, 65, 100, 129, 257], L=2, M=30, config=29)
+    stepwise_parity(w, "fp16 scan + site bound, sc=7", form=binding.FORM_SPLIT_BF16,
+                    flags=binding.FLAG_FP16_SCAN | binding.FLAG_SITE_BOUND, states_per_item=7)
+
+
+def test_fp16_scan_matches_fp32_scan_n600():
+    """4 instances of N=600, M=120, L=64: every search and merged set equal to
+    the FP32 scan's, and fewer than one admitted pair in 10^4 rejected."""
+    w = wl.c3_n600(n_instances=4)
+    note("[fp16 scan n600]")
+    a = binding.IsingSearch.from_workload(w, form=binding.FORM_SPLIT_BF16)
+    h = binding.IsingSearch.from_workload(w, form=binding.FORM_SPLIT_BF16, flags=binding.FLAG_FP16_SCAN)
+    ia, _ = a.run()
+    ih, stable = h.run()
+    assert stable and ia == ih
+    for sid in range(w.n_searches):
+        assert_same_set(h.get_search(sid), a.get_search(sid), f"fp16 n600 search {sid}")
+    for b in range(len(w.instances)):
+        ab, aE = a.get_states(b)
+        hb, hE = h.get_states(b)
+        assert np.array_equal(ab, hb) and np.array_equal(aE, hE)
+    sa, sh = a.stats(), h.stats()
+    note(f"  rejected by the re-score: fp32 {sa['fallbacks']}, fp16 {sh['fallbacks']}; pairs {sh['pair_evals']:.3e}")
+    assert sh["pair_evals"] == sa["pair_evals"]
+    a.destroy()
+    h.destroy()
+
+
+def test_fp16_scan_large_n_and_persistent():
+    w = wl.custom([700, 1000, 300], L=2, M=40, config=30)
+    note("[fp16 scan large N, graph replay] vs plain")
+    a = binding.IsingSearch.from_workload(w)
+    h = binding.IsingSearch.from_workload(w, form=binding.FORM_SPLIT_BF16, flags=binding.FLAG_FP16_SCAN, persistent=1)
+    for t in range(2000):
+        na = a.step()
+        nh = h.step()
+        assert na == nh, f"step {t + 1}: active {na} vs {nh}"
+        for sid in range(a.B * a.L):
+            assert_same_set(h.get_search(sid), a.get_search(sid), f"fp16 large N search {sid} step {t + 1}")
+        if na == 0:
+            break
+    assert na == 0
+    a.destroy()
+    h.destroy()
+
+
+def test_fp16_scan_rejects_values_outside_its_range():
+    inst = wl.make_instance(40, 31, 2)
+    J = inst.J * 2.0 ** 12
+    with pytest.raises(binding.IsingError):
+        binding.IsingSearch([inst.N], [J], [inst.h], [inst.init_bits], 8, form=binding.FORM_SPLIT_BF16,
+                            flags=binding.FLAG_FP16_SCAN)
+    assert "FP16" in binding.last_error()
