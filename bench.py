@@ -8,9 +8,10 @@ timed region starts.
 
 Workload: 120 instances, N = 600, J_ij ~ N(0,1)/sqrt(N), h_i ~ N(0,1) (both on
 the 2^-24 grid), M = 120 kept states, 64 initial states per instance.  The
-headline is the split-bf16 form (initial local fields on bf16 matrix cores,
-FP32 pair scan with a proven slack, FP64 re-score; kept sets identical to the
-FP64 form); the plain FP64 form runs the same workload for comparison; the
+headline is the split-bf16 form with its pair scan in packed FP16 (initial
+local fields on bf16 matrix cores, FP16 pair scan with a proven slack, FP64
+re-score; kept sets identical to the FP64 form); the same form with the FP32
+scan and the plain FP64 form run the same workload for comparison; the
 learned-proposal form (network trained first on traces of other instances of
 the same shape) runs a bounded sample of it, next to the plain form on the
 same sample, and its miss rate is judged against full enumeration.  The
@@ -35,16 +36,19 @@ METRIC = "pair-flip ΔE evals/s + time-to-solution/instance at N=600,M=120 vs pl
 # FP64 78.6 TFLOP/s = 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 flops;
 # FP32 157.3 TFLOP/s, twice that (it needs packed FP32, which this build does
 # not use, so the FP32 scan can reach half of its peak).
-VALU_LANE_OPS_PER_S = {"f64": 256 * 4 * 16 * 2.4e9, "f32": 2 * 256 * 4 * 16 * 2.4e9}
+VALU_LANE_OPS_PER_S = {"f64": 256 * 4 * 16 * 2.4e9, "f32": 2 * 256 * 4 * 16 * 2.4e9,
+                       # packed FP16: two halves per lane and cycle from the same unit counts
+                       "f16": 2 * 256 * 4 * 16 * 2.4e9}
 OPS_PER_PAIR = 2          # fma(s_i, s_j 4J_ij, a_j) and the compare with T - a_i (a running minimum)
-FORM_DTYPE = {"plain": "f64", "split_bf16": "f32", "learned": "f64", "plain_bound": "f64", "split_bf16_bound": "f64"}
+FORM_DTYPE = {"plain": "f64", "split_bf16": "f32", "split_fp16": "f16", "learned": "f64", "plain_bound": "f64",
+              "split_bf16_bound": "f64"}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCE = {"k_scan": "k_step.hip", "k_scan32": "k_split.hip", "k_learn": "k_learn.hip"}
+KERNEL_SOURCE = {"k_scan": "k_step.hip", "k_scan32": "k_split.hip", "k_scan16": "k_split.hip", "k_learn": "k_learn.hip"}
 
 
 def source_digest(kernel="k_scan"):
@@ -100,11 +104,13 @@ def cpu_baseline(w, budget_s):
     }
 
 
-FORM_CODES = {"plain": 0, "split_bf16": 1, "learned": 2, "plain_bound": 0, "split_bf16_bound": 1}
+FORM_CODES = {"plain": 0, "split_bf16": 1, "split_fp16": 1, "learned": 2, "plain_bound": 0, "split_bf16_bound": 1}
 # the *_bound forms run with the site bound (only the pairs that can pass the
 # cut are evaluated; identical kept sets): a time-to-solution figure, not an
 # evaluation rate
-FORM_FLAGS = {"plain_bound": 2, "split_bf16_bound": 2}
+FORM_FLAGS = {"plain_bound": 2, "split_bf16_bound": 2, "split_fp16": 4}
+SITE_BOUND_FORMS = ("plain_bound", "split_bf16_bound")
+SCAN_KERNEL = {"plain": "k_scan", "split_bf16": "k_scan32", "split_fp16": "k_scan16"}
 HBM_PEAK_GBS = 8000.0
 # multiply-adds of the scoring network per pair, counted as 2 flops each:
 # layer 1 (4 x 64), layer 2 (64 x 64), output (64)
@@ -286,7 +292,7 @@ def measure(binding, torch, w, form, steps, warmup, batching, copy_gib):
         log(f"calibration copy: {n * 8} bytes read, {n * 8} bytes written")
     s.destroy()
     torch.cuda.synchronize()
-    if form in FORM_FLAGS:
+    if form in SITE_BOUND_FORMS:
         # the preparation kernel evaluates the bounded states: its algorithmic
         # bytes are the F row of each expanded state (8N) and one FP32 coupling
         # per evaluated pair (4)
@@ -302,7 +308,7 @@ def measure(binding, torch, w, form, steps, warmup, batching, copy_gib):
         }
     else:
         roofline = {
-            "kernel": "k_scan32" if form == "split_bf16" else "k_scan",
+            "kernel": SCAN_KERNEL[form],
             "bound": "alu",
             "achieved": ops_per_s / 1e12,
             "peak": peak / 1e12,
@@ -341,7 +347,7 @@ def main():
                          "L=32, run as the batching form (persistent graph, autotuned tiles)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--forms", default="split_bf16,plain,split_bf16_bound,plain_bound,learned",
+    ap.add_argument("--forms", default="split_fp16,split_bf16,plain,split_bf16_bound,plain_bound,learned",
                     help="comma list of forms to time; the first gives the headline value")
     ap.add_argument("--learned-instances", type=int, default=2,
                     help="instances of the workload the learned form runs on (a bounded sample)")

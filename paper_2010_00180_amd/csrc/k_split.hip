@@ -576,6 +576,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const size_t fb = (size_t)b * lay.fmax;
         const int row = bi * TILE + (int)lane;
         const int col0 = bj * T16;
+        // groups of 16 columns with a pair in the triangle (the others hold only NaN)
+        uint32_t live = 0;
+        for (int g = 0; g < T16 / 2; g += 8)
+            if (col0 + 2 * g < N && col0 + 2 * g + 15 > bi * TILE) live |= 1u << (g >> 3);
+        live = (uint32_t)__builtin_amdgcn_readfirstlane((int)live);
+        if (!live) continue;
         const int w0 = 2 * bj, w1 = 2 * bj + 1 < Wm ? 2 * bj + 1 : -1;   // words of the tile's columns
         // row i of the (symmetric) couplings, four columns per 8-byte load;
         // columns at or past Np are not read
@@ -702,6 +708,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 #pragma unroll
                             for (int u = 0; u < 8; ++u) a8n[u] = aj[g + 8 + u];
                         }
+                        if (!((live >> (g >> 3)) & 1u)) continue;
                         const uint64_t dwg = dw[g >> 5] >> ((2 * g) & 63);
                         if (dwg & 0xFFFFull) {
 #pragma unroll
