@@ -176,64 +176,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         // slack of the FP32 threshold, from the instance's bound on |a|
         const double u = 5.9604644775390625e-08;   // 2^-24
         double delta = 4.0 * u * (lay.ybound[b] + lay.abound[b]) + (from_ft ? 2.0 * lay.ebf[b] : 0.0);
-        int nhit = 0;
-        if (H16 && Np <= 64 * 10) {
+        if (H16) {
             // packed FP16 scan: the row holds fl16(a_j), and the slack covers FP16
             // rounding of a_j, of 4J_ij and of the fma, each at most 2^-11 of its
-            // magnitude (2^-25 absolute below the normal range), taken with this
-            // state's own max |a_j|; a is held in registers between the passes
-            _Float16* A16 = reinterpret_cast<_Float16*>(A32);
-            double areg[10];
-            double amax = 0.0;
-#pragma unroll
-            for (int k = 0; k < 10; ++k) {
-                const int i = 64 * k + (int)lane;
-                double a = 0.0, av = 0.0;
-                if (i < N) {
-                    a = -2.0 * spin_d(x, i) * F[i];
-                    av = from_ft ? -2.0 * spin_d(x, i) * (double)Ft[i] : a;
-                }
-                areg[k] = a;
-                if (i < Np) A16[i] = (_Float16)av;
-                amax = fmax(amax, fabs(av));
-            }
-            for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+            // magnitude (2^-25 absolute below the normal range), with the
+            // instance's bound on |a|
             const double u16 = 4.8828125e-04;   // 2^-11
-            delta = 2.01 * u16 * (lay.ybound[b] + amax) + 2.384185791015625e-07 + (from_ft ? 2.0 * lay.ebf[b] : 0.0);
-#pragma unroll
-            for (int k = 0; k < 10; ++k) {
-                const int i = 64 * k + (int)lane;
-                if (i < Np) {
-                    if (lay.tr_feat) A[i] = areg[k];   // FP64 a is read back only by trace capture
-                    RR[i] = i < N ? __double2float_ru(T - areg[k] + delta) : -INFINITY;
-                }
-                nhit += __builtin_popcountll(__builtin_amdgcn_ballot_w64(i < N && Em + areg[k] <= c));
-            }
-        } else {
-            if (H16) {
-                // as above, with the a row read twice
-                _Float16* A16 = reinterpret_cast<_Float16*>(A32);
-                double amax = 0.0;
-                for (int i0 = 0; i0 < Np; i0 += 64) {
-                    const int i = i0 + lane;
-                    double av = 0.0;
-                    if (i < N) av = -2.0 * spin_d(x, i) * (from_ft ? (double)Ft[i] : F[i]);
-                    A16[i] = (_Float16)av;
-                    amax = fmax(amax, fabs(av));
-                }
-                for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
-                const double u16 = 4.8828125e-04;   // 2^-11
-                delta = 2.01 * u16 * (lay.ybound[b] + amax) + 2.384185791015625e-07 + (from_ft ? 2.0 * lay.ebf[b] : 0.0);
-            }
-            for (int i0 = 0; i0 < Np; i0 += 64) {
-                const int i = i0 + lane;
-                double a = 0.0;
-                if (i < N) a = -2.0 * spin_d(x, i) * F[i];
-                if (lay.tr_feat) A[i] = a;   // FP64 a is read back only by trace capture
-                if (!H16) A32[i] = i < N ? (float)(from_ft ? -2.0 * spin_d(x, i) * (double)Ft[i] : a) : 0.f;
-                RR[i] = i < N ? __double2float_ru(T - a + delta) : -INFINITY;
-                nhit += __builtin_popcountll(__builtin_amdgcn_ballot_w64(i < N && Em + a <= c));
-            }
+            delta = 2.01 * u16 * (lay.ybound[b] + lay.abound[b]) + 2.384185791015625e-07 +
+                    (from_ft ? 2.0 * lay.ebf[b] : 0.0);
+        }
+        _Float16* A16 = reinterpret_cast<_Float16*>(A32);
+        int nhit = 0;
+        for (int i0 = 0; i0 < Np; i0 += 64) {
+            const int i = i0 + lane;
+            double a = 0.0;
+            if (i < N) a = -2.0 * spin_d(x, i) * F[i];
+            if (lay.tr_feat) A[i] = a;   // FP64 a is read back only by trace capture
+            const double av = i < N ? (from_ft ? -2.0 * spin_d(x, i) * (double)Ft[i] : a) : 0.0;
+            if (H16) A16[i] = (_Float16)av;
+            else A32[i] = (float)av;
+            RR[i] = i < N ? __double2float_ru(T - a + delta) : -INFINITY;
+            nhit += __builtin_popcountll(__builtin_amdgcn_ballot_w64(i < N && Em + a <= c));
         }
         int base = 0;
         if (nhit) {
