@@ -114,6 +114,19 @@ __device__ inline int find_inst(const long long* prefix, int B, long long e)
     return lo;
 }
 
+// x rounded up to the next FP16 value at or above it
+__device__ inline _Float16 half_up(float x)
+{
+    _Float16 h = (_Float16)x;
+    if ((float)h < x) {
+        uint16_t u = __builtin_bit_cast(uint16_t, h);
+        u = (u & 0x8000u) ? (uint16_t)(u - 1u) : (uint16_t)(u + 1u);
+        if (u == 0x8000u) u = 0;   // from the smallest negative subnormal up to zero
+        h = __builtin_bit_cast(_Float16, u);
+    }
+    return h;
+}
+
 template <bool SB, bool H16>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_prep32(Layout lay, const long long* __restrict__ fr_prefix)
 {
@@ -195,7 +208,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             const double av = i < N ? (from_ft ? -2.0 * spin_d(x, i) * (double)Ft[i] : a) : 0.0;
             if (H16) A16[i] = (_Float16)av;
             else A32[i] = (float)av;
-            RR[i] = i < N ? __double2float_ru(T - a + delta) : -INFINITY;
+            const float rr = i < N ? __double2float_ru(T - a + delta) : -INFINITY;
+            if (H16) reinterpret_cast<_Float16*>(RR)[i] = half_up(rr);   // rounded up once more, to FP16
+            else RR[i] = rr;
             nhit += __builtin_popcountll(__builtin_amdgcn_ballot_w64(i < N && Em + a <= c));
         }
         int base = 0;
@@ -480,23 +495,10 @@ __device__ inline long long tiles16(int N)
     return t;
 }
 
-// x rounded up to the next FP16 value at or above it
-__device__ inline _Float16 half_up(float x)
-{
-    _Float16 h = (_Float16)x;
-    if ((float)h < x) {
-        uint16_t u = __builtin_bit_cast(uint16_t, h);
-        u = (u & 0x8000u) ? (uint16_t)(u - 1u) : (uint16_t)(u + 1u);
-        if (u == 0x8000u) u = 0;   // from the smallest negative subnormal up to zero
-        h = __builtin_bit_cast(_Float16, u);
-    }
-    return h;
-}
-
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_scan16(Layout lay, const uint16_t* __restrict__ J16,
                                                const double* __restrict__ J4,
                                                const uint16_t* __restrict__ A16,
-                                               const float* __restrict__ RR32,
+                                               const _Float16* __restrict__ RR16,
                                                const double* __restrict__ Fpool,
                                                const FrRec* __restrict__ recs,
                                                const uint64_t* __restrict__ fbits,
@@ -623,17 +625,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
             // a row of state k: 2 Npmax halves per entry; the tile reads halves
             // col0 .. col0+127 < Np + 64 <= 2 Npmax
             const uint32_t* A0 = reinterpret_cast<const uint32_t*>(A16);
-            float nrr = RR32[sFe[0] * Npm + row];
+            _Float16 nrr = RR16[sFe[0] * 2 * Npm + row];   // rows of 2 Npmax halves
             uint32_t naj = A0[sFe[0] * Npm + (col0 >> 1) + lane];
             int cur = 0;
             abuf[0][lane] = naj;
             __syncthreads();
             for (int k = 0; k < ns; ++k) {
-                const _Float16 rr = half_up(nrr);
-                const h2v rr2 = {rr, rr};
+                const _Float16 rr = nrr;
                 if (k + 1 < ns) {
                     const size_t fn = sFe[k + 1] * Npm;
-                    nrr = RR32[fn + row];
+                    nrr = RR16[2 * fn + row];
                     naj = A0[fn + (col0 >> 1) + lane];
                 }
                 const int s = __builtin_amdgcn_readfirstlane(sS[k]);
@@ -816,7 +817,7 @@ hipError_t launch_scan32(const Layout& lay, int scan_grid, hipStream_t st)
     if (lay.h16) {
         hipLaunchKernelGGL(k_plan16, dim3(1), dim3(1024), 0, st, lay, iprefix);
         hipLaunchKernelGGL(k_scan16, dim3(scan_grid), dim3(64), 0, st, lay, lay.J16, lay.J4,
-                           (const uint16_t*)lay.A32, (const float*)lay.RR32, (const double*)lay.F,
+                           (const uint16_t*)lay.A32, (const _Float16*)lay.RR32, (const double*)lay.F,
                            (const FrRec*)lay.rec, (const uint64_t*)lay.fbits, (const long long*)iprefix);
         return hipGetLastError();
     }
