@@ -1517,10 +1517,22 @@ __global__ __launch_bounds__(256) void k_fupdate(Layout lay, const double* __res
         const float* Jf = lay.J4f + lay.joff[b];
         const float* Ji = Jf + (size_t)i * Np;
         const float* Jj = Jf + (size_t)(pairf ? j : i) * Np;
-        for (int k = lane; k < Np; k += 64) {
-            double v = Fp[k] + ci * (double)Ji[k];
-            if (pairf) v += cj * (double)Jj[k];
-            Fn[k] = k < N ? v : 0.0;
+        // two entries per lane and load (rows are 64-entry aligned), four
+        // iterations in flight
+#pragma unroll 4
+        for (int k = 2 * lane; k < Np; k += 128) {
+            const double2 f = *reinterpret_cast<const double2*>(Fp + k);
+            const float2 ji = *reinterpret_cast<const float2*>(Ji + k);
+            double v0 = f.x + ci * (double)ji.x, v1 = f.y + ci * (double)ji.y;
+            if (pairf) {
+                const float2 jj = *reinterpret_cast<const float2*>(Jj + k);
+                v0 += cj * (double)jj.x;
+                v1 += cj * (double)jj.y;
+            }
+            double2 o;
+            o.x = k < N ? v0 : 0.0;
+            o.y = k + 1 < N ? v1 : 0.0;
+            *reinterpret_cast<double2*>(Fn + k) = o;
         }
         return;
     }
