@@ -206,13 +206,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             if (i < N) a = -2.0 * spin_d(x, i) * F[i];
             if (lay.tr_feat) A[i] = a;   // FP64 a is read back only by trace capture
             const double av = i < N ? (from_ft ? -2.0 * spin_d(x, i) * (double)Ft[i] : a) : 0.0;
-            if (H16) A16[i] = (_Float16)av;
+            if (H16) A16[i] = i < N ? (_Float16)av : (_Float16)INFINITY;   // padding: no pair can pass
             else A32[i] = (float)av;
             const float rr = i < N ? __double2float_ru(T - a + delta) : -INFINITY;
             if (H16) reinterpret_cast<_Float16*>(RR)[i] = half_up(rr);   // rounded up once more, to FP16
             else RR[i] = rr;
             nhit += __builtin_popcountll(__builtin_amdgcn_ballot_w64(i < N && Em + a <= c));
         }
+        // the FP16 scan reads whole 128-column tiles: +inf past Np as well
+        if (H16)
+            for (int i = Np + (int)lane; i < ((Np + 127) & ~127); i += 64) A16[i] = (_Float16)INFINITY;
         int base = 0;
         if (nhit) {
             if (lane == 0) base = atomicAdd(&lay.surv_count[s], nhit);
@@ -480,8 +483,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // The split scan in packed FP16 (on request): one wave per (instance, chunk of
 // states, tile of 64 rows x 128 columns with some column above the rows).
 // Lane = row i; 64 registers hold y_j = s_j fl16(4J_ij) for 128 columns as
-// pairs; per two pairs one v_pk_fma_f16 and one v_pk_min_f16, one compare per
-// group of 16 columns against RR_i rounded up to FP16.  RR_i carries the FP16
+// pairs; per group of 16 columns eight v_pk_fma_f16, four v_pk_minimum3_f16 and
+// one compare against RR_i rounded up to FP16.  RR_i carries the FP16
 // slack; admitted pairs are queued and re-scored in FP64 as in k_scan32.
 constexpr int T16 = 128;
 typedef _Float16 h2v __attribute__((ext_vector_type(2)));
@@ -541,7 +544,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const size_t fb = (size_t)b * lay.fmax;
         const int row = bi * TILE + (int)lane;
         const int col0 = bj * T16;
-        // groups of 16 columns with a pair in the triangle (the others hold only NaN)
+        // groups of 16 columns with a pair in the triangle (the others are skipped)
         uint32_t live = 0;
         for (int g = 0; g < T16 / 2; g += 8)
             if (col0 + 2 * g < N && col0 + 2 * g + 15 > bi * TILE) live |= 1u << (g >> 3);
@@ -549,7 +552,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         if (!live) continue;
         const int w0 = 2 * bj, w1 = 2 * bj + 1 < Wm ? 2 * bj + 1 : -1;   // words of the tile's columns
         // row i of the (symmetric) couplings, four columns per 8-byte load;
-        // columns at or past Np are not read
+        // columns at or past Np are not read.  No entry is NaN, so that a
+        // NaN-propagating three-way minimum can reduce them: rows and columns
+        // at or past N hold 0 (such a row's threshold is -inf, such a column's
+        // a_j is +inf); the diagonal holds +inf, which the column-sign tracking
+        // turns into s_i inf, so that its product with s_i is +inf; below the
+        // diagonal the couplings stay (each such pair is also met above it) and
+        // the admission step drops them.
         const uint64_t* Jrow = reinterpret_cast<const uint64_t*>(J16 + lay.joff[b] + (size_t)row * Np);
         uint32_t Jb[T16 / 2];   // columns col0 + 2v (low half) and col0 + 2v + 1 (high half)
 #pragma unroll
@@ -557,11 +566,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
             const int c4 = col0 + 4 * q;
             uint64_t v = (row < N && c4 < Np) ? Jrow[c4 >> 2] : 0ull;
 #pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                const int col = c4 + h;
-                if (!(row < N && col < N && col > row))   // NaN: fmin drops it
-                    v = (v & ~(0xFFFFull << (16 * h))) | (0x7E00ull << (16 * h));
-            }
+            for (int h = 0; h < 4; ++h)
+                if (row < N && c4 + h == row) v = (v & ~(0xFFFFull << (16 * h))) | (0x7C00ull << (16 * h));
             Jb[2 * q] = (uint32_t)v;
             Jb[2 * q + 1] = (uint32_t)(v >> 32);
         }
@@ -678,10 +684,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 #pragma unroll
                             for (int u = 0; u < 8; ++u) {
                                 // the two sign bits of the pair, formed in one scalar register
-                                // so that the flip is a single v_xor_b32
+                                // (bit 0 of the 2-bit field to bit 15, bit 1 to bit 31, by one
+                                // multiply) so that the flip is a single vector op
                                 const uint32_t fl = (uint32_t)__builtin_amdgcn_readfirstlane(
-                                    (int)(((uint32_t)((dwg >> (2 * u)) & 1ull) << 15) |
-                                          ((uint32_t)((dwg >> (2 * u + 1)) & 1ull) << 31)));
+                                    (int)(((((uint32_t)dwg >> (2 * u)) & 3u) * 0x40008000u) & 0x80008000u));
                                 Jb[g + u] ^= fl;
                             }
                         }
@@ -689,13 +695,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                             return __builtin_elementwise_fma(si2, __builtin_bit_cast(h2v, Jb[g + u]),
                                                              __builtin_bit_cast(h2v, a8[u]));
                         };
-                        h2v mm0 = __builtin_elementwise_min(xf(0), xf(1));
-                        h2v mm1 = __builtin_elementwise_min(xf(2), xf(3));
-                        mm0 = __builtin_elementwise_min(mm0, xf(4));
-                        mm1 = __builtin_elementwise_min(mm1, xf(5));
-                        mm0 = __builtin_elementwise_min(mm0, xf(6));
-                        mm1 = __builtin_elementwise_min(mm1, xf(7));
-                        const h2v mm = __builtin_elementwise_min(mm0, mm1);
+                        // three-way minima (v_pk_minimum3_f16): four for the 16 columns
+                        const h2v m1 = __builtin_elementwise_minimum(__builtin_elementwise_minimum(xf(0), xf(1)), xf(2));
+                        const h2v m2 = __builtin_elementwise_minimum(__builtin_elementwise_minimum(xf(3), xf(4)), xf(5));
+                        const h2v m3 = __builtin_elementwise_minimum(__builtin_elementwise_minimum(xf(6), xf(7)), m1);
+                        const h2v mm = __builtin_elementwise_minimum(m2, m3);
                         const bool any = mm[0] <= rr || mm[1] <= rr;
                         if (__builtin_amdgcn_ballot_w64(any)) {
                             // admitted pairs wait for the exact re-score; a mask of the
@@ -709,6 +713,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 #pragma unroll
                                 for (int h = 0; h < 2; ++h) am |= (xu[h] <= rr ? 1u : 0u) << (2 * u + h);
                             }
+                            // columns at or below the row (the diagonal block) are not pairs;
+                            // the empty asm keeps this rare step from being hoisted out of the
+                            // loop over states into registers held throughout it
+                            int rw = row;
+                            asm volatile("" : "+v"(rw));
+                            const int lo = rw - (col0 + 2 * g) + 1;
+                            if (lo > 0) am = lo >= 16 ? 0u : am & (0xFFFFu << lo);
                             // each round queues the lowest admitted column of every lane that
                             // has one (admitted pairs are sparse: usually one round)
                             for (uint64_t m = __builtin_amdgcn_ballot_w64(am != 0); m;
