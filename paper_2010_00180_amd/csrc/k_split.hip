@@ -16,6 +16,14 @@ __device__ inline uint32_t mbcnt64s(uint64_t m)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// A value the whole wave holds alike, moved to scalar registers.
+__device__ inline uint32_t uniform_u32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+
+__device__ inline uint64_t uniform_u64(uint64_t v)
+{
+    return ((uint64_t)uniform_u32((uint32_t)(v >> 32)) << 32) | uniform_u32((uint32_t)v);
+}
+
 __device__ inline double spin_d(const uint64_t* x, int i)
 {
     return ((x[i >> 6] >> (i & 63)) & 1ull) ? -1.0 : 1.0;
@@ -293,7 +301,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     __shared__ double sT[64], sE[64];
     __shared__ int sS[64], sCode[64];
     __shared__ uint64_t sWi[64], sWj[64];
-    __shared__ size_t sFe[64];
+    __shared__ uint32_t sFe[64];   // entry index: below 2^32, as the FP64 rows of every entry fit in memory
     constexpr int PEND = 640;
     __shared__ uint32_t pend[PEND];   // admitted pairs awaiting the FP64 re-score: k << 12 | row << 6 | col
     const uint32_t lane = lane_id32();
@@ -382,21 +390,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 sE[lane] = rc.E;
                 sS[lane] = rc.s;
                 sCode[lane] = rc.code;
-                sFe[lane] = fe;
+                sFe[lane] = (uint32_t)fe;
                 const uint64_t* fw = fbits + fe * Wm;
                 sWi[lane] = fw[bi];
                 sWj[lane] = fw[bj];
             }
             __syncthreads();
-            float nrr = RR32[sFe[0] * Npm + row];
-            float naj = A32[sFe[0] * Npm + col0 + lane];
+            const size_t fe0 = (size_t)uniform_u32(sFe[0]) * Npm;
+            float nrr = RR32[fe0 + row];
+            float naj = A32[fe0 + col0 + lane];
             int cur = 0;
             abuf[0][lane] = naj;
             __syncthreads();
             for (int k = 0; k < ns; ++k) {
                 const float rrt = nrr;
                 if (k + 1 < ns) {
-                    const size_t fn = sFe[k + 1] * Npm;
+                    const size_t fn = (size_t)uniform_u32(sFe[k + 1]) * Npm;
                     nrr = RR32[fn + row];
                     naj = A32[fn + col0 + lane];
                 }
@@ -408,11 +417,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                         flush32(lay, stage, nstage, sstage);
                         sstage = s;
                     }
-                    const uint64_t wi = sWi[k];
-                    const float si = ((wi >> lane) & 1ull) ? -1.f : 1.f;
-                    const uint32_t wlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)sWj[k]);
-                    const uint32_t whi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(sWj[k] >> 32));
-                    const uint64_t wj = ((uint64_t)whi << 32) | wlo;
+                    // the row bits of the state are the lane mask of the negative s_i
+                    const float si = __builtin_amdgcn_inverse_ballot_w64(uniform_u64(sWi[k])) ? -1.f : 1.f;
+                    const uint64_t wj = uniform_u64(sWj[k]);
                     const uint64_t dw = wj ^ prev_wj;
                     prev_wj = wj;
                     const float* aj = abuf[cur];
@@ -512,7 +519,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     __shared__ double sT[64], sE[64];
     __shared__ int sS[64], sCode[64];
     __shared__ uint64_t sWi[64], sWj0[64], sWj1[64];
-    __shared__ size_t sFe[64];
+    __shared__ uint32_t sFe[64];   // entry index: below 2^32, as the FP64 rows of every entry fit in memory
     constexpr int PEND = 512;
     __shared__ uint32_t pend[PEND];   // admitted pairs awaiting the FP64 re-score: k << 13 | row << 7 | col
     const uint32_t lane = lane_id32();
@@ -621,7 +628,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 sE[lane] = rc.E;
                 sS[lane] = rc.s;
                 sCode[lane] = rc.code;
-                sFe[lane] = fe;
+                sFe[lane] = (uint32_t)fe;
                 const uint64_t* fw = fbits + fe * Wm;
                 sWi[lane] = fw[bi];
                 sWj0[lane] = fw[w0];
@@ -631,15 +638,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
             // a row of state k: 2 Npmax halves per entry; the tile reads halves
             // col0 .. col0+127 < Np + 64 <= 2 Npmax
             const uint32_t* A0 = reinterpret_cast<const uint32_t*>(A16);
-            _Float16 nrr = RR16[sFe[0] * 2 * Npm + row];   // rows of 2 Npmax halves
-            uint32_t naj = A0[sFe[0] * Npm + (col0 >> 1) + lane];
+            const size_t fe0 = (size_t)uniform_u32(sFe[0]) * Npm;
+            _Float16 nrr = RR16[2 * fe0 + row];   // rows of 2 Npmax halves
+            uint32_t naj = A0[fe0 + (col0 >> 1) + lane];
             int cur = 0;
             abuf[0][lane] = naj;
             __syncthreads();
             for (int k = 0; k < ns; ++k) {
                 const _Float16 rr = nrr;
                 if (k + 1 < ns) {
-                    const size_t fn = sFe[k + 1] * Npm;
+                    const size_t fn = (size_t)uniform_u32(sFe[k + 1]) * Npm;
                     nrr = RR16[2 * fn + row];
                     naj = A0[fn + (col0 >> 1) + lane];
                 }
@@ -651,16 +659,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                         flush32(lay, stage, nstage, sstage);
                         sstage = s;
                     }
-                    const _Float16 sh = ((sWi[k] >> lane) & 1ull) ? (_Float16)-1.0f : (_Float16)1.0f;
-                    const h2v si2 = {sh, sh};
-                    uint64_t wj[2];
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const uint64_t wv = h == 0 ? sWj0[k] : sWj1[k];
-                        const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)wv);
-                        const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(wv >> 32));
-                        wj[h] = ((uint64_t)hi << 32) | lo;
-                    }
+                    // s_i for both halves (-1 or +1 in FP16): the row bits of the state
+                    // are the lane mask of the negative ones
+                    const h2v si2 = __builtin_bit_cast(
+                        h2v, __builtin_amdgcn_inverse_ballot_w64(uniform_u64(sWi[k])) ? 0xBC00BC00u : 0x3C003C00u);
+                    const uint64_t wj[2] = {uniform_u64(sWj0[k]), uniform_u64(sWj1[k])};
                     const uint64_t dw[2] = {wj[0] ^ prev0, wj[1] ^ prev1};
                     prev0 = wj[0];
                     prev1 = wj[1];
