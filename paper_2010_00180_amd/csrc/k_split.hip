@@ -24,10 +24,16 @@ __device__ inline uint64_t uniform_u64(uint64_t v)
     return ((uint64_t)uniform_u32((uint32_t)(v >> 32)) << 32) | uniform_u32((uint32_t)v);
 }
 
-__device__ inline double spin_d(const uint64_t* x, int i)
+// Word k of a state held one word per lane (lane k), as a wave-uniform value.
+__device__ inline uint64_t lane_word(uint64_t xw, int k)
 {
-    return ((x[i >> 6] >> (i & 63)) & 1ull) ? -1.0 : 1.0;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)xw, k);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(xw >> 32), k);
+    return ((uint64_t)hi << 32) | lo;
 }
+
+// blocks of 64 sites whose loads a preparation wave issues together
+constexpr int PREP_CH = 8;
 
 // ------------------------------------------------------------------ bf16 hi+lo GEMM
 // One wave: 16 sites x 16 searches of acc = (hi + lo) * S with
@@ -181,7 +187,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             r.code = code;
             lay.rec[fe] = r;
         }
-        if ((int)lane < lay.Wmax) lay.fbits[fe * lay.Wmax + lane] = x[lane];
+        // lane w holds word w of the state (at most 64 words)
+        const uint64_t xw = (int)lane < lay.Wmax ? x[lane] : 0ull;
+        if ((int)lane < lay.Wmax) lay.fbits[fe * lay.Wmax + lane] = xw;
         if (retry_mode && lane == 0) {
             // with the site bound the pairs are counted once the entries are sorted out
             if (!lay.sb) atomicAdd(&lay.ctr[CTR_PAIRS], (unsigned long long)N * (N - 1) / 2);
@@ -207,47 +215,72 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                     (from_ft ? 2.0 * lay.ebf[b] : 0.0);
         }
         _Float16* A16 = reinterpret_cast<_Float16*>(A32);
-        int nhit = 0;
-        for (int i0 = 0; i0 < Np; i0 += 64) {
-            const int i = i0 + lane;
-            double a = 0.0;
-            if (i < N) a = -2.0 * spin_d(x, i) * F[i];
-            if (lay.tr_feat) A[i] = a;   // FP64 a is read back only by trace capture
-            const double av = i < N ? (from_ft ? -2.0 * spin_d(x, i) * (double)Ft[i] : a) : 0.0;
-            if (H16) A16[i] = i < N ? (_Float16)av : (_Float16)INFINITY;   // padding: no pair can pass
-            else A32[i] = (float)av;
-            const float rr = i < N ? __double2float_ru(T - a + delta) : -INFINITY;
-            if (H16) reinterpret_cast<_Float16*>(RR)[i] = half_up(rr);   // rounded up once more, to FP16
-            else RR[i] = rr;
-            nhit += __builtin_popcountll(__builtin_amdgcn_ballot_w64(i < N && Em + a <= c));
-        }
-        // the FP16 scan reads whole 128-column tiles: +inf past Np as well
-        if (H16)
-            for (int i = Np + (int)lane; i < ((Np + 127) & ~127); i += 64) A16[i] = (_Float16)INFINITY;
-        int base = 0;
-        if (nhit) {
-            if (lane == 0) base = atomicAdd(&lay.surv_count[s], nhit);
-            base = __shfl(base, 0, 64);
-        }
-        for (int i0 = 0; nhit && i0 < Np; i0 += 64) {
-            const int i = i0 + lane;
-            double a = 0.0;
-            if (i < N) a = -2.0 * spin_d(x, i) * F[i];
-            const double Ec = Em + a;
-            const bool hit = i < N && Ec <= c;
-            const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
-            if (m) {
-                if (hit) {
-                    const int pos = base + (int)mbcnt64s(m);
-                    if (pos < lay.cap_surv) {
-                        Surv r;
-                        r.E = Ec;
-                        r.code = (uint32_t)code;
-                        r.pair = (uint32_t)i | (SINGLE << 16);
-                        lay.surv[(size_t)s * lay.cap_surv + pos] = r;
+        // rounds of PREP_CH blocks of 64 sites: the loads of a round are issued
+        // together, so that the wave waits on memory once per round
+        for (int i0 = 0; i0 < Np; i0 += 64 * PREP_CH) {
+            // blocks past Np load the last block again (unused), so that every
+            // load is unconditional and in bounds
+            double Fv[PREP_CH];
+            float Ftv[PREP_CH];
+#pragma unroll
+            for (int r = 0; r < PREP_CH; ++r) Fv[r] = F[min(i0 + 64 * r, Np - 64) + (int)lane];
+            if (from_ft) {
+#pragma unroll
+                for (int r = 0; r < PREP_CH; ++r) Ftv[r] = Ft[min(i0 + 64 * r, Np - 64) + (int)lane];
+            }
+            // a_i and the thresholds; the single flips below the cut are counted,
+            // so that one atomic reserves their places for the round
+            double ar[PREP_CH];
+            int nhit = 0;
+#pragma unroll
+            for (int r = 0; r < PREP_CH; ++r) {
+                const int ib = i0 + 64 * r;
+                ar[r] = 0.0;
+                if (ib < Np) {
+                    const int i = ib + (int)lane;
+                    // the word of sites ib .. ib+63 is the lane mask of the flipped spins
+                    const bool neg = __builtin_amdgcn_inverse_ballot_w64(lane_word(xw, ib >> 6));
+                    const double sp = neg ? -1.0 : 1.0;
+                    const double a = i < N ? -2.0 * sp * Fv[r] : 0.0;
+                    ar[r] = a;
+                    if (lay.tr_feat) A[i] = a;   // FP64 a is read back only by trace capture
+                    const double av = i < N ? (from_ft ? -2.0 * sp * (double)Ftv[r] : a) : 0.0;
+                    if (H16) A16[i] = i < N ? (_Float16)av : (_Float16)INFINITY;   // padding: no pair can pass
+                    else A32[i] = (float)av;
+                    const float rr = i < N ? __double2float_ru(T - a + delta) : -INFINITY;
+                    if (H16) reinterpret_cast<_Float16*>(RR)[i] = half_up(rr);   // rounded up once more, to FP16
+                    else RR[i] = rr;
+                    nhit += __builtin_popcountll(__builtin_amdgcn_ballot_w64(i < N && Em + a <= c));
+                }
+            }
+            if (H16 && i0 + 64 * PREP_CH >= Np) {
+                // the FP16 scan reads whole 128-column tiles: +inf past Np as well
+                for (int i = Np + (int)lane; i < ((Np + 127) & ~127); i += 64) A16[i] = (_Float16)INFINITY;
+            }
+            if (nhit) {
+                int base = 0;
+                if (lane == 0) base = atomicAdd(&lay.surv_count[s], nhit);
+                base = __shfl(base, 0, 64);
+#pragma unroll
+                for (int r = 0; r < PREP_CH; ++r) {
+                    const int i = i0 + 64 * r + (int)lane;
+                    const double Ec = Em + ar[r];
+                    const bool hit = i < N && Ec <= c;
+                    const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
+                    if (m) {
+                        if (hit) {
+                            const int pos = base + (int)mbcnt64s(m);
+                            if (pos < lay.cap_surv) {
+                                Surv rec;
+                                rec.E = Ec;
+                                rec.code = (uint32_t)code;
+                                rec.pair = (uint32_t)i | (SINGLE << 16);
+                                lay.surv[(size_t)s * lay.cap_surv + pos] = rec;
+                            }
+                        }
+                        base += __builtin_popcountll(m);
                     }
                 }
-                base += __builtin_popcountll(m);
             }
         }
     }

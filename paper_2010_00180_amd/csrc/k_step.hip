@@ -31,6 +31,17 @@ __device__ inline uint32_t mbcnt64(uint64_t m)
 
 __device__ inline int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Word k of a state held one word per lane (lane k), as a wave-uniform value.
+__device__ inline uint64_t word_of_lane(uint64_t xw, int k)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)xw, k);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(xw >> 32), k);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// blocks of 64 sites whose loads a preparation wave issues together
+constexpr int PREP_BLOCKS = 8;
+
 __device__ inline double spin_of(const uint64_t* x, int i)
 {
     return ((x[i >> 6] >> (i & 63)) & 1ull) ? -1.0 : 1.0;
@@ -580,7 +591,9 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
             r.code = code;
             lay.rec[fe] = r;
         }
-        if ((int)lane < lay.Wmax) lay.fbits[fe * lay.Wmax + lane] = x[lane];
+        // lane w holds word w of the state (at most 64 words)
+        const uint64_t xw = (int)lane < lay.Wmax ? x[lane] : 0ull;
+        if ((int)lane < lay.Wmax) lay.fbits[fe * lay.Wmax + lane] = xw;
         if (retry_mode && lane == 0) {
             const unsigned long long all = (unsigned long long)N * (N - 1) / 2;
             // with the site bound the pairs are counted once the entries are sorted out
@@ -595,41 +608,56 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
             if (lane == 0) lay.fr_bound[fe] = (uint16_t)(r + 1);
             if (r >= 0) continue;
         }
-        // a_i, and the single flips below the cut: counted first, so that one
+        // a_i, and the single flips below the cut, in rounds of PREP_BLOCKS
+        // blocks of 64 sites: the loads of a round are issued together (blocks
+        // past Np load the last block again, unused, so that every load is
+        // unconditional and in bounds); the round's hits are counted, so that one
         // atomic reserves their places, then recorded
-        int nhit = 0;
-        for (int i0 = 0; i0 < Np; i0 += 64) {
-            const int i = i0 + lane;
-            double a = 0.0;
-            if (i < N) a = -2.0 * spin_of(x, i) * F[i];
-            A[i] = a;
-            // a ranked state's singles go with its pairs
-            nhit += __builtin_popcountll(__builtin_amdgcn_ballot_w64(!ranked && i < N && Em + a <= c));
-        }
-        int base = 0;
-        if (nhit) {
-            if (lane == 0) base = atomicAdd(&lay.surv_count[s], nhit);
-            base = __shfl(base, 0, 64);
-        }
-        for (int i0 = 0; nhit && i0 < Np; i0 += 64) {
-            const int i = i0 + lane;
-            double a = 0.0;
-            if (i < N) a = -2.0 * spin_of(x, i) * F[i];
-            const double Ec = Em + a;
-            const bool hit = i < N && Ec <= c;
-            const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
-            if (m) {
-                if (hit) {
-                    const int pos = base + (int)mbcnt64(m);
-                    if (pos < lay.cap_surv) {
-                        Surv r;
-                        r.E = Ec;
-                        r.code = (uint32_t)code;
-                        r.pair = (uint32_t)i | (SINGLE << 16);
-                        lay.surv[(size_t)s * lay.cap_surv + pos] = r;
+        for (int i0 = 0; i0 < Np; i0 += 64 * PREP_BLOCKS) {
+            double Fv[PREP_BLOCKS];
+#pragma unroll
+            for (int r = 0; r < PREP_BLOCKS; ++r) Fv[r] = F[min(i0 + 64 * r, Np - 64) + (int)lane];
+            double ar[PREP_BLOCKS];
+            int nhit = 0;
+#pragma unroll
+            for (int r = 0; r < PREP_BLOCKS; ++r) {
+                const int ib = i0 + 64 * r;
+                ar[r] = 0.0;
+                if (ib < Np) {
+                    const int i = ib + (int)lane;
+                    // the word of sites ib .. ib+63 is the lane mask of the flipped spins
+                    const bool neg = __builtin_amdgcn_inverse_ballot_w64(word_of_lane(xw, ib >> 6));
+                    const double a = i < N ? -2.0 * (neg ? -1.0 : 1.0) * Fv[r] : 0.0;
+                    ar[r] = a;
+                    A[i] = a;
+                    // a ranked state's singles go with its pairs
+                    nhit += __builtin_popcountll(__builtin_amdgcn_ballot_w64(!ranked && i < N && Em + a <= c));
+                }
+            }
+            if (nhit) {
+                int base = 0;
+                if (lane == 0) base = atomicAdd(&lay.surv_count[s], nhit);
+                base = __shfl(base, 0, 64);
+#pragma unroll
+                for (int r = 0; r < PREP_BLOCKS; ++r) {
+                    const int i = i0 + 64 * r + (int)lane;
+                    const double Ec = Em + ar[r];
+                    const bool hit = i < N && Ec <= c;
+                    const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
+                    if (m) {
+                        if (hit) {
+                            const int pos = base + (int)mbcnt64(m);
+                            if (pos < lay.cap_surv) {
+                                Surv rec;
+                                rec.E = Ec;
+                                rec.code = (uint32_t)code;
+                                rec.pair = (uint32_t)i | (SINGLE << 16);
+                                lay.surv[(size_t)s * lay.cap_surv + pos] = rec;
+                            }
+                        }
+                        base += __builtin_popcountll(m);
                     }
                 }
-                base += __builtin_popcountll(m);
             }
         }
     }
