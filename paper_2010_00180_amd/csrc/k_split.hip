@@ -738,35 +738,44 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                         const h2v mm = __builtin_elementwise_minimum(m2, m3);
                         const bool any = mm[0] <= rr || mm[1] <= rr;
                         if (__builtin_amdgcn_ballot_w64(any)) {
-                            // admitted pairs wait for the exact re-score; a mask of the
-                            // lane's 16 columns, walked column by column so that the
-                            // queue is drained whenever a column could overfill it
-                            uint32_t am = 0;
+                            // admitted pairs wait for the exact re-score.  The lane's admitted
+                            // columns come from the signs of RR_i - x_ij (exact: +0 when equal),
+                            // gathered by byte permutes into a 16-bit mask in which bit 8b + q
+                            // stands for column 4q + b of the group
+                            const h2v rr2 = {rr, rr};
+                            uint32_t d[8];
 #pragma unroll
-                            for (int u = 0; u < 8; ++u) {
-                                const h2v xu = __builtin_elementwise_fma(si2, __builtin_bit_cast(h2v, Jb[g + u]),
-                                                                         __builtin_bit_cast(h2v, a8[u]));
+                            for (int u = 0; u < 8; ++u) d[u] = __builtin_bit_cast(uint32_t, rr2 - xf(u));
+                            uint32_t t = 0;
 #pragma unroll
-                                for (int h = 0; h < 2; ++h) am |= (xu[h] <= rr ? 1u : 0u) << (2 * u + h);
+                            for (int q = 0; q < 4; ++q) {
+                                // high bytes of both halves of d[2q] and d[2q+1]: columns 4q .. 4q+3
+                                const uint32_t sb = __builtin_amdgcn_perm(d[2 * q + 1], d[2 * q], 0x07050301u);
+                                t |= (sb >> (7 - q)) & (0x01010101u << q);
                             }
-                            // columns at or below the row (the diagonal block) are not pairs;
-                            // the empty asm keeps this rare step from being hoisted out of the
-                            // loop over states into registers held throughout it
+                            uint32_t am = ~t & 0x0F0F0F0Fu;
+                            // columns at or below the row (the diagonal block) or at or past N
+                            // are not pairs; the empty asm keeps this rare step from being
+                            // hoisted out of the loop over states
                             int rw = row;
                             asm volatile("" : "+v"(rw));
-                            const int lo = rw - (col0 + 2 * g) + 1;
-                            if (lo > 0) am = lo >= 16 ? 0u : am & (0xFFFFu << lo);
+                            const int lo = rw - (col0 + 2 * g) + 1, hi = N - (col0 + 2 * g);
                             // each round queues the lowest admitted column of every lane that
                             // has one (admitted pairs are sparse: usually one round)
                             for (uint64_t m = __builtin_amdgcn_ballot_w64(am != 0); m;
                                  m = __builtin_amdgcn_ballot_w64(am != 0)) {
                                 if (npend > PEND - 64) rescore();
+                                int j = -1;
                                 if (am) {
-                                    pend[npend + (int)mbcnt64s(m)] = ((uint32_t)k << 13) | (lane << 7) |
-                                                                     (uint32_t)(2 * g + __builtin_ctz(am));
+                                    const int p = __builtin_ctz(am);
                                     am &= am - 1u;
+                                    j = 4 * (p & 7) + (p >> 3);
+                                    if (j < lo || j >= hi) j = -1;
                                 }
-                                npend += __builtin_popcountll(m);
+                                const uint64_t w = __builtin_amdgcn_ballot_w64(j >= 0);
+                                if (j >= 0)
+                                    pend[npend + (int)mbcnt64s(w)] = ((uint32_t)k << 13) | (lane << 7) | (uint32_t)(2 * g + j);
+                                npend += __builtin_popcountll(w);
                             }
                         }
                     }
