@@ -143,12 +143,16 @@ __device__ inline int pow2_at_least(int n)
 // child energies.  The cut starts at the M-th kept energy (a child above it
 // ranks behind the whole kept set, the paper's "E < E_{K+1}" acceptance test).
 // Pilots tighten it: any M distinct members of the union bound its M-th
-// lowest distinct energy from above.  The pilots are the NPILOT lowest new
-// states; each offers its single flips and pair flips among its PILOT_K
-// lightest sites (lowest a_i), with exact energies.  Two such children of
-// pilots p, q are the same state iff x_p xor x_q equals the symmetric
-// difference of their flip sets, which is checked exactly from the pilots'
-// words, so the pool's M-th distinct energy is a valid cut.
+// lowest distinct energy from above, whichever children they are.  The pilots
+// are the NPIL lowest new states, one wave each: every lane takes the lightest
+// of its sites (i = lane mod 64, lowest a_i), the wave sorts the 64, and the
+// pilot offers the single flips of the PKW lightest of them and the pair flips
+// among these, with exact energies (more pilots with fewer sites each give a
+// tighter cut than a few pilots with many sites).  A ranking step (learned
+// form) instead takes the singles of the PCAND lightest sites of NPILOT
+// pilots.  Two children of pilots p, q are the same state iff x_p xor x_q
+// equals the symmetric difference of their flip sets, which is checked exactly
+// from the pilots' words, so the pool's M-th distinct energy is a valid cut.
 // Sorts by (value, index) the shortest prefix of the (value, index) order of
 // n elements that holds at least `need` of them, into key/idx[0..cnt), and
 // returns cnt.  A 256-bin histogram over [min, max] finds the prefix: every
@@ -243,9 +247,31 @@ __device__ int sort_prefix(const Get& get, int n, int need, double* key, uint32_
     return cnt;
 }
 
-constexpr int NPILOT = 4;
-constexpr int PK = 32;                       // lightest sites per pilot
-constexpr int PCAND = PK * (PK + 1) / 2;     // candidates per pilot
+constexpr int NPILOT = 4;                    // pilots of a ranking step
+constexpr int PK = 32;
+constexpr int PCAND = PK * (PK + 1) / 2;     // singles per pilot of a ranking step
+constexpr int NPIL = 32;                     // pilots of a full step
+constexpr int PKW = 10;                      // sites per pilot of a full step (at least)
+constexpr int PCW = PKW * (PKW + 1) / 2;     // candidates per pilot of a full step
+constexpr int POOL = NPILOT * PCAND;         // candidate pool
+static_assert(NPIL * PCW <= POOL, "the candidate pool holds either kind of step");
+static_assert(NPIL <= 32, "the pilot index takes the top 6 bits of a candidate id");
+
+// Sites where the states at xa and xb differ, up to 4 of them into d;
+// returns their number, or 5 when there are more.
+__device__ inline int pilot_diff(const uint64_t* xa, const uint64_t* xb, int W, int* d)
+{
+    int n = 0;
+    for (int w = 0; w < W && n <= 4; ++w) {
+        uint64_t x = xa[w] ^ xb[w];
+        while (x && n <= 4) {
+            if (n < 4) d[n] = w * 64 + __builtin_ctzll(x);
+            ++n;
+            x &= x - 1;
+        }
+    }
+    return n;
+}
 
 __device__ inline void cand_sites(uint32_t id, int* out, int& n)
 {
@@ -262,10 +288,9 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
     __shared__ double pE[NPILOT * PCAND];
     __shared__ uint32_t pid[NPILOT * PCAND];
     __shared__ int tmp[256];
-    __shared__ int pslot[NPILOT];
-    __shared__ int dsites[NPILOT][NPILOT][5];   // [0] = count (5 = farther than 4 flips)
-    __shared__ double aK[PK];
-    __shared__ int iK[PK];
+    __shared__ int pslot[NPIL];
+    __shared__ double aW[4][64];   // a full step: the sites of each wave's pilot
+    __shared__ int iW[4][64];
     __shared__ PrefixShared ps;
     const int s = blockIdx.x;
     const int b = s / lay.L;
@@ -304,7 +329,7 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
         }
         if (nfresh > 0) tmp[0] = atomicAdd(ranked ? &lay.lr_count[b] : &lay.fr_count[b], nfresh);
     }
-    if ((int)threadIdx.x < NPILOT) pslot[threadIdx.x] = (int)threadIdx.x < nfresh ? (int)idx[threadIdx.x] : -1;
+    if ((int)threadIdx.x < NPIL) pslot[threadIdx.x] = (int)threadIdx.x < nfresh ? (int)idx[threadIdx.x] : -1;
     __syncthreads();
     if (nfresh > 0) {
         const int fr_base = tmp[0];
@@ -324,66 +349,102 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
     const int W = words_of(N);
     // a ranking step offers every single flip but only ranked pairs, so its
     // pilots contribute their lightest single flips only
-    const int K = N < PK ? N : PK;
-    const int nc = ranked ? (N < PCAND ? N : PCAND) : K * (K + 1) / 2;
-    const int np = nfresh < NPILOT ? nfresh : NPILOT;
+    const int npil = ranked ? NPILOT : NPIL;
+    const int np = nfresh < npil ? nfresh : npil;
+    // few pilots take more sites each, up to twice M candidates as the pool allows
+    int KW = PKW;
+    while (KW < 64 && np * (KW * (KW + 1) / 2) < 2 * M && np * ((KW + 1) * (KW + 2) / 2) <= POOL) ++KW;
+    if (KW > N) KW = N;
+    const int nc = ranked ? (N < PCAND ? N : PCAND) : KW * (KW + 1) / 2;
     if (nc * np < M) {   // too few candidates to bound anything
         if (threadIdx.x == 0) lay.cut[s] = ecut;
         return;
     }
-    // sites where two pilots differ (when at most 4)
-    if ((int)threadIdx.x < np * np) {
-        const int p = threadIdx.x / np, q = threadIdx.x % np;
-        const uint64_t* xp = lay.bits + (q0 + pslot[p]) * lay.Wmax;
-        const uint64_t* xq = lay.bits + (q0 + pslot[q]) * lay.Wmax;
-        int n = 0;
-        for (int w = 0; w < W && n <= 4; ++w) {
-            uint64_t d = xp[w] ^ xq[w];
-            while (d && n <= 4) {
-                const int bit = __builtin_ctzll(d);
-                if (n < 4) dsites[p][q][1 + n] = w * 64 + bit;
-                ++n;
-                d &= d - 1;
+    if (ranked) {
+        for (int p = 0; p < np; ++p) {
+            const uint64_t* xp = lay.bits + (q0 + pslot[p]) * lay.Wmax;
+            const double* Fp = lay.F + (q0 + pslot[p]) * lay.Npmax;
+            const double Ep = lay.E[q0 + pslot[p]];
+            // the lightest sites (lowest a_i, then lowest i) in key/idx[0 ..)
+            sort_prefix([&](int i, double& v, uint32_t& id) {
+                v = -2.0 * spin_of(xp, i) * Fp[i];
+                id = (uint32_t)i;
+            }, N, nc, key, idx, ps);
+            for (int t = threadIdx.x; t < nc; t += blockDim.x) {
+                pE[p * nc + t] = Ep + key[t];
+                pid[p * nc + t] = ((uint32_t)p << 26) | (1u << 25) | (idx[t] << 12);
             }
+            __syncthreads();
         }
-        dsites[p][q][0] = n;
-    }
-    const double* Jb = J4 + lay.joff[b];
-    for (int p = 0; p < np; ++p) {
-        const uint64_t* xp = lay.bits + (q0 + pslot[p]) * lay.Wmax;
-        const double* Fp = lay.F + (q0 + pslot[p]) * lay.Npmax;
-        const double Ep = lay.E[q0 + pslot[p]];
-        // the lightest sites (lowest a_i, then lowest i) in key/idx[0 ..)
-        sort_prefix([&](int i, double& v, uint32_t& id) {
-            v = -2.0 * spin_of(xp, i) * Fp[i];
-            id = (uint32_t)i;
-        }, N, ranked ? nc : K, key, idx, ps);
-        if ((int)threadIdx.x < K) {
-            aK[threadIdx.x] = key[threadIdx.x];
-            iK[threadIdx.x] = (int)idx[threadIdx.x];
-        }
-        __syncthreads();
-        for (int t = threadIdx.x; t < nc; t += blockDim.x) {
-            double v;
-            uint32_t id;
-            if (ranked) {
-                v = key[t];
-                id = (1u << 25) | (idx[t] << 12);
-            } else if (t < K) {
-                v = aK[t];
-                id = (1u << 25) | ((uint32_t)iK[t] << 12);
-            } else {
-                int u = t - K, a = 0;   // pairs (a, c), a < c < K
-                while (u >= K - 1 - a) { u -= K - 1 - a; ++a; }
-                const int c = a + 1 + u;
-                int i = iK[a], j = iK[c];
-                if (i > j) { const int x = i; i = j; j = x; }
-                const double sij = spin_of(xp, i) * spin_of(xp, j);
-                v = aK[a] + aK[c] + sij * Jb[(size_t)i * Np + j];
-                id = ((uint32_t)i << 12) | (uint32_t)j;
+    } else {
+        const double* Jb = J4 + lay.joff[b];
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        for (int p = wave; p < np; p += 4) {
+            const uint64_t* xp = lay.bits + (q0 + pslot[p]) * lay.Wmax;
+            const double* Fp = lay.F + (q0 + pslot[p]) * lay.Npmax;
+            const double Ep = lay.E[q0 + pslot[p]];
+            // the lane's lightest site (the first of equals): rounds of 8 blocks
+            // of 64 sites whose loads are issued together (blocks past Np load
+            // the last block again, unused); the word of block k, held by lane
+            // k, is the lane mask of the flipped spins
+            const uint64_t xw = lane < W ? xp[lane] : 0ull;
+            double best = INFINITY;
+            int bi = 0x7FFFFFFF;
+            for (int i0 = 0; i0 < N; i0 += 512) {
+                double f[8];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) f[r] = Fp[min(i0 + 64 * r, Np - 64) + lane];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int ib = i0 + 64 * r, i = ib + lane;
+                    if (ib < N) {
+                        const bool neg = __builtin_amdgcn_inverse_ballot_w64(word_of_lane(xw, ib >> 6));
+                        const double a = -2.0 * (neg ? -1.0 : 1.0) * f[r];
+                        if (i < N && a < best) {
+                            best = a;
+                            bi = i;
+                        }
+                    }
+                }
             }
-            pE[p * nc + t] = Ep + v;
-            pid[p * nc + t] = ((uint32_t)p << 26) | id;
+            // bitonic sort of the 64 (a, i) across the wave, ascending
+            for (int k = 2; k <= 64; k <<= 1)
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    const double ob = __shfl_xor(best, j, 64);
+                    const int oi = __shfl_xor(bi, j, 64);
+                    const bool other_less = ob < best || (ob == best && oi < bi);
+                    // in an ascending run the lower lane of a pair keeps the smaller
+                    const bool keep_small = ((lane & k) == 0) == ((lane & j) == 0);
+                    if (other_less == keep_small) {
+                        best = ob;
+                        bi = oi;
+                    }
+                }
+            if (lane < KW) {
+                aW[wave][lane] = best;
+                iW[wave][lane] = bi;
+            }
+            wave_sync();
+            for (int t = lane; t < nc; t += 64) {
+                double v;
+                uint32_t id;
+                if (t < KW) {
+                    v = aW[wave][t];
+                    id = (1u << 25) | ((uint32_t)iW[wave][t] << 12);
+                } else {
+                    int u = t - KW, a = 0;   // pairs (a, c), a < c < KW
+                    while (u >= KW - 1 - a) { u -= KW - 1 - a; ++a; }
+                    const int c = a + 1 + u;
+                    int i = iW[wave][a], j = iW[wave][c];
+                    if (i > j) { const int x = i; i = j; j = x; }
+                    const double sij = spin_of(xp, i) * spin_of(xp, j);
+                    v = aW[wave][a] + aW[wave][c] + sij * Jb[(size_t)i * Np + j];
+                    id = ((uint32_t)i << 12) | (uint32_t)j;
+                }
+                pE[p * nc + t] = Ep + v;
+                pid[p * nc + t] = ((uint32_t)p << 26) | id;
+            }
+            wave_sync();   // aW is rewritten for the wave's next pilot
         }
         __syncthreads();
     }
@@ -412,7 +473,9 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
                 const uint32_t ib = idx[u];
                 const int pb = (int)(ib >> 26);
                 if (pb == pa) continue;   // children of one parent are distinct
-                const int nd = dsites[pa][pb][0];
+                int dsite[4];
+                const int nd = pilot_diff(lay.bits + (q0 + pslot[pa]) * lay.Wmax,
+                                          lay.bits + (q0 + pslot[pb]) * lay.Wmax, W, dsite);
                 if (nd > 4) continue;
                 int fb[2], nb2;
                 cand_sites(ib, fb, nb2);
@@ -432,7 +495,7 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
                 bool same = true;
                 for (int e = 0; e < ns && same; ++e) {
                     bool in = false;
-                    for (int g = 0; g < nd; ++g) in |= sd[e] == dsites[pa][pb][1 + g];
+                    for (int g = 0; g < nd; ++g) in |= sd[e] == dsite[g];
                     same = in;
                 }
                 if (same) isnew = 0;
