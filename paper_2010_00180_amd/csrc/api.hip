@@ -619,6 +619,10 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     if (hipGetDeviceProperties(&prop, hd->device) == hipSuccess && prop.multiProcessorCount > 0)
         cus = prop.multiProcessorCount;
     hd->scan_grid = cus * 16;
+    if (frontier_set_lds(lay) != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(fail(ISING_ERR_HIP, "the frontier kernel cannot use its LDS"));
+    }
     if (cfg->form == ISING_FORM_LEARNED) {
         const size_t lds = learn_lds_bytes(lay);
         if (learn_set_lds(lds) != hipSuccess) {

@@ -447,6 +447,7 @@ hipError_t launch_scan32(const Layout& lay, int scan_grid, hipStream_t st);
 hipError_t launch_step_begin(const Layout& lay, bool retry_mode, hipStream_t st);
 hipError_t launch_learn(const Layout& lay, int grid, hipStream_t st);
 hipError_t learn_set_lds(size_t bytes);
+hipError_t frontier_set_lds(const Layout& lay);
 size_t learn_lds_bytes(const Layout& lay);
 hipError_t launch_trace(const Layout& lay, hipStream_t st);
 // training of the scoring network (device pointers; partial = workspace)

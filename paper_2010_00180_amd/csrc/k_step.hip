@@ -149,7 +149,7 @@ __device__ inline int pow2_at_least(int n)
 // pilot offers the single flips of the PKW lightest of them and the pair flips
 // among these, with exact energies (more pilots with fewer sites each give a
 // tighter cut than a few pilots with many sites).  A ranking step (learned
-// form) instead takes the singles of the PCAND lightest sites of NPILOT
+// form) instead takes the singles of the PRANK lightest sites of NPILOT
 // pilots.  Two children of pilots p, q are the same state iff x_p xor x_q
 // equals the symmetric difference of their flip sets, which is checked exactly
 // from the pilots' words, so the pool's M-th distinct energy is a valid cut.
@@ -248,13 +248,13 @@ __device__ int sort_prefix(const Get& get, int n, int need, double* key, uint32_
 }
 
 constexpr int NPILOT = 4;                    // pilots of a ranking step
-constexpr int PK = 32;
-constexpr int PCAND = PK * (PK + 1) / 2;     // singles per pilot of a ranking step
+constexpr int PRANK = 512;                   // singles per pilot of a ranking step
 constexpr int NPIL = 32;                     // pilots of a full step
 constexpr int PKW = 10;                      // sites per pilot of a full step (at least)
 constexpr int PCW = PKW * (PKW + 1) / 2;     // candidates per pilot of a full step
-constexpr int POOL = NPILOT * PCAND;         // candidate pool
+constexpr int POOL = NPILOT * PRANK;         // candidate pool, a power of 2
 static_assert(NPIL * PCW <= POOL, "the candidate pool holds either kind of step");
+static_assert(POOL >= 1024 && POOL >= 4 * 64, "key/idx hold the fresh states (M <= 1024) and the pilots' sites");
 static_assert(NPIL <= 32, "the pilot index takes the top 6 bits of a candidate id");
 
 // Sites where the states at xa and xb differ, up to 4 of them into d;
@@ -281,16 +281,17 @@ __device__ inline void cand_sites(uint32_t id, int* out, int& n)
     if (!((id >> 25) & 1u)) out[n++] = (int)(id & 0xFFFu);
 }
 
-__global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __restrict__ J4)
+__global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __restrict__ J4, int kn)
 {
-    __shared__ double key[MAX_N];
-    __shared__ uint32_t idx[MAX_N];
-    __shared__ double pE[NPILOT * PCAND];
-    __shared__ uint32_t pid[NPILOT * PCAND];
+    // key/idx: kn >= max(POOL, pow2(Npmax)) entries, in dynamic LDS, so that
+    // three blocks share a CU for N up to 2048
+    extern __shared__ __align__(16) unsigned char fr_dyn[];
+    double* const key = reinterpret_cast<double*>(fr_dyn);
+    uint32_t* const idx = reinterpret_cast<uint32_t*>(fr_dyn + sizeof(double) * kn);
+    __shared__ double pE[POOL];
+    __shared__ uint32_t pid[POOL];
     __shared__ int tmp[256];
     __shared__ int pslot[NPIL];
-    __shared__ double aW[4][64];   // a full step: the sites of each wave's pilot
-    __shared__ int iW[4][64];
     __shared__ PrefixShared ps;
     const int s = blockIdx.x;
     const int b = s / lay.L;
@@ -355,7 +356,7 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
     int KW = PKW;
     while (KW < 64 && np * (KW * (KW + 1) / 2) < 2 * M && np * ((KW + 1) * (KW + 2) / 2) <= POOL) ++KW;
     if (KW > N) KW = N;
-    const int nc = ranked ? (N < PCAND ? N : PCAND) : KW * (KW + 1) / 2;
+    const int nc = ranked ? (N < PRANK ? N : PRANK) : KW * (KW + 1) / 2;
     if (nc * np < M) {   // too few candidates to bound anything
         if (threadIdx.x == 0) lay.cut[s] = ecut;
         return;
@@ -379,6 +380,9 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
     } else {
         const double* Jb = J4 + lay.joff[b];
         const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        // the sites of each wave's pilot, in key/idx (free until the pool is sorted)
+        double* const aW = key + 64 * wave;
+        uint32_t* const iW = idx + 64 * wave;
         for (int p = wave; p < np; p += 4) {
             const uint64_t* xp = lay.bits + (q0 + pslot[p]) * lay.Wmax;
             const double* Fp = lay.F + (q0 + pslot[p]) * lay.Npmax;
@@ -421,24 +425,24 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
                     }
                 }
             if (lane < KW) {
-                aW[wave][lane] = best;
-                iW[wave][lane] = bi;
+                aW[lane] = best;
+                iW[lane] = (uint32_t)bi;
             }
             wave_sync();
             for (int t = lane; t < nc; t += 64) {
                 double v;
                 uint32_t id;
                 if (t < KW) {
-                    v = aW[wave][t];
-                    id = (1u << 25) | ((uint32_t)iW[wave][t] << 12);
+                    v = aW[t];
+                    id = (1u << 25) | (iW[t] << 12);
                 } else {
                     int u = t - KW, a = 0;   // pairs (a, c), a < c < KW
                     while (u >= KW - 1 - a) { u -= KW - 1 - a; ++a; }
                     const int c = a + 1 + u;
-                    int i = iW[wave][a], j = iW[wave][c];
+                    int i = (int)iW[a], j = (int)iW[c];
                     if (i > j) { const int x = i; i = j; j = x; }
                     const double sij = spin_of(xp, i) * spin_of(xp, j);
-                    v = aW[wave][a] + aW[wave][c] + sij * Jb[(size_t)i * Np + j];
+                    v = aW[a] + aW[c] + sij * Jb[(size_t)i * Np + j];
                     id = ((uint32_t)i << 12) | (uint32_t)j;
                 }
                 pE[p * nc + t] = Ep + v;
@@ -1687,10 +1691,26 @@ hipError_t launch_step_begin(const Layout& lay, bool retry_mode, hipStream_t st)
     return hipGetLastError();
 }
 
+// Entries of the frontier's key/idx arrays: the candidate pool, the fresh
+// states (M <= 1024) and a prefix of the sites of one state.
+static int frontier_keys(const Layout& lay)
+{
+    int kn = POOL;
+    while (kn < lay.Npmax) kn <<= 1;
+    return kn;
+}
+
+hipError_t frontier_set_lds(const Layout& lay)
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(k_frontier), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               frontier_keys(lay) * 12);
+}
+
 hipError_t launch_frontier_plan(const Layout& lay, hipStream_t st)
 {
     long long* fr_prefix = lay.item_prefix + (lay.B + 1);
-    hipLaunchKernelGGL(k_frontier, dim3(lay.S), dim3(256), 0, st, lay, lay.J4);
+    const int kn = frontier_keys(lay);
+    hipLaunchKernelGGL(k_frontier, dim3(lay.S), dim3(256), (size_t)kn * 12, st, lay, lay.J4, kn);
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, lay, fr_prefix, 1);
     return hipGetLastError();
 }
