@@ -85,7 +85,10 @@ typedef struct {
     int32_t M;                 /* states kept per search, >= 1 */
     int32_t max_iters;         /* default step cap used by ising_search_run when its cap is <= 0 */
     int32_t form;              /* ising_form_t */
-    int32_t states_per_item;   /* scan tile: frontier states per work item; 0 = tuned default */
+    int32_t states_per_item;   /* scan tile: frontier states per work item; 0 = chosen by every step
+                                  from its work (the largest power of two up to 256 that leaves each
+                                  scan wave 16 items; 64 with the site bound or the learned form) until
+                                  ising_search_autotune replaces it */
     int32_t topk_factor;       /* learned form: K = topk_factor * N pairs per state (default 8) */
     int32_t persistent;        /* 1 = capture the kernels of one step into a hipGraph once and replay
                                   it for every step (an internal stream is used when none is given) */
@@ -207,7 +210,8 @@ int ising_search_get_stats(ising_search_t *s, ising_stats_t *out);
  */
 int ising_search_autotune(ising_search_t *s, int32_t *n_active);
 
-/* The states per scan item in use for each instance (n_inst values). */
+/* The states per scan item in use for each instance (n_inst values; when
+   chosen per step, those of the last step). */
 int ising_search_get_tuning(ising_search_t *s, int32_t *states_per_item);
 
 /*

@@ -424,6 +424,9 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     lay.Jn16 = dJn;
     lay.sb = sb ? 1 : 0;
     lay.h16 = h16 ? 1 : 0;
+    // states per scan item chosen each step unless given, tuned, or the scan
+    // serves only the states the site bound leaves (or ranked ones)
+    lay.sc_auto = (cfg->states_per_item == 0 && !sb && cfg->form != ISING_FORM_LEARNED) ? 1 : 0;
     lay.J16 = dJ16;
     lay.rmax4 = drm;
     lay.mlp = hd->d_mlp;
@@ -619,6 +622,7 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     if (hipGetDeviceProperties(&prop, hd->device) == hipSuccess && prop.multiProcessorCount > 0)
         cus = prop.multiProcessorCount;
     hd->scan_grid = cus * 16;
+    hd->lay.scan_waves = hd->scan_grid;
     if (frontier_set_lds(lay) != hipSuccess) {
         (void)hipGetLastError();
         return bail(fail(ISING_ERR_HIP, "the frontier kernel cannot use its LDS"));
@@ -767,6 +771,11 @@ extern "C" int ising_search_autotune(ising_search_t* s, int32_t* n_active)
     if (rc != ISING_OK) return rc;
     if (s->lay.form == ISING_FORM_LEARNED && !s->scorer_set)
         return fail(ISING_ERR_BAD_STATE, "the learned form needs ising_search_set_scorer before stepping");
+    // tuned tiles replace the per-step choice (and any step captured with it)
+    if (s->lay.sc_auto) {
+        s->lay.sc_auto = 0;
+        drop_graph(s);
+    }
     const Layout& lay = s->lay;
     hipStream_t st = s->stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -856,6 +865,13 @@ extern "C" int ising_search_get_tuning(ising_search_t* s, int32_t* states_per_it
     int rc = check_handle(s);
     if (rc != ISING_OK) return rc;
     if (!states_per_item) return fail(ISING_ERR_INVALID_ARG, "NULL output pointer");
+    if (s->lay.sc_auto) {
+        // chosen by the last step's plan
+        HIP_TRY(hipMemcpyAsync(states_per_item, s->d_scb, sizeof(int32_t) * s->lay.B, hipMemcpyDeviceToHost,
+                               s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        return ISING_OK;
+    }
     for (int b = 0; b < s->lay.B; ++b) states_per_item[b] = s->sc_h[b];
     return ISING_OK;
 }

@@ -58,7 +58,9 @@ struct Layout {
     int Wmax, Npmax;         // words and padded spins of the largest instance
     int fmax;                // frontier entries per instance (= L*M)
     int cap_surv;            // survivor records per search
-    const int* scb;          // [B] frontier states per scan item, per instance (tuned per N)
+    int* scb;                // [B] frontier states per scan item, per instance (tuned per N)
+    int sc_auto;             // 1: the plan chooses the states per item each step
+    int scan_waves;          // waves of the scan's grid
     const int* N;            // [B]
     const int* Npad;         // [B]
     const long long* joff;   // [B] offset of instance b in J4 (doubles)
@@ -154,6 +156,27 @@ __host__ __device__ inline int pad_of(int N) { return (N + TILE - 1) / TILE * TI
 __host__ __device__ inline long long tiles_of(int N) {
     const long long nb = (N + TILE - 1) / TILE, nc = 2 * nb;
     return nb * nc - nb * (nb - 1);
+}
+// Tiles of 64 x 64 (FP32 scan) with row block <= column block.
+__host__ __device__ inline long long tiles64(int N)
+{
+    const long long nb = (N + TILE - 1) / TILE;
+    return nb * (nb + 1) / 2;
+}
+// Tiles of 64 rows x 128 columns (FP16 scan) with some column above the rows.
+constexpr int T16 = 128;
+__host__ __device__ inline long long tiles16(int N)
+{
+    const int Np = pad_of(N);
+    const int nb = Np / TILE, nc = (Np + T16 - 1) / T16;
+    long long t = 0;
+    for (int bi = 0; bi < nb; ++bi) t += nc - (bi >> 1);
+    return t;
+}
+// Tiles of the form's full scan.
+__host__ __device__ inline long long scan_tiles(const Layout& lay, int N)
+{
+    return lay.form == 1 ? (lay.h16 ? tiles16(N) : tiles64(N)) : tiles_of(N);
 }
 
 // Site bound of one frontier state, evaluated by one wave.  The pair (i, j)

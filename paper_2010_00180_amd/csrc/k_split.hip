@@ -312,12 +312,6 @@ __device__ inline void flush32(const Layout& lay, Surv* stage, int& n, int s)
     n = 0;
 }
 
-__device__ inline long long tiles64(int N)
-{
-    const long long nb = (N + TILE - 1) / TILE;
-    return nb * (nb + 1) / 2;
-}
-
 // At most 128 VGPRs, so that four waves share each SIMD: the loop is bound by
 // latency, and occupancy decides its speed.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_scan32(Layout lay, const float* __restrict__ J32,
@@ -526,17 +520,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // pairs; per group of 16 columns eight v_pk_fma_f16, four v_pk_minimum3_f16 and
 // one compare against RR_i rounded up to FP16.  RR_i carries the FP16
 // slack; admitted pairs are queued and re-scored in FP64 as in k_scan32.
-constexpr int T16 = 128;
 typedef _Float16 h2v __attribute__((ext_vector_type(2)));
-
-__device__ inline long long tiles16(int N)
-{
-    const int Np = pad_of(N);
-    const int nb = Np / TILE, nc = (Np + T16 - 1) / T16;
-    long long t = 0;
-    for (int bi = 0; bi < nb; ++bi) t += nc - (bi >> 1);
-    return t;
-}
 
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_scan16(Layout lay, const uint16_t* __restrict__ J16,
                                                const double* __restrict__ J4,

@@ -538,12 +538,36 @@ __global__ __launch_bounds__(1024) void k_plan(Layout lay, long long* __restrict
     const int t = threadIdx.x;
     const int per = (lay.B + 1023) / 1024;
     const int b0 = t * per;
+    __shared__ int sc_all;
+    if (lay.sc_auto) {
+        // states per scan item, chosen each step: the largest power of two up
+        // to 256 that still gives every scan wave 16 items of this step's
+        // tiles x states, so that each item loads its couplings for as many
+        // states as the balance of the grid allows
+        __shared__ long long wsum[1024];
+        long long w = 0;
+        for (int b = b0; b < b0 + per && b < lay.B; ++b) w += (long long)lay.fr_count[b] * scan_tiles(lay, lay.N[b]);
+        wsum[t] = w;
+        __syncthreads();
+        for (int off = 512; off > 0; off >>= 1) {
+            if (t < off) wsum[t] += wsum[t + off];
+            __syncthreads();
+        }
+        if (t == 0) {
+            const long long target = 16ll * lay.scan_waves;
+            int sc = 256;
+            while (sc > 16 && wsum[0] / sc < target) sc >>= 1;
+            sc_all = sc;
+        }
+        __syncthreads();
+        for (int b = b0; b < b0 + per && b < lay.B; ++b) lay.scb[b] = sc_all;
+    }
     long long items = 0, fr = 0, lr = 0, pairs = 0, singles = 0, scored = 0;
     for (int b = b0; b < b0 + per && b < lay.B; ++b) {
         const long long P = lay.fr_count[b];
         const long long Q = lay.lr_count[b];
         const long long N = lay.N[b];
-        const int sc = lay.scb[b];
+        const int sc = lay.sc_auto ? sc_all : lay.scb[b];
         items += (P + sc - 1) / sc * tiles_of((int)N);
         fr += P + Q;
         lr += Q;
@@ -573,7 +597,8 @@ __global__ __launch_bounds__(1024) void k_plan(Layout lay, long long* __restrict
         lr_prefix[b] = run_l;
         const long long P = lay.fr_count[b];
         const long long Q = lay.lr_count[b];
-        run_i += (P + lay.scb[b] - 1) / lay.scb[b] * tiles_of(lay.N[b]);
+        const int sc = lay.sc_auto ? sc_all : lay.scb[b];
+        run_i += (P + sc - 1) / sc * tiles_of(lay.N[b]);
         run_f += P + Q;
         run_l += Q;
     }
