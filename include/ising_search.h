@@ -87,8 +87,8 @@ typedef struct {
     int32_t form;              /* ising_form_t */
     int32_t states_per_item;   /* scan tile: frontier states per work item; 0 = chosen by every step
                                   from its work (the largest power of two up to 256 that leaves each
-                                  scan wave 16 items; 64 with the site bound or the learned form) until
-                                  ising_search_autotune replaces it */
+                                  scan wave 16 items; 64 with the site bound or the learned form);
+                                  ising_search_autotune keeps it only if it beats the tuned tiles */
     int32_t topk_factor;       /* learned form: K = topk_factor * N pairs per state (default 8) */
     int32_t persistent;        /* 1 = capture the kernels of one step into a hipGraph once and replay
                                   it for every step (an internal stream is used when none is given) */
@@ -202,11 +202,13 @@ int ising_search_get_stats(ising_search_t *s, ising_stats_t *out);
 
 /*
  * One step (as ising_search_step) that first tunes the pair scan: for every
- * distinct N among the instances it times the scan for 16, 32, 64 and 128
+ * distinct N among the instances it times the scan for 16, 32, 64, 128 and 256
  * frontier states per work item on this step's frontier (coordinate descent
- * over the N buckets) and keeps the fastest.  Results do not depend on the
- * choice; only the time does.  Best called once the frontier is full (after
- * the first step).
+ * over the N buckets) and keeps the fastest; when the configuration leaves the
+ * states per item to the steps (states_per_item 0), the tuned tiles are then
+ * timed against that per-step choice and the faster is kept.  Results do not
+ * depend on the choice; only the time does.  Best called once the frontier is
+ * full (after the first step).
  */
 int ising_search_autotune(ising_search_t *s, int32_t *n_active);
 

@@ -74,6 +74,7 @@ struct ising_search {
     // states per scan item, per instance (host copy of lay.scb)
     std::vector<int> sc_h;
     int* d_scb = nullptr;
+    bool sc_auto_ok = false;   // the configuration lets each step choose its states per item
     // persistent mode: one step captured into a graph
     bool persistent = false;
     hipStream_t own_stream = nullptr;
@@ -427,6 +428,7 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     // states per scan item chosen each step unless given, tuned, or the scan
     // serves only the states the site bound leaves (or ranked ones)
     lay.sc_auto = (cfg->states_per_item == 0 && !sb && cfg->form != ISING_FORM_LEARNED) ? 1 : 0;
+    hd->sc_auto_ok = lay.sc_auto != 0;
     lay.J16 = dJ16;
     lay.rmax4 = drm;
     lay.mlp = hd->d_mlp;
@@ -771,7 +773,8 @@ extern "C" int ising_search_autotune(ising_search_t* s, int32_t* n_active)
     if (rc != ISING_OK) return rc;
     if (s->lay.form == ISING_FORM_LEARNED && !s->scorer_set)
         return fail(ISING_ERR_BAD_STATE, "the learned form needs ising_search_set_scorer before stepping");
-    // tuned tiles replace the per-step choice (and any step captured with it)
+    // tuned tiles are timed against the per-step choice; the captured step
+    // holds the choice by value
     if (s->lay.sc_auto) {
         s->lay.sc_auto = 0;
         drop_graph(s);
@@ -783,7 +786,7 @@ extern "C" int ising_search_autotune(ising_search_t* s, int32_t* n_active)
         if (e0) (void)hipEventDestroy(e0);
         return fail(ISING_ERR_HIP, "hipEventCreate failed");
     }
-    static const int cand[] = {16, 32, 64, 128};
+    static const int cand[] = {16, 32, 64, 128, 256};
     std::vector<int> sizes(s->N);
     std::sort(sizes.begin(), sizes.end());
     sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
@@ -817,6 +820,16 @@ extern "C" int ising_search_autotune(ising_search_t* s, int32_t* n_active)
         }
         for (int b = 0; b < lay.B; ++b)
             if (s->N[b] == sizes[k]) s->sc_h[b] = best;
+    }
+    // the per-step choice competes with the tuned tiles on this step's frontier
+    if (e == hipSuccess && s->sc_auto_ok) {
+        float ms_t = 0.f, ms_a = 0.f;
+        e = scan_ms(ms_t, false);
+        if (e == hipSuccess) {
+            s->lay.sc_auto = 1;
+            e = scan_ms(ms_a, false);
+        }
+        if (e == hipSuccess && !(ms_a < ms_t)) s->lay.sc_auto = 0;
     }
     // the step itself with the chosen tiles
     float ms = 0.f;
