@@ -241,7 +241,8 @@ def test_autotune_keeps_results_and_picks_candidates():
     a.step()
     t.autotune()
     tiles = t.tuning()
-    assert all(x in (16, 32, 64, 128) for x in tiles)
+    # tuned per N, or the per-step choice (one power of two for all) if faster
+    assert all(x in (16, 32, 64, 128, 256) for x in tiles)
     assert tiles[0] == tiles[2]   # same N, same choice
     a.run()
     t.run()
@@ -249,6 +250,39 @@ def test_autotune_keeps_results_and_picks_candidates():
         assert_same_set(t.get_search(sid), a.get_search(sid), f"autotuned search {sid}")
     a.destroy()
     t.destroy()
+
+
+@pytest.mark.parametrize("form,flags", [(binding.FORM_PLAIN, 0), (binding.FORM_SPLIT_BF16, 0),
+                                        (binding.FORM_SPLIT_BF16, binding.FLAG_FP16_SCAN)])
+def test_states_per_item_chosen_per_step(form, flags):
+    """With states_per_item 0 every step picks a power of two in [16, 256] from
+    its work; the kept sets match those of a fixed 64 step by step."""
+    # enough work that a full frontier leaves every scan wave 16 items of 32 states
+    w = wl.custom([600] * 40 + [300] * 8, L=32, M=60, config=27)
+    note(f"[states per item] form={form} flags={flags}")
+    a = binding.IsingSearch.from_workload(w, states_per_item=64, form=form, flags=flags)
+    c = binding.IsingSearch.from_workload(w, form=form, flags=flags)
+    seen = set()
+    for t in range(600):
+        na = a.step()
+        nc = c.step()
+        assert na == nc, f"step {t + 1}: active {na} vs {nc}"
+        tiles = c.tuning()
+        assert len(set(tiles)) == 1 and tiles[0] in (16, 32, 64, 128, 256), tiles
+        seen.add(tiles[0])
+        if t % 25 == 0:
+            for sid in range(0, a.B * a.L, 97):
+                assert_same_set(c.get_search(sid), a.get_search(sid), f"search {sid} step {t + 1}")
+        if na == 0:
+            break
+    assert na == 0
+    assert max(seen) > 16 and min(seen) < max(seen), seen   # the choice follows the work
+    for b in range(a.B):
+        ab, aE = a.get_states(b)
+        cb, cE = c.get_states(b)
+        assert np.array_equal(ab, cb) and np.array_equal(aE, cE), f"instance {b}"
+    a.destroy()
+    c.destroy()
 
 
 def test_uneven_batch_persistent_sampled():
