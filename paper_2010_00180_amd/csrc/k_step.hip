@@ -454,11 +454,11 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
     }
     // pool: sort a prefix by energy, drop duplicates, take the M-th distinct
     // (a prefix with fewer than M distinct states is widened; the pilots of a
-    // search share many children, so the first prefix holds 4M + 64)
+    // search share many children, so the first prefix holds 3M + 64)
     const int npool = np * nc;
     double theta = INFINITY;
     int seen = 0;
-    for (int need = 4 * M + 64 < npool ? 4 * M + 64 : npool;; need = 2 * need < npool ? 2 * need : npool) {
+    for (int need = 3 * M + 64 < npool ? 3 * M + 64 : npool;; need = 2 * need < npool ? 2 * need : npool) {
     const int cnt = sort_prefix([&](int k, double& v, uint32_t& id) {
         v = pE[k];
         id = pid[k];
