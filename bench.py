@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "pair-flip ΔE evals/s + time-to-solution/instance at N=600,M=120 vs plain"
 # MI355X vector peaks as lane-operations per second (an FMA counted once):
 # FP64 78.6 TFLOP/s = 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 flops;
-# FP32 157.3 TFLOP/s, twice that (it needs packed FP32, which this build does
+# FP32 157.3 TFLOP/s, twice that (it needs packed FP32, which these kernels do
 # not use, so the FP32 scan can reach half of its peak).
 VALU_LANE_OPS_PER_S = {"f64": 256 * 4 * 16 * 2.4e9, "f32": 2 * 256 * 4 * 16 * 2.4e9,
                        # packed FP16: two halves per lane and cycle from the same unit counts

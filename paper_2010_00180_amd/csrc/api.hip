@@ -192,7 +192,7 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     if (!cfg) return fail(ISING_ERR_INVALID_ARG, "cfg is NULL");
     if (cfg->M < 1 || cfg->M > 1024) return fail(ISING_ERR_INVALID_ARG, "M=%d outside [1, 1024]", cfg->M);
     if (cfg->form != ISING_FORM_PLAIN && cfg->form != ISING_FORM_SPLIT_BF16 && cfg->form != ISING_FORM_LEARNED)
-        return fail(ISING_ERR_INVALID_ARG, "form %d is not available in this build", cfg->form);
+        return fail(ISING_ERR_INVALID_ARG, "form %d is unknown (0 plain, 1 split-bf16, 2 learned)", cfg->form);
     if (cfg->flags & ~(ISING_FLAG_RECORD_PROPOSALS | ISING_FLAG_SITE_BOUND | ISING_FLAG_FP16_SCAN))
         return fail(ISING_ERR_INVALID_ARG, "unknown flag bits 0x%x", cfg->flags);
     if ((cfg->flags & ISING_FLAG_FP16_SCAN) && cfg->form != ISING_FORM_SPLIT_BF16)
