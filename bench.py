@@ -330,6 +330,8 @@ def measure(binding, torch, w, form, steps, warmup, batching, copy_gib):
         "survivors": d["survivors"], "retries": d["retries"], "fallbacks": d["fallbacks"],
         "split_field_err": st1.get("split_field_err"),
         "scan_states_per_item": sorted(set(zip([i.N for i in w.instances], tiles))),
+        "scan_states_per_item_note": "those of the last step: unless fixed or tuned, every step "
+                                     "chooses a power of two in [16, 256] from its work",
         "bounded_states": d.get("bounded_states", 0),
         "expanded_states": d["frontier_states"],
         "roofline": roofline,
@@ -450,6 +452,7 @@ def main():
         "survivors": head["survivors"],
         "retries": head["retries"],
         "scan_states_per_item": head["scan_states_per_item"],
+        "scan_states_per_item_note": head["scan_states_per_item_note"],
         "roofline": roof,
         "forms": {f: {k: v for k, v in r.items() if k not in ("E1", "wall", "pairs")} for f, r in results.items()},
         "forms_same_E1": all(r["E1"] == head["E1"] for r in results.values()),
