@@ -1612,11 +1612,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // ------------------------------------------------------------------ k_fupdate
 // Local fields of the states that entered in the last merge (row a6):
 // F_k = F_k(parent) - 2 s_i J_ik - 2 s_j J_jk with the parent's spins.  One
-// wave per new state, lanes over sites; grid (search, group of 4 states).
+// wave per new state, lanes over sites; blocks of 4 states, search-major, so
+// that the blocks of one instance run together and its coupling rows stay in
+// L2 while its new states use them.
 __global__ __launch_bounds__(256) void k_fupdate(Layout lay, const double* __restrict__ J4)
 {
-    const int s = blockIdx.x;
-    const int m = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int groups = (lay.M + 3) / 4;
+    const int s = (int)(blockIdx.x / groups);
+    const int m = (int)(blockIdx.x % groups) * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (m >= lay.nm_count[s]) return;
     const int b = s / lay.L;
@@ -1862,7 +1865,7 @@ hipError_t launch_merge(const Layout& lay, hipStream_t st)
 
 hipError_t launch_fupdate(const Layout& lay, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_fupdate, dim3(lay.S, (lay.M + 3) / 4), dim3(256), 0, st, lay, lay.J4);
+    hipLaunchKernelGGL(k_fupdate, dim3(lay.S * ((lay.M + 3) / 4)), dim3(256), 0, st, lay, lay.J4);
     return hipGetLastError();
 }
 
