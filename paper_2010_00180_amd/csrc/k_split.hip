@@ -324,7 +324,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                                                const long long* __restrict__ iprefix)
 {
     __shared__ Surv stage[STAGE];
-    __shared__ float abuf[2][T32];
+    __shared__ float abuf[T32];   // a_j of the current state
     __shared__ double sT[64], sE[64];
     __shared__ int sS[64], sCode[64];
     __shared__ uint64_t sWi[64], sWj[64];
@@ -426,8 +426,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
             const size_t fe0 = (size_t)uniform_u32(sFe[0]) * Npm;
             float nrr = RR32[fe0 + row];
             float naj = A32[fe0 + col0 + lane];
-            int cur = 0;
-            abuf[0][lane] = naj;
+            abuf[lane] = naj;
             __syncthreads();
             for (int k = 0; k < ns; ++k) {
                 const float rrt = nrr;
@@ -449,7 +448,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     const uint64_t wj = uniform_u64(sWj[k]);
                     const uint64_t dw = wj ^ prev_wj;
                     prev_wj = wj;
-                    const float* aj = abuf[cur];
+                    const float* aj = abuf;
                     float a8n[8];   // the next group's a_j, read one group ahead
 #pragma unroll
                     for (int u = 0; u < 8; ++u) a8n[u] = aj[u];
@@ -495,8 +494,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                         }
                     }
                 }
-                if (k + 1 < ns) abuf[cur ^ 1][lane] = naj;
-                cur ^= 1;
+                // one wave: its LDS accesses complete in order, so the next row can
+                // replace this one once its reads are issued
+                if (k + 1 < ns) abuf[lane] = naj;
                 __syncthreads();
             }
             rescore();   // before the next 64 states replace the records
@@ -532,7 +532,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                                                const long long* __restrict__ iprefix)
 {
     __shared__ Surv stage[STAGE];
-    __shared__ uint32_t abuf[2][T16 / 2];   // fl16(a_j) pairs of the current and the next state
+    __shared__ uint32_t abuf[T16 / 2];   // fl16(a_j) pairs of the current state
     __shared__ double sT[64], sE[64];
     __shared__ int sS[64], sCode[64];
     __shared__ uint64_t sWi[64], sWj0[64], sWj1[64];
@@ -658,8 +658,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
             const size_t fe0 = (size_t)uniform_u32(sFe[0]) * Npm;
             _Float16 nrr = RR16[2 * fe0 + row];   // rows of 2 Npmax halves
             uint32_t naj = A0[fe0 + (col0 >> 1) + lane];
-            int cur = 0;
-            abuf[0][lane] = naj;
+            abuf[lane] = naj;
             __syncthreads();
             for (int k = 0; k < ns; ++k) {
                 const _Float16 rr = nrr;
@@ -684,7 +683,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     const uint64_t dw[2] = {wj[0] ^ prev0, wj[1] ^ prev1};
                     prev0 = wj[0];
                     prev1 = wj[1];
-                    const uint32_t* aj = abuf[cur];
+                    const uint32_t* aj = abuf;
                     uint32_t a8n[8];   // the next group's a_j pairs, read one group ahead
 #pragma unroll
                     for (int u = 0; u < 8; ++u) a8n[u] = aj[u];
@@ -764,8 +763,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                         }
                     }
                 }
-                if (k + 1 < ns) abuf[cur ^ 1][lane] = naj;
-                cur ^= 1;
+                // one wave: its LDS accesses complete in order, so the next row can
+                // replace this one once its reads are issued
+                if (k + 1 < ns) abuf[lane] = naj;
                 __syncthreads();
             }
             rescore();   // before the next 64 states replace the records

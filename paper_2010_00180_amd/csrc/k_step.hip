@@ -769,8 +769,9 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
 // loop is one v_fma_f64 and one v_min_f64 per pair and one compare per group;
 // a group whose minimum passes runs the exact pass that records survivors.
 // Pairs outside the triangle or the instance hold NaN, which fmin ignores and
-// no compare passes.  a_j is wave-uniform and read from a per-wave LDS double
-// buffer filled one state ahead; the next state's record, words and a_i are
+// no compare passes.  a_j is wave-uniform and read from a per-wave LDS row
+// that the next state's row replaces once the current one's reads are issued
+// (one wave's LDS accesses complete in order); the next state's record, words and a_i are
 // loaded while the current state is scanned.  Survivors are staged in LDS and
 // appended to the search's buffer with one atomic per flush.
 __device__ inline void flush_stage(const Layout& lay, Surv* stage, int& n, int s)
@@ -794,7 +795,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                                              const uint64_t* __restrict__ fbits)
 {
     __shared__ Surv stage[STAGE];
-    __shared__ double abuf[2][TCOL];   // a_j of the current and the next state
+    __shared__ double abuf[TCOL];   // a_j of the current state
     // per-state data of up to 64 states of the chunk, staged once per item
     __shared__ double sT[64], sE[64];
     __shared__ int sS[64], sCode[64];
@@ -867,8 +868,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
             const double* A0 = Abuf + sFe[0] * Npm;   // a values of state g0
             double nai = A0[row];
             double naj = lane < TCOL ? A0[col0 + lane] : 0.0;
-            int cur = 0;
-            if (lane < TCOL) abuf[0][lane] = naj;
+            if (lane < TCOL) abuf[lane] = naj;
             __syncthreads();
             for (int k = 0; k < ns; ++k) {
                 const double ai = nai;
@@ -892,7 +892,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     const uint32_t dw = wj ^ prev_wj;
                     prev_wj = wj;
                     const int code = sCode[k];
-                    const double* aj = abuf[cur];
+                    const double* aj = abuf;
 #pragma unroll
                     for (int g = 0; g < TCOL; g += 8) {
                         if ((dw >> g) & 0xFFu) {
@@ -940,9 +940,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                         }
                     }
                 }
-                if (k + 1 < ns && lane < TCOL) abuf[cur ^ 1][lane] = naj;
-                cur ^= 1;
-                __syncthreads();   // one wave: an LDS wait before abuf[cur] is read
+                // one wave: its LDS accesses complete in order, so the next row can
+                // replace this one once its reads are issued
+                if (k + 1 < ns && lane < TCOL) abuf[lane] = naj;
+                __syncthreads();
             }
         }
         flush_stage(lay, stage, nstage, sstage);
