@@ -326,9 +326,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     __shared__ Surv stage[STAGE];
     __shared__ float abuf[T32];   // a_j of the current state
     __shared__ double sT[64], sE[64];
-    __shared__ int sS[64], sCode[64];
-    __shared__ uint64_t sWi[64], sWj[64];
-    __shared__ uint32_t sFe[64];   // entry index: below 2^32, as the FP64 rows of every entry fit in memory
+    __shared__ int sCode[64];
+    // per state, what the loop over states reads: one address for all of it
+    struct StRec {
+        uint64_t wi, wj;   // words of the tile's rows and columns
+        uint32_t s;        // search
+        uint32_t fe;       // entry index: below 2^32, as the FP64 rows of every entry fit in memory
+    };
+    __shared__ StRec srec[64];
     constexpr int PEND = 640;
     __shared__ uint32_t pend[PEND];   // admitted pairs awaiting the FP64 re-score: k << 12 | row << 6 | col
     const uint32_t lane = lane_id32();
@@ -387,8 +392,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     const int prow = bi * TILE + rl, pcol = col0 + cl;
                     const int cd = sCode[k];
                     const double* Frow = Fpool + (size_t)cd * lay.Npmax;
-                    const double sid = ((sWi[k] >> rl) & 1ull) ? -1.0 : 1.0;
-                    const double sj = ((sWj[k] >> cl) & 1ull) ? -1.0 : 1.0;
+                    const double sid = ((srec[k].wi >> rl) & 1ull) ? -1.0 : 1.0;
+                    const double sj = ((srec[k].wj >> cl) & 1ull) ? -1.0 : 1.0;
                     const double ai = -2.0 * sid * Frow[prow];
                     const double x = -2.0 * sj * Frow[pcol] + sid * sj * J4[lay.joff[b] + (size_t)prow * Np + pcol];
                     keep = ai + x <= sT[k];
@@ -415,15 +420,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 const FrRec rc = recs[fe];
                 sT[lane] = rc.T;
                 sE[lane] = rc.E;
-                sS[lane] = rc.s;
                 sCode[lane] = rc.code;
-                sFe[lane] = (uint32_t)fe;
                 const uint64_t* fw = fbits + fe * Wm;
-                sWi[lane] = fw[bi];
-                sWj[lane] = fw[bj];
+                StRec sr;
+                sr.wi = fw[bi];
+                sr.wj = fw[bj];
+                sr.s = (uint32_t)rc.s;
+                sr.fe = (uint32_t)fe;
+                srec[lane] = sr;
             }
             __syncthreads();
-            const size_t fe0 = (size_t)uniform_u32(sFe[0]) * Npm;
+            const size_t fe0 = (size_t)uniform_u32(srec[0].fe) * Npm;
             float nrr = RR32[fe0 + row];
             float naj = A32[fe0 + col0 + lane];
             abuf[lane] = naj;
@@ -431,11 +438,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
             for (int k = 0; k < ns; ++k) {
                 const float rrt = nrr;
                 if (k + 1 < ns) {
-                    const size_t fn = (size_t)uniform_u32(sFe[k + 1]) * Npm;
+                    const size_t fn = (size_t)uniform_u32(srec[k + 1].fe) * Npm;
                     nrr = RR32[fn + row];
                     naj = A32[fn + col0 + lane];
                 }
-                const int s = __builtin_amdgcn_readfirstlane(sS[k]);
+                const StRec cur = srec[k];
+                const int s = (int)uniform_u32(cur.s);
                 const bool skip = retry_mode && !lay.retry[s];
                 if (!skip) {
                     if (s != sstage) {
@@ -444,8 +452,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                         sstage = s;
                     }
                     // the row bits of the state are the lane mask of the negative s_i
-                    const float si = __builtin_amdgcn_inverse_ballot_w64(uniform_u64(sWi[k])) ? -1.f : 1.f;
-                    const uint64_t wj = uniform_u64(sWj[k]);
+                    const float si = __builtin_amdgcn_inverse_ballot_w64(uniform_u64(cur.wi)) ? -1.f : 1.f;
+                    const uint64_t wj = uniform_u64(cur.wj);
                     const uint64_t dw = wj ^ prev_wj;
                     prev_wj = wj;
                     const float* aj = abuf;
@@ -534,9 +542,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     __shared__ Surv stage[STAGE];
     __shared__ uint32_t abuf[T16 / 2];   // fl16(a_j) pairs of the current state
     __shared__ double sT[64], sE[64];
-    __shared__ int sS[64], sCode[64];
-    __shared__ uint64_t sWi[64], sWj0[64], sWj1[64];
-    __shared__ uint32_t sFe[64];   // entry index: below 2^32, as the FP64 rows of every entry fit in memory
+    __shared__ int sCode[64];
+    // per state, what the loop over states reads: one address for all of it
+    struct StRec {
+        uint64_t wi, wj0, wj1;   // words of the tile's rows and columns
+        uint32_t s;              // search
+        uint32_t fe;             // entry index: below 2^32, as the FP64 rows of every entry fit in memory
+    };
+    __shared__ StRec srec[64];
     constexpr int PEND = 512;
     __shared__ uint32_t pend[PEND];   // admitted pairs awaiting the FP64 re-score: k << 13 | row << 7 | col
     const uint32_t lane = lane_id32();
@@ -614,8 +627,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     const int prow = bi * TILE + rl, pcol = col0 + cl;
                     const int cd = sCode[k];
                     const double* Frow = Fpool + (size_t)cd * lay.Npmax;
-                    const double sid = ((sWi[k] >> rl) & 1ull) ? -1.0 : 1.0;
-                    const uint64_t wj = cl < 64 ? sWj0[k] : sWj1[k];
+                    const double sid = ((srec[k].wi >> rl) & 1ull) ? -1.0 : 1.0;
+                    const uint64_t wj = cl < 64 ? srec[k].wj0 : srec[k].wj1;
                     const double sj = ((wj >> (cl & 63)) & 1ull) ? -1.0 : 1.0;
                     const double ai = -2.0 * sid * Frow[prow];
                     const double x = -2.0 * sj * Frow[pcol] + sid * sj * J4[lay.joff[b] + (size_t)prow * Np + pcol];
@@ -643,19 +656,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 const FrRec rc = recs[fe];
                 sT[lane] = rc.T;
                 sE[lane] = rc.E;
-                sS[lane] = rc.s;
                 sCode[lane] = rc.code;
-                sFe[lane] = (uint32_t)fe;
                 const uint64_t* fw = fbits + fe * Wm;
-                sWi[lane] = fw[bi];
-                sWj0[lane] = fw[w0];
-                sWj1[lane] = w1 >= 0 ? fw[w1] : 0ull;
+                StRec sr;
+                sr.wi = fw[bi];
+                sr.wj0 = fw[w0];
+                sr.wj1 = w1 >= 0 ? fw[w1] : 0ull;
+                sr.s = (uint32_t)rc.s;
+                sr.fe = (uint32_t)fe;
+                srec[lane] = sr;
             }
             __syncthreads();
             // a row of state k: 2 Npmax halves per entry; the tile reads halves
             // col0 .. col0+127 < Np + 64 <= 2 Npmax
             const uint32_t* A0 = reinterpret_cast<const uint32_t*>(A16);
-            const size_t fe0 = (size_t)uniform_u32(sFe[0]) * Npm;
+            const size_t fe0 = (size_t)uniform_u32(srec[0].fe) * Npm;
             _Float16 nrr = RR16[2 * fe0 + row];   // rows of 2 Npmax halves
             uint32_t naj = A0[fe0 + (col0 >> 1) + lane];
             abuf[lane] = naj;
@@ -663,11 +678,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
             for (int k = 0; k < ns; ++k) {
                 const _Float16 rr = nrr;
                 if (k + 1 < ns) {
-                    const size_t fn = (size_t)uniform_u32(sFe[k + 1]) * Npm;
+                    const size_t fn = (size_t)uniform_u32(srec[k + 1].fe) * Npm;
                     nrr = RR16[2 * fn + row];
                     naj = A0[fn + (col0 >> 1) + lane];
                 }
-                const int s = __builtin_amdgcn_readfirstlane(sS[k]);
+                const StRec cur = srec[k];
+                const int s = (int)uniform_u32(cur.s);
                 const bool skip = retry_mode && !lay.retry[s];
                 if (!skip) {
                     if (s != sstage) {
@@ -678,8 +694,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     // s_i for both halves (-1 or +1 in FP16): the row bits of the state
                     // are the lane mask of the negative ones
                     const h2v si2 = __builtin_bit_cast(
-                        h2v, __builtin_amdgcn_inverse_ballot_w64(uniform_u64(sWi[k])) ? 0xBC00BC00u : 0x3C003C00u);
-                    const uint64_t wj[2] = {uniform_u64(sWj0[k]), uniform_u64(sWj1[k])};
+                        h2v, __builtin_amdgcn_inverse_ballot_w64(uniform_u64(cur.wi)) ? 0xBC00BC00u : 0x3C003C00u);
+                    const uint64_t wj[2] = {uniform_u64(cur.wj0), uniform_u64(cur.wj1)};
                     const uint64_t dw[2] = {wj[0] ^ prev0, wj[1] ^ prev1};
                     prev0 = wj[0];
                     prev1 = wj[1];
