@@ -797,11 +797,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     __shared__ Surv stage[STAGE];
     __shared__ double abuf[TCOL];   // a_j of the current state
     // per-state data of up to 64 states of the chunk, staged once per item
-    __shared__ double sT[64], sE[64];
-    __shared__ int sS[64], sCode[64];
-    __shared__ uint32_t sWj[64];
-    __shared__ uint64_t sWi[64];
-    __shared__ size_t sFe[64];
+    // per state, what the loop over states reads: one address for all of it
+    struct StRec {
+        double T, E;       // threshold and energy
+        uint64_t wi;       // word of the tile's rows
+        uint32_t wj;       // the tile's 32 columns of their word
+        int s, code;       // search, pool slot of the state
+        uint32_t fe;       // entry index: below 2^32, as the FP64 rows of every entry fit in memory
+    };
+    __shared__ StRec srec[64];
     const uint32_t lane = lane_id();
     const long long total = lay.item_prefix[lay.B];
     const int retry_mode = lay.flags[FLAG_RETRY_MODE];
@@ -855,17 +859,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
             if ((int)lane < ns) {
                 const size_t fe = fb + (lay.sb ? lay.full_list[fb + g0 + lane] : g0 + (int)lane);
                 const FrRec rc = recs[fe];
-                sT[lane] = rc.T;
-                sE[lane] = rc.E;
-                sS[lane] = rc.s;
-                sCode[lane] = rc.code;
-                sFe[lane] = fe;
                 const uint64_t* fw = fbits + fe * Wm;
-                sWi[lane] = fw[wrow];
-                sWj[lane] = (uint32_t)(fw[wcol] >> shcol);
+                StRec sr;
+                sr.T = rc.T;
+                sr.E = rc.E;
+                sr.wi = fw[wrow];
+                sr.wj = (uint32_t)(fw[wcol] >> shcol);
+                sr.s = rc.s;
+                sr.code = rc.code;
+                sr.fe = (uint32_t)fe;
+                srec[lane] = sr;
             }
             __syncthreads();
-            const double* A0 = Abuf + sFe[0] * Npm;   // a values of state g0
+            const double* A0 = Abuf + (size_t)(uint32_t)uniform_int((int)srec[0].fe) * Npm;   // a values of state g0
             double nai = A0[row];
             double naj = lane < TCOL ? A0[col0 + lane] : 0.0;
             if (lane < TCOL) abuf[lane] = naj;
@@ -873,25 +879,29 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
             for (int k = 0; k < ns; ++k) {
                 const double ai = nai;
                 if (k + 1 < ns) {
-                    const double* An = Abuf + sFe[k + 1] * Npm;
+                    const double* An = Abuf + (size_t)(uint32_t)uniform_int((int)srec[k + 1].fe) * Npm;
                     nai = An[row];
                     if (lane < TCOL) naj = An[col0 + lane];
                 }
-                const int s = uniform_int(sS[k]);
+                const StRec cur = srec[k];
+                const int s = uniform_int(cur.s);
                 const bool skip = retry_mode && !lay.retry[s];
                 if (!skip) {
                     if (s != sstage) {
                         flush_stage(lay, stage, nstage, sstage);
                         sstage = s;
                     }
-                    const double Tm = sT[k];
-                    const double Ea = sE[k] + ai;
+                    const double Tm = cur.T;
+                    const double Ea = cur.E + ai;
                     const double rr = row < N ? Tm - ai : -INFINITY;
-                    const double si = ((sWi[k] >> lane) & 1ull) ? -1.0 : 1.0;
-                    const uint32_t wj = (uint32_t)uniform_int((int)sWj[k]);
+                    // the row bits of the state are the lane mask of the negative s_i
+                    const double si = __builtin_amdgcn_inverse_ballot_w64(
+                        ((uint64_t)(uint32_t)uniform_int((int)(cur.wi >> 32)) << 32) |
+                        (uint32_t)uniform_int((int)(uint32_t)cur.wi)) ? -1.0 : 1.0;
+                    const uint32_t wj = (uint32_t)uniform_int((int)cur.wj);
                     const uint32_t dw = wj ^ prev_wj;
                     prev_wj = wj;
-                    const int code = sCode[k];
+                    const int code = cur.code;
                     const double* aj = abuf;
 #pragma unroll
                     for (int g = 0; g < TCOL; g += 8) {
