@@ -128,17 +128,19 @@ __device__ inline int find_inst(const long long* prefix, int B, long long e)
     return lo;
 }
 
-// x rounded up to the next FP16 value at or above it
-__device__ inline _Float16 half_up(float x)
+// An FP16 value at or above x that has no FP16 value between it and x (the
+// smallest one, except that a result of zero is +0).  The hardware conversions
+// to FP32 (to nearest) and on to FP16 (toward zero) land on one of the two FP16
+// values around x, as both are FP32 values and each rounding stays between
+// them; the one below x is moved up a step.  The same value as rounding up to
+// FP32 and then up to FP16, as every FP16 value is an FP32 value.
+__device__ inline _Float16 half_up(double x)
 {
-    _Float16 h = (_Float16)x;
-    if ((float)h < x) {
-        uint16_t u = __builtin_bit_cast(uint16_t, h);
-        u = (u & 0x8000u) ? (uint16_t)(u - 1u) : (uint16_t)(u + 1u);
-        if (u == 0x8000u) u = 0;   // from the smallest negative subnormal up to zero
-        h = __builtin_bit_cast(_Float16, u);
-    }
-    return h;
+    const float xf = (float)x;
+    uint32_t u = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(xf, xf)) & 0xFFFFu;
+    if ((double)__builtin_bit_cast(_Float16, (uint16_t)u) < x) u = (u & 0x8000u) ? u - 1u : u + 1u;
+    if (u == 0x8000u) u = 0;   // -0 as +0: an admission test reads the sign of RR_i - x
+    return __builtin_bit_cast(_Float16, (uint16_t)u);
 }
 
 template <bool SB, bool H16>
@@ -247,9 +249,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                     const double av = i < N ? (from_ft ? -2.0 * sp * (double)Ftv[r] : a) : 0.0;
                     if (H16) A16[i] = i < N ? (_Float16)av : (_Float16)INFINITY;   // padding: no pair can pass
                     else A32[i] = (float)av;
-                    const float rr = i < N ? __double2float_ru(T - a + delta) : -INFINITY;
-                    if (H16) reinterpret_cast<_Float16*>(RR)[i] = half_up(rr);   // rounded up once more, to FP16
-                    else RR[i] = rr;
+                    if (H16) reinterpret_cast<_Float16*>(RR)[i] = i < N ? half_up(T - a + delta) : (_Float16)-INFINITY;
+                    else RR[i] = i < N ? __double2float_ru(T - a + delta) : -INFINITY;
                     nhit += __builtin_popcountll(__builtin_amdgcn_ballot_w64(i < N && Em + a <= c));
                 }
             }
