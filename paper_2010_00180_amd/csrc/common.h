@@ -23,7 +23,6 @@ namespace qi {
 constexpr int TILE = 64;            // rows of one J tile (one row per lane)
 constexpr int TCOL = 32;            // columns of one J tile held in registers
 constexpr int MAX_N = 4096;         // pair indices are packed into 16 bits
-constexpr int PILOT_K = 48;         // lightest sites used for the per-search pilot cut
 constexpr int MERGE_CH = 2048;      // candidates sorted per merge pass (LDS)
 constexpr int STAGE = 256;          // wave-private survivor staging (records)
 constexpr uint32_t SINGLE = 0xFFFFu;   // j field of a single-flip record
