@@ -217,25 +217,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                     (from_ft ? 2.0 * lay.ebf[b] : 0.0);
         }
         _Float16* A16 = reinterpret_cast<_Float16*>(A32);
-        // rounds of PREP_CH blocks of 64 sites: the loads of a round are issued
-        // together, so that the wave waits on memory once per round
-        for (int i0 = 0; i0 < Np; i0 += 64 * PREP_CH) {
+        // rounds of CH blocks of 64 sites: the loads of a round are issued
+        // together, so that the wave waits on memory once per round.  The FP16
+        // rows take shorter rounds: its fewer registers let more waves share a
+        // SIMD, which hides more of the latency than the longer rounds save
+        constexpr int CH = (H16 && !SB) ? 6 : PREP_CH;
+        for (int i0 = 0; i0 < Np; i0 += 64 * CH) {
             // blocks past Np load the last block again (unused), so that every
             // load is unconditional and in bounds
-            double Fv[PREP_CH];
-            float Ftv[PREP_CH];
+            double Fv[CH];
+            float Ftv[CH];
 #pragma unroll
-            for (int r = 0; r < PREP_CH; ++r) Fv[r] = F[min(i0 + 64 * r, Np - 64) + (int)lane];
+            for (int r = 0; r < CH; ++r) Fv[r] = F[min(i0 + 64 * r, Np - 64) + (int)lane];
             if (from_ft) {
 #pragma unroll
-                for (int r = 0; r < PREP_CH; ++r) Ftv[r] = Ft[min(i0 + 64 * r, Np - 64) + (int)lane];
+                for (int r = 0; r < CH; ++r) Ftv[r] = Ft[min(i0 + 64 * r, Np - 64) + (int)lane];
             }
             // a_i and the thresholds; the single flips below the cut are counted,
             // so that one atomic reserves their places for the round
-            double ar[PREP_CH];
+            double ar[CH];
             int nhit = 0;
 #pragma unroll
-            for (int r = 0; r < PREP_CH; ++r) {
+            for (int r = 0; r < CH; ++r) {
                 const int ib = i0 + 64 * r;
                 ar[r] = 0.0;
                 if (ib < Np) {
@@ -254,7 +257,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                     nhit += __builtin_popcountll(__builtin_amdgcn_ballot_w64(i < N && Em + a <= c));
                 }
             }
-            if (H16 && i0 + 64 * PREP_CH >= Np) {
+            if (H16 && i0 + 64 * CH >= Np) {
                 // the FP16 scan reads whole 128-column tiles: +inf past Np as well
                 for (int i = Np + (int)lane; i < ((Np + 127) & ~127); i += 64) A16[i] = (_Float16)INFINITY;
             }
@@ -263,7 +266,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 if (lane == 0) base = atomicAdd(&lay.surv_count[s], nhit);
                 base = __shfl(base, 0, 64);
 #pragma unroll
-                for (int r = 0; r < PREP_CH; ++r) {
+                for (int r = 0; r < CH; ++r) {
                     const int i = i0 + 64 * r + (int)lane;
                     const double Ec = Em + ar[r];
                     const bool hit = i < N && Ec <= c;
