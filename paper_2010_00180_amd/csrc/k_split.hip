@@ -218,10 +218,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         }
         _Float16* A16 = reinterpret_cast<_Float16*>(A32);
         // rounds of CH blocks of 64 sites: the loads of a round are issued
-        // together, so that the wave waits on memory once per round.  The FP16
-        // rows take shorter rounds: its fewer registers let more waves share a
-        // SIMD, which hides more of the latency than the longer rounds save
-        constexpr int CH = (H16 && !SB) ? 6 : PREP_CH;
+        // together, so that the wave waits on memory once per round.  Without
+        // the site bound the rounds are shorter: their fewer registers let more
+        // waves share a SIMD, which hides more of the latency than longer
+        // rounds save
+        constexpr int CH = SB ? PREP_CH : 6;
         for (int i0 = 0; i0 < Np; i0 += 64 * CH) {
             // blocks past Np load the last block again (unused), so that every
             // load is unconditional and in bounds
