@@ -303,6 +303,22 @@ int ising_mlp_forward(const float *params, const float *feat, int64_t n, float *
 int ising_mlp_loss_grad(const float *params, const float *feat, const uint8_t *label, int64_t n,
                         float pos_weight, float *grad, float *loss, void *workspace,
                         int64_t workspace_bytes, void *stream);
+/*
+ * ising_mlp_loss_grad without a workspace argument and without any device
+ * allocation, for callers that cannot allocate (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc).  Same loss, gradient and
+ * pointer rules as ising_mlp_loss_grad; the per-block partial sums go to a
+ * static device array of 256 rows (4,654,080 bytes per device, held until the
+ * process ends), so the samples are spread over at most 256 blocks: for
+ * n <= 16384 the result is bit-identical to ising_mlp_loss_grad, beyond that
+ * it differs only in the FP32 summation order.  Every n >= 1 is accepted.
+ * The array is shared by all calls on one device: calls that overlap on one
+ * device (different streams or threads) race and must be serialised by the
+ * caller.  `stream` must belong to the current device.  Errors: INVALID_ARG,
+ * NO_DEVICE, HIP.
+ */
+int ising_mlp_loss_grad_noalloc(const float *params, const float *feat, const uint8_t *label, int64_t n,
+                                float pos_weight, float *grad, float *loss, void *stream);
 /* One Adam step (t >= 1): m, v and params updated in place (Kingma and Ba, Alg. 1). */
 int ising_mlp_adam(float *params, float *m, float *v, const float *grad, int32_t t, float lr,
                    float beta1, float beta2, float eps, void *stream);

@@ -60,6 +60,7 @@ EXPORTED = (
     "ising_mlp_loss_grad",
     "ising_mlp_adam",
     "ising_mlp_train",
+    "ising_mlp_loss_grad_noalloc",
 )
 
 
@@ -167,6 +168,8 @@ def load(path: str = LIB_PATH):
     L.ising_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
     L.ising_mlp_loss_grad.restype = ctypes.c_int
     L.ising_mlp_loss_grad.argtypes = [vp, vp, vp, i64, f32, vp, vp, vp, i64, vp]
+    L.ising_mlp_loss_grad_noalloc.restype = ctypes.c_int
+    L.ising_mlp_loss_grad_noalloc.argtypes = [vp, vp, vp, i64, f32, vp, vp, vp]
     L.ising_mlp_adam.restype = ctypes.c_int
     L.ising_mlp_adam.argtypes = [vp, vp, vp, vp, i32, f32, f32, f32, f32, vp]
     L.ising_mlp_train.restype = ctypes.c_int
@@ -379,6 +382,11 @@ def mlp_forward(params, feat, n, logits, stream=None):
 def mlp_loss_grad(params, feat, label, n, pos_weight, grad, loss, workspace, workspace_bytes, stream=None):
     _check(load().ising_mlp_loss_grad(_vp(params), _vp(feat), _vp(label), int(n), float(pos_weight), _vp(grad),
                                       _vp(loss), _vp(workspace), int(workspace_bytes), _vp(stream)))
+
+
+def mlp_loss_grad_noalloc(params, feat, label, n, pos_weight, grad, loss, stream=None):
+    _check(load().ising_mlp_loss_grad_noalloc(_vp(params), _vp(feat), _vp(label), int(n), float(pos_weight),
+                                              _vp(grad), _vp(loss), _vp(stream)))
 
 
 def mlp_adam(params, m, v, grad, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

@@ -1307,6 +1307,68 @@ extern "C" int ising_mlp_loss_grad(const float* params, const float* feat, const
     return ISING_OK;
 }
 
+// ------------------------------------------------------------------ gradient without allocation
+// The partial gradients of at most MLP_NOALLOC_GRID blocks live in a
+// file-scope device array (4,654,080 bytes), one copy per device, held until
+// the process ends.  Host code never passes the array's name to a kernel: its
+// device address is looked up once per device with hipGetSymbolAddress and
+// kept in g_scratch_ptr.
+namespace {
+constexpr int MLP_NOALLOC_GRID = 256;
+constexpr size_t MLP_NOALLOC_FLOATS = (size_t)MLP_NOALLOC_GRID * (MLP_NPARAM + 1);
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+static __device__ __align__(256) float scratch[MLP_NOALLOC_FLOATS];
+
+namespace {
+int scratch_for_current_device(float** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ISING_ERR_NO_DEVICE, "hipGetDevice failed");
+    }
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(ISING_ERR_NO_DEVICE, "device %d outside [0, %d)", dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(ISING_ERR_HIP, "hipGetSymbolAddress of the gradient scratch failed: %s", hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = static_cast<float*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return ISING_OK;
+}
+}  // namespace
+
+extern "C" int ising_mlp_loss_grad_noalloc(const float* params, const float* feat, const uint8_t* label, int64_t n,
+                                           float pos_weight, float* grad, float* loss, void* stream)
+{
+    g_err.clear();
+    if (!params || !feat || !label || !grad || n < 1) return fail(ISING_ERR_INVALID_ARG, "NULL pointer or n < 1");
+    if (!(pos_weight > 0.f) || !std::isfinite(pos_weight)) return fail(ISING_ERR_INVALID_ARG, "pos_weight must be > 0");
+    int rc = have_device();
+    if (rc != ISING_OK) return rc;
+    float* partial = nullptr;
+    rc = scratch_for_current_device(&partial);
+    if (rc != ISING_OK) return rc;
+    // at most MLP_NOALLOC_GRID blocks (rows of the scratch); more samples are
+    // spread over them, so no sample count exceeds the scratch
+    const int grid = std::min(mlp_grid_for(n), MLP_NOALLOC_GRID);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // every block writes its whole row of partial sums, so the scratch needs no clearing
+    hipError_t e = launch_mlp_grad(params, feat, label, n, n, 0, -1, pos_weight, partial, grid, st);
+    if (e == hipSuccess) e = launch_mlp_reduce(partial, grid, grad, loss, st);
+    if (e != hipSuccess) return fail(ISING_ERR_HIP, "gradient launch failed: %s", hipGetErrorString(e));
+    return ISING_OK;
+}
+
 extern "C" int ising_mlp_adam(float* params, float* m, float* v, const float* grad, int32_t t, float lr, float beta1,
                               float beta2, float eps, void* stream)
 {

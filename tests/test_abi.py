@@ -152,6 +152,9 @@ def test_training_entry_points_validate_before_touching_memory():
     assert lib.ising_mlp_loss_grad(fake, fake, fake, 0, 1.0, fake, None, fake, ws, None) == E
     assert lib.ising_mlp_loss_grad(fake, fake, fake, 10, 1.0, fake, None, fake, ws - 4, None) == E
     assert lib.ising_mlp_loss_grad(fake, fake, fake, 10, 0.0, fake, None, fake, ws, None) == E
+    assert lib.ising_mlp_loss_grad_noalloc(fake, fake, fake, 0, 1.0, fake, None, None) == E
+    assert lib.ising_mlp_loss_grad_noalloc(fake, fake, None, 10, 1.0, fake, None, None) == E
+    assert lib.ising_mlp_loss_grad_noalloc(fake, fake, fake, 10, 0.0, fake, None, None) == E
     assert lib.ising_mlp_adam(fake, fake, fake, fake, 0, 1e-3, 0.9, 0.999, 1e-8, None) == E
     assert lib.ising_mlp_adam(fake, fake, fake, fake, 1, 1e-3, 1.0, 0.999, 1e-8, None) == E
     assert lib.ising_mlp_train(fake, fake, fake, fake, fake, 10, 0, 1, 0, 1e-3, 1.0, 0, None, fake, ws, None) == E
@@ -172,3 +175,4 @@ def test_training_entry_points_report_no_device():
     ws = lib.ising_mlp_workspace_bytes()
     assert lib.ising_mlp_forward(fake, fake, 4, fake, None) == binding.ISING_ERR_NO_DEVICE
     assert lib.ising_mlp_loss_grad(fake, fake, fake, 10, 1.0, fake, None, fake, ws, None) == binding.ISING_ERR_NO_DEVICE
+    assert lib.ising_mlp_loss_grad_noalloc(fake, fake, fake, 10, 1.0, fake, None, None) == binding.ISING_ERR_NO_DEVICE
