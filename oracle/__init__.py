@@ -58,6 +58,12 @@ def load(path: str):
     L.qo_step_proposed.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int, ctypes.c_int, _u64p, _dp,
                                    ctypes.c_int, _ip, _ip, ctypes.POINTER(ctypes.c_uint32),
                                    _u64p, _dp, _u8p, _ip]
+    L.qo_field_change.restype = ctypes.c_double
+    L.qo_field_change.argtypes = [ctypes.c_int, _dp, _dp, _u64p, ctypes.c_int, _ip]
+    L.qo_step_fields.restype = ctypes.c_int
+    L.qo_step_fields.argtypes = L.qo_step.argtypes
+    L.qo_step_proposed_fields.restype = ctypes.c_int
+    L.qo_step_proposed_fields.argtypes = L.qo_step_proposed.argtypes
     L.qo_num_threads.restype = ctypes.c_int
     L.qo_num_threads.argtypes = []
     return L
@@ -115,8 +121,18 @@ def flip_change(J, h, x, sites) -> float:
     return lib().qo_flip_change(len(h), _d(J), _d(h), _u64(x), len(s), s.ctypes.data_as(_ip))
 
 
-def step(J, h, M, bits, E=None, front=None, literal=False):
-    """One synchronous step.  Returns (bits, E, front, n_new)."""
+def field_change(J, h, x, sites) -> float:
+    """The energy change of flipping one or two sites, from the local fields of x."""
+    J, h = _prep(J, h)
+    x = np.ascontiguousarray(x, dtype=np.uint64)
+    s = np.ascontiguousarray(sites, dtype=np.int32)
+    return lib().qo_field_change(len(h), _d(J), _d(h), _u64(x), len(s), s.ctypes.data_as(_ip))
+
+
+def step(J, h, M, bits, E=None, front=None, literal=False, fields=False):
+    """One synchronous step.  Returns (bits, E, front, n_new).  fields=True takes
+    every energy change from the parent's local fields (O(1) per flip instead of
+    O(N)); the result is the same."""
     J, h = _prep(J, h)
     N = len(h)
     W = _W(N)
@@ -133,7 +149,8 @@ def step(J, h, M, bits, E=None, front=None, literal=False):
     oE = np.zeros(M, dtype=np.float64)
     of = np.zeros(M, dtype=np.uint8)
     nn = ctypes.c_int(0)
-    r = lib().qo_step(N, _d(J), _d(h), M, 1 if literal else 0, n, _u64(bits), Ep,
+    fn = lib().qo_step_fields if fields else lib().qo_step
+    r = fn(N, _d(J), _d(h), M, 1 if literal else 0, n, _u64(bits), Ep,
                       front.ctypes.data_as(_u8p), _u64(ob), _d(oE), of.ctypes.data_as(_u8p),
                       ctypes.byref(nn))
     if r < 0:
@@ -142,10 +159,10 @@ def step(J, h, M, bits, E=None, front=None, literal=False):
     return ob[:k], oE[:k], of[:k], r
 
 
-def step_proposed(J, h, M, bits, E, parents, pair_lists):
+def step_proposed(J, h, M, bits, E, parents, pair_lists, fields=False):
     """One learned-form step: S_t plus, for each parent index, its N single
     flips and only the listed pair flips (codes i | j << 16).  Returns
-    (bits, E, front, n_new)."""
+    (bits, E, front, n_new).  fields=True as in step()."""
     J, h = _prep(J, h)
     N = len(h)
     W = _W(N)
@@ -161,7 +178,8 @@ def step_proposed(J, h, M, bits, E, parents, pair_lists):
     oE = np.zeros(M, dtype=np.float64)
     of = np.zeros(M, dtype=np.uint8)
     nn = ctypes.c_int(0)
-    r = lib().qo_step_proposed(N, _d(J), _d(h), M, bits.shape[0], _u64(bits), _d(E), len(par),
+    fn = lib().qo_step_proposed_fields if fields else lib().qo_step_proposed
+    r = fn(N, _d(J), _d(h), M, bits.shape[0], _u64(bits), _d(E), len(par),
                                par.ctypes.data_as(_ip), npairs.ctypes.data_as(_ip),
                                flat.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
                                _u64(ob), _d(oE), of.ctypes.data_as(_u8p), ctypes.byref(nn))

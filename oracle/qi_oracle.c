@@ -32,6 +32,17 @@
  *     same sets (children of an old member were already offered one step
  *     earlier and either entered or ranked behind the whole kept set).
  *
+ * Two ways to get a flipped state's energy, both from the parent's energy:
+ *   - qo_flip_change: the terms of Eq. 1 that touch the flipped sites, summed
+ *     afresh, O(N) per flipped state (the cost paragraph of Sec. III);
+ *   - the *_fields entry points: the parent's local fields
+ *     F_k = h_k + sum_l J_kl s_l are summed once per parent (O(N^2)), and a
+ *     flip of i changes E by -2 s_i F_i, a flip of i and j by
+ *     -2 s_i F_i - 2 s_j F_j + 4 J_ij s_i s_j (the coupling of the pair keeps its
+ *     sign, and F_i, F_j each counted it once with the wrong sign).  O(1) per
+ *     flipped state, which makes N = 600 and N = 1000 steps affordable.
+ * The two are pinned against each other and against Eq. 1 by the tests.
+ *
  * Exactness: inputs on the 2^-24 grid with modest magnitudes make every sum
  * here exact in FP64, so the result does not depend on summation order.
  */
@@ -94,6 +105,44 @@ double qo_flip_change(int N, const double *J, const double *h, const uint64_t *x
     return d;
 }
 
+/* Local fields of state x by a direct sum: F_k = h_k + sum_l J_kl s_l. */
+static void local_fields(int N, const double *J, const double *h, const uint64_t *x, double *F)
+{
+    for (int k = 0; k < N; ++k) {
+        double f = h[k];
+        for (int l = 0; l < N; ++l)
+            f += J[(size_t)k * N + l] * (double)spin_of(x, l);
+        F[k] = f;
+    }
+}
+
+/* E(x') - E(x) for one or two distinct flipped sites, from the fields F of x. */
+static double field_change(int N, const double *J, const uint64_t *x, const double *F,
+                           int nflip, const int *sites)
+{
+    int i = sites[0];
+    double si = (double)spin_of(x, i);
+    double d = -2.0 * si * F[i];
+    if (nflip == 2) {
+        int j = sites[1];
+        double sj = (double)spin_of(x, j);
+        d += -2.0 * sj * F[j] + 4.0 * J[(size_t)i * N + j] * si * sj;
+    }
+    return d;
+}
+
+/* The same change through the local fields (one or two sites); a pin compares it with qo_flip_change. */
+double qo_field_change(int N, const double *J, const double *h, const uint64_t *x, int nflip, const int *sites)
+{
+    if (nflip < 1 || nflip > 2) return NAN;
+    double *F = (double *)malloc(sizeof(double) * (size_t)N);
+    if (!F) return NAN;
+    local_fields(N, J, h, x, F);
+    double d = field_change(N, J, x, F, nflip, sites);
+    free(F);
+    return d;
+}
+
 /* Total order: energy first, then the state integer psi (highest word first). */
 static int order_cmp(double Ea, const uint64_t *a, double Eb, const uint64_t *b, int W)
 {
@@ -153,9 +202,17 @@ static int klist_offer(klist *L, double E, const uint64_t *x, uint8_t flag)
     return 1;
 }
 
-/* Offer the neighbourhood of parent x (energy Ex): single flips, then pairs i<j. */
+/* Energy change of a flip of x: from the fields F of x, or (F == NULL) afresh. */
+static double change_of(int N, const double *J, const double *h, const uint64_t *x, const double *F,
+                        int nflip, const int *sites)
+{
+    return F ? field_change(N, J, x, F, nflip, sites) : qo_flip_change(N, J, h, x, nflip, sites);
+}
+
+/* Offer the neighbourhood of parent x (energy Ex): single flips, then pairs i<j.
+   F: the local fields of x, or NULL to evaluate each change afresh. */
 static void offer_children(klist *L, int N, const double *J, const double *h,
-                           const uint64_t *x, double Ex, uint64_t *child)
+                           const uint64_t *x, double Ex, uint64_t *child, const double *F)
 {
     int W = words_of(N);
     int sites[2];
@@ -163,7 +220,7 @@ static void offer_children(klist *L, int N, const double *J, const double *h,
         memcpy(child, x, sizeof(uint64_t) * W);
         child[i >> 6] ^= (uint64_t)1 << (i & 63);
         sites[0] = i;
-        klist_offer(L, Ex + qo_flip_change(N, J, h, x, 1, sites), child, 1);
+        klist_offer(L, Ex + change_of(N, J, h, x, F, 1, sites), child, 1);
     }
     for (int i = 0; i < N; ++i) {
         for (int j = i + 1; j < N; ++j) {
@@ -171,7 +228,7 @@ static void offer_children(klist *L, int N, const double *J, const double *h,
             child[i >> 6] ^= (uint64_t)1 << (i & 63);
             child[j >> 6] ^= (uint64_t)1 << (j & 63);
             sites[0] = i; sites[1] = j;
-            klist_offer(L, Ex + qo_flip_change(N, J, h, x, 2, sites), child, 1);
+            klist_offer(L, Ex + change_of(N, J, h, x, F, 2, sites), child, 1);
         }
     }
 }
@@ -185,9 +242,9 @@ static void offer_children(klist *L, int N, const double *J, const double *h,
  * S_t; otherwise only those with in_front set.  Returns the number of new
  * states (0 means the set is stable), or -1 on allocation failure.
  */
-int qo_step(int N, const double *J, const double *h, int M, int literal,
-            int n_in, const uint64_t *in_bits, const double *in_E, const uint8_t *in_front,
-            uint64_t *out_bits, double *out_E, uint8_t *out_front, int *n_out)
+static int step_impl(int N, const double *J, const double *h, int M, int literal, int use_fields,
+                     int n_in, const uint64_t *in_bits, const double *in_E, const uint8_t *in_front,
+                     uint64_t *out_bits, double *out_E, uint8_t *out_front, int *n_out)
 {
     int W = words_of(N);
     double *E_in = (double *)malloc(sizeof(double) * (size_t)(n_in > 0 ? n_in : 1));
@@ -212,11 +269,15 @@ int qo_step(int N, const double *J, const double *h, int M, int literal,
             tid = omp_get_thread_num();
 #endif
             uint64_t *child = (uint64_t *)malloc(sizeof(uint64_t) * W);
+            double *F = use_fields ? (double *)malloc(sizeof(double) * (size_t)N) : NULL;
 #pragma omp for schedule(dynamic, 1)
             for (int k = 0; k < n_in; ++k) {
                 if (!literal && !in_front[k]) continue;
-                offer_children(&part[tid], N, J, h, in_bits + (size_t)k * W, E_in[k], child);
+                const uint64_t *x = in_bits + (size_t)k * W;
+                if (F) local_fields(N, J, h, x, F);
+                offer_children(&part[tid], N, J, h, x, E_in[k], child, F);
             }
+            free(F);
             free(child);
         }
     }
@@ -248,6 +309,21 @@ int qo_step(int N, const double *J, const double *h, int M, int literal,
     return n_new;
 }
 
+int qo_step(int N, const double *J, const double *h, int M, int literal,
+            int n_in, const uint64_t *in_bits, const double *in_E, const uint8_t *in_front,
+            uint64_t *out_bits, double *out_E, uint8_t *out_front, int *n_out)
+{
+    return step_impl(N, J, h, M, literal, 0, n_in, in_bits, in_E, in_front, out_bits, out_E, out_front, n_out);
+}
+
+/* qo_step with every energy change taken from the parent's local fields. */
+int qo_step_fields(int N, const double *J, const double *h, int M, int literal,
+                   int n_in, const uint64_t *in_bits, const double *in_E, const uint8_t *in_front,
+                   uint64_t *out_bits, double *out_E, uint8_t *out_front, int *n_out)
+{
+    return step_impl(N, J, h, M, literal, 1, n_in, in_bits, in_E, in_front, out_bits, out_E, out_front, n_out);
+}
+
 /*
  * One search from initial state x0 (S_0 = {x0}); steps until the set is
  * stable or max_iters steps were taken.  *iters counts the steps evaluated,
@@ -263,16 +339,17 @@ int qo_step(int N, const double *J, const double *h, int M, int literal,
  * M lowest distinct candidates, as in qo_step.  Returns the number of new
  * states, or -1 on allocation failure or a malformed pair.
  */
-int qo_step_proposed(int N, const double *J, const double *h, int M,
-                     int n_in, const uint64_t *in_bits, const double *in_E,
-                     int n_par, const int *parent, const int *npairs, const uint32_t *pairs,
-                     uint64_t *out_bits, double *out_E, uint8_t *out_front, int *n_out)
+static int step_proposed_impl(int N, const double *J, const double *h, int M, int use_fields,
+                              int n_in, const uint64_t *in_bits, const double *in_E,
+                              int n_par, const int *parent, const int *npairs, const uint32_t *pairs,
+                              uint64_t *out_bits, double *out_E, uint8_t *out_front, int *n_out)
 {
     int W = words_of(N);
     klist R;
     if (klist_init(&R, M, W) != 0) return -1;
     uint64_t *child = (uint64_t *)malloc(sizeof(uint64_t) * W);
-    if (!child) { klist_free(&R); return -1; }
+    double *F = use_fields ? (double *)malloc(sizeof(double) * (size_t)N) : NULL;
+    if (!child || (use_fields && !F)) { free(child); free(F); klist_free(&R); return -1; }
     for (int k = 0; k < n_in; ++k)
         klist_offer(&R, in_E[k], in_bits + (size_t)k * W, 0);
     size_t off = 0;
@@ -281,11 +358,12 @@ int qo_step_proposed(int N, const double *J, const double *h, int M,
         const uint64_t *x = in_bits + (size_t)parent[p] * W;
         double Ex = in_E[parent[p]];
         int sites[2];
+        if (F) local_fields(N, J, h, x, F);
         for (int i = 0; i < N; ++i) {
             memcpy(child, x, sizeof(uint64_t) * W);
             child[i >> 6] ^= (uint64_t)1 << (i & 63);
             sites[0] = i;
-            klist_offer(&R, Ex + qo_flip_change(N, J, h, x, 1, sites), child, 1);
+            klist_offer(&R, Ex + change_of(N, J, h, x, F, 1, sites), child, 1);
         }
         for (int q = 0; q < npairs[p]; ++q) {
             uint32_t code = pairs[off + q];
@@ -295,7 +373,7 @@ int qo_step_proposed(int N, const double *J, const double *h, int M,
             child[i >> 6] ^= (uint64_t)1 << (i & 63);
             child[j >> 6] ^= (uint64_t)1 << (j & 63);
             sites[0] = i; sites[1] = j;
-            klist_offer(&R, Ex + qo_flip_change(N, J, h, x, 2, sites), child, 1);
+            klist_offer(&R, Ex + change_of(N, J, h, x, F, 2, sites), child, 1);
         }
         off += (size_t)npairs[p];
     }
@@ -311,8 +389,28 @@ int qo_step_proposed(int N, const double *J, const double *h, int M,
         *n_out = R.n;
     }
     free(child);
+    free(F);
     klist_free(&R);
     return n_new;
+}
+
+int qo_step_proposed(int N, const double *J, const double *h, int M,
+                     int n_in, const uint64_t *in_bits, const double *in_E,
+                     int n_par, const int *parent, const int *npairs, const uint32_t *pairs,
+                     uint64_t *out_bits, double *out_E, uint8_t *out_front, int *n_out)
+{
+    return step_proposed_impl(N, J, h, M, 0, n_in, in_bits, in_E, n_par, parent, npairs, pairs,
+                              out_bits, out_E, out_front, n_out);
+}
+
+/* qo_step_proposed with every energy change taken from the parent's local fields. */
+int qo_step_proposed_fields(int N, const double *J, const double *h, int M,
+                            int n_in, const uint64_t *in_bits, const double *in_E,
+                            int n_par, const int *parent, const int *npairs, const uint32_t *pairs,
+                            uint64_t *out_bits, double *out_E, uint8_t *out_front, int *n_out)
+{
+    return step_proposed_impl(N, J, h, M, 1, n_in, in_bits, in_E, n_par, parent, npairs, pairs,
+                              out_bits, out_E, out_front, n_out);
 }
 
 int qo_search(int N, const double *J, const double *h, int M, int max_iters, int literal,

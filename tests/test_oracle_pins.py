@@ -293,6 +293,79 @@ def test_merge_is_lowest_M_distinct_of_union(seed):
     assert [float(e) for e in E] == [table[p] for p in want]
 
 
+@pytest.mark.parametrize("N,dist", [(65, "sk"), (130, "pmj"), (200, "uniform")])
+def test_field_change_equals_energy_difference(N, dist):
+    """The local-field form of the change (Sec. III cost paragraph, with the
+    fields cached): every single flip and a sample of pair flips against Eq. 1
+    evaluated on both states, and against the afresh-summed change."""
+    inst = wl.make_instance(N, 9700 + N, 2, dist)
+    rng = np.random.default_rng(N)
+    for x in inst.init_bits:
+        e0 = oracle.energy(inst.J, inst.h, x)
+        sites = [[i] for i in range(N)]
+        sites += [sorted(rng.choice(N, 2, replace=False).tolist()) for _ in range(300)]
+        sites += [[0, N - 1], [63, 64] if N > 64 else [0, 1], [N - 2, N - 1]]
+        for st in sites:
+            y = x.copy()
+            for i in st:
+                y[i >> 6] ^= np.uint64(1 << (i & 63))
+            d = oracle.field_change(inst.J, inst.h, x, st)
+            assert d == oracle.energy(inst.J, inst.h, y) - e0, (st, d)
+            assert d == oracle.flip_change(inst.J, inst.h, x, st)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_field_step_equals_step(seed):
+    """The step with changes from local fields is the step (same kept set, order,
+    energies and new-state flags), from states along real trajectories, in both
+    expansion modes and on inputs with exact ties."""
+    rng = np.random.default_rng(400 + seed)
+    N = int(rng.integers(3, 140))
+    M = int(rng.integers(1, 90))
+    dist = ("sk", "pmj", "uniform", "sk_h0")[seed % 4]
+    inst = wl.make_instance(N, 9800 + seed, 2, dist)
+    for x0 in inst.init_bits:
+        bits, E, front = x0.reshape(1, -1), None, np.ones(1, np.uint8)
+        for t in range(6):
+            for literal in (False, True):
+                a = oracle.step(inst.J, inst.h, M, bits, E, front, literal=literal)
+                b = oracle.step(inst.J, inst.h, M, bits, E, front, literal=literal, fields=True)
+                for u, v in zip(a, b):
+                    assert np.array_equal(u, v), (N, M, t, literal)
+            if a[3] == 0:
+                break
+            bits, E, front = a[0], a[1], a[2]
+
+
+def test_field_step_equals_step_n600():
+    """Ten words per state: two parents of an N = 600 instance."""
+    inst = wl.make_instance(600, 9900, 2, "sk")
+    bits = np.asarray(inst.init_bits, np.uint64)
+    a = oracle.step(inst.J, inst.h, 120, bits)
+    b = oracle.step(inst.J, inst.h, 120, bits, fields=True)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+    assert a[3] == 120
+
+
+def test_field_step_proposed_equals_step_proposed():
+    inst = wl.make_instance(90, 9950, 3, "pmj")
+    rng = np.random.default_rng(5)
+    bits = np.asarray(inst.init_bits, np.uint64)
+    E = np.array([oracle.energy(inst.J, inst.h, x) for x in bits])
+    lists = []
+    for _ in range(3):
+        pr = set()
+        while len(pr) < 200:
+            i, j = sorted(rng.choice(90, 2, replace=False).tolist())
+            pr.add(i | (j << 16))
+        lists.append(sorted(pr))
+    a = oracle.step_proposed(inst.J, inst.h, 40, bits, E, [0, 1, 2], lists)
+    b = oracle.step_proposed(inst.J, inst.h, 40, bits, E, [0, 1, 2], lists, fields=True)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+
+
 def test_search_stops_at_iteration_cap():
     inst = wl.make_instance(40, 9500, 1, "sk")
     b, E, iters, stable = oracle.search(inst.J, inst.h, 20, inst.init_bits[0], max_iters=2)
@@ -308,7 +381,12 @@ MUTANTS = {
     "pair_keeps_coupling": ("if (in_sites(l, nflip, sites)) continue;", "if (l == k) continue;"),
     "sum_all_pairs": ("for (int j = i + 1; j < N; ++j)", "for (int j = 0; j < N; ++j)"),
     "no_distinctness": ("if (memcmp(L->bits + (size_t)k * W, x, sizeof(uint64_t) * W) == 0)", "if (0)"),
-    "skip_single_flips": ("klist_offer(L, Ex + qo_flip_change(N, J, h, x, 1, sites), child, 1);", "(void)0;"),
+    "skip_single_flips": ("klist_offer(L, Ex + change_of(N, J, h, x, F, 1, sites), child, 1);", "(void)0;"),
+    "field_pair_sign": ("d += -2.0 * sj * F[j] + 4.0 * J[(size_t)i * N + j] * si * sj;",
+                        "d += -2.0 * sj * F[j] - 4.0 * J[(size_t)i * N + j] * si * sj;"),
+    "field_drops_h": ("double f = h[k];", "double f = 0.0;"),
+    "field_wrong_index": ("4.0 * J[(size_t)i * N + j] * si * sj", "4.0 * J[(size_t)i * N + i] * si * sj"),
+    "field_single_sign": ("double d = -2.0 * si * F[i];", "double d = 2.0 * si * F[i];"),
 }
 
 
@@ -319,6 +397,7 @@ def _core_pins_pass() -> bool:
         for s in range(4):
             test_step_is_lowest_M_of_enumerated_union(s)
         test_brute_force_equals_definition("pmj")
+        test_field_change_equals_energy_difference(65, "sk")
     except AssertionError:
         return False
     return True
