@@ -332,6 +332,34 @@ int ising_mlp_train(float *params, float *m, float *v, const float *feat, const 
                     int32_t batch, int32_t steps, int32_t t0, float lr, float pos_weight, uint64_t seed,
                     float *loss, void *workspace, int64_t workspace_bytes, void *stream);
 
+/*
+ * ---------------------------------------------------------------- exhaustive enumeration
+ * The K lowest states of each instance over all 2^N states, sorted by
+ * (E, psi): the brute-force reference of Sec. IV (Fig. 1) and the exact
+ * low-energy spectra of Sec. V (ground energy, first gap, E_k).  Every state is
+ * visited on the GPU in Gray-code order (one spin flip per state, the energy
+ * updated from the flipped site's couplings); energies are exact on the 2^-24
+ * grid.  Not a step of the search: a separate call for references and
+ * spectra.
+ *
+ *   n_inst     instances, >= 1; N[b] in [1, 40] (2^N states are visited, so
+ *              N = 30 takes about 10^9 state visits per instance)
+ *   J, h       host pointers as for ising_search_init (symmetric, zero
+ *              diagonal, multiples of 2^-24, sum |J_ij| + sum |h_i| <= 2^24)
+ *   K          states wanted per instance, 1 <= K <= 4096 (fewer when 2^N < K)
+ *   bits_out   caller buffer of n_inst*K words: instance b's states at
+ *              b*K .. b*K+count[b]-1 (one word per state, bit i = sigma_i)
+ *   E_out      caller buffer of n_inst*K doubles, the same layout
+ *   count      caller buffer of n_inst ints: min(K, 2^N)
+ *   stream     hipStream_t or NULL
+ * The call allocates device memory for its own use and frees it before
+ * returning; it synchronises the stream.  Errors: INVALID_ARG, NO_DEVICE,
+ * OUT_OF_MEMORY, HIP, CAPACITY (more than 8192 states tie at the K-th lowest
+ * energy of an instance).
+ */
+int ising_brute_lowest(int32_t n_inst, const int32_t *N, const double *const *J, const double *const *h,
+                       int32_t K, uint64_t *bits_out, double *E_out, int32_t *count, void *stream);
+
 /* Frees all device memory of the handle.  NULL is accepted. */
 void ising_search_destroy(ising_search_t *s);
 

@@ -61,6 +61,7 @@ EXPORTED = (
     "ising_mlp_adam",
     "ising_mlp_train",
     "ising_mlp_loss_grad_noalloc",
+    "ising_brute_lowest",
 )
 
 
@@ -168,6 +169,9 @@ def load(path: str = LIB_PATH):
     L.ising_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
     L.ising_mlp_loss_grad.restype = ctypes.c_int
     L.ising_mlp_loss_grad.argtypes = [vp, vp, vp, i64, f32, vp, vp, vp, i64, vp]
+    L.ising_brute_lowest.restype = ctypes.c_int
+    L.ising_brute_lowest.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp, vp,
+                                     ctypes.POINTER(i32), vp]
     L.ising_mlp_loss_grad_noalloc.restype = ctypes.c_int
     L.ising_mlp_loss_grad_noalloc.argtypes = [vp, vp, vp, i64, f32, vp, vp, vp]
     L.ising_mlp_adam.restype = ctypes.c_int
@@ -201,6 +205,34 @@ def current_stream_handle() -> Optional[int]:
 
 def _words(N: int) -> int:
     return (N + 63) // 64
+
+
+def brute_lowest(Js, hs, K: int, stream: Optional[int] = None):
+    """The K lowest states of every instance over all 2^N states (N <= 40),
+    sorted by (E, psi), enumerated on the GPU.  Returns a list of
+    (bits (k, 1) uint64, E (k,)) per instance."""
+    L = load()
+    B = len(hs)
+    keep = []
+    Jp = (ctypes.c_void_p * B)()
+    hp = (ctypes.c_void_p * B)()
+    Ns = []
+    for b in range(B):
+        Jb = np.ascontiguousarray(Js[b], dtype=np.float64)
+        hb = np.ascontiguousarray(hs[b], dtype=np.float64)
+        keep += [Jb, hb]
+        Jp[b] = Jb.ctypes.data
+        hp[b] = hb.ctypes.data
+        Ns.append(len(hb))
+    Narr = (ctypes.c_int32 * B)(*Ns)
+    bits = np.zeros((B, int(K)), np.uint64)
+    E = np.zeros((B, int(K)), np.float64)
+    cnt = (ctypes.c_int32 * B)()
+    if stream is None:
+        stream = current_stream_handle()
+    _check(L.ising_brute_lowest(B, Narr, Jp, hp, int(K), bits.ctypes.data, E.ctypes.data, cnt,
+                                ctypes.c_void_p(stream) if stream else None))
+    return [(bits[b, :cnt[b]].reshape(-1, 1).copy(), E[b, :cnt[b]].copy()) for b in range(B)]
 
 
 class IsingSearch:

@@ -7,11 +7,11 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = ["csrc/api.hip", "csrc/k_init.hip", "csrc/k_step.hip", "csrc/k_split.hip", "csrc/k_learn.hip",
-           "csrc/k_mlp.hip"]
+           "csrc/k_mlp.hip", "csrc/k_brute.hip"]
 OUT = os.path.join(HERE, "lib", "libising_search.so")
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # matrix-core accumulators in ordinary VGPRs (no copies through AGPRs)
@@ -20,13 +20,30 @@ HIPCC_FLAGS = [
 
 
 def build_library(verbose: bool = False) -> str:
+    """Compile every source to an object in parallel, then link the shared library."""
     os.makedirs(os.path.dirname(OUT), exist_ok=True)
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    objdir = os.path.join(HERE, "lib", "obj")
+    os.makedirs(objdir, exist_ok=True)
+    jobs = []
+    for src in SOURCES:
+        obj = os.path.join(objdir, os.path.basename(src).replace(".hip", ".o"))
+        cmd = [hipcc, *HIPCC_FLAGS, "-c", os.path.join(HERE, src), "-o", obj]
+        jobs.append((cmd, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
+    errors = []
+    for cmd, obj, p in jobs:
+        out, err = p.communicate()
+        if p.returncode != 0:
+            errors.append(" ".join(cmd) + "\n" + out + err)
+        elif verbose:
+            print(" ".join(cmd))
+    if errors:
+        raise RuntimeError("hipcc failed:\n" + "\n".join(errors))
     tmp = OUT + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, *[os.path.join(HERE, s) for s in SOURCES], "-o", tmp]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *[o for _, o, _ in jobs], "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
+        raise RuntimeError("link failed:\n" + res.stdout + res.stderr)
     if verbose:
         print(" ".join(cmd))
     os.replace(tmp, OUT)

@@ -1416,3 +1416,211 @@ extern "C" int ising_mlp_train(float* params, float* m, float* v, const float* f
     }
     return ISING_OK;
 }
+
+// ------------------------------------------------------------------ exhaustive enumeration
+namespace {
+
+// device buffers of one size group, freed on every exit path
+struct BruteBufs {
+    std::vector<void*> p;
+    ~BruteBufs()
+    {
+        for (void* q : p) (void)hipFree(q);
+    }
+    template <class T>
+    int get(T** out, size_t count)
+    {
+        void* v = nullptr;
+        const size_t bytes = std::max<size_t>(count * sizeof(T), 8);
+        if (hipMalloc(&v, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(ISING_ERR_OUT_OF_MEMORY, "hipMalloc of %zu bytes failed", bytes);
+        }
+        p.push_back(v);
+        *out = static_cast<T*>(v);
+        return ISING_OK;
+    }
+};
+
+}  // namespace
+
+extern "C" int ising_brute_lowest(int32_t n_inst, const int32_t* N, const double* const* J, const double* const* h,
+                                  int32_t K, uint64_t* bits_out, double* E_out, int32_t* count, void* stream)
+{
+    g_err.clear();
+    if (n_inst < 1) return fail(ISING_ERR_INVALID_ARG, "n_inst=%d < 1", n_inst);
+    if (!N || !J || !h || !bits_out || !E_out || !count) return fail(ISING_ERR_INVALID_ARG, "NULL array argument");
+    if (K < 1 || K > BF_KMAX) return fail(ISING_ERR_INVALID_ARG, "K=%d outside [1, %d]", K, BF_KMAX);
+    for (int b = 0; b < n_inst; ++b) {
+        if (N[b] < 1 || N[b] > BF_NMAX) return fail(ISING_ERR_INVALID_ARG, "N[%d]=%d outside [1, %d]", b, N[b], BF_NMAX);
+        if (!J[b] || !h[b]) return fail(ISING_ERR_INVALID_ARG, "NULL pointer for instance %d", b);
+        const int n = N[b];
+        double bound = 0.0;
+        for (int i = 0; i < n; ++i) {
+            if (!on_grid(h[b][i]))
+                return fail(ISING_ERR_INVALID_ARG, "h[%d][%d]=%g is not a finite multiple of 2^-24", b, i, h[b][i]);
+            bound += std::fabs(h[b][i]);
+            if (J[b][(size_t)i * n + i] != 0.0)
+                return fail(ISING_ERR_INVALID_ARG, "J[%d] has a nonzero diagonal at %d", b, i);
+            for (int j = i + 1; j < n; ++j) {
+                const double v = J[b][(size_t)i * n + j];
+                if (!on_grid(v))
+                    return fail(ISING_ERR_INVALID_ARG, "J[%d][%d,%d]=%g is not a finite multiple of 2^-24", b, i, j, v);
+                if (v != J[b][(size_t)j * n + i])
+                    return fail(ISING_ERR_INVALID_ARG, "J[%d] is not symmetric at (%d,%d)", b, i, j);
+                bound += std::fabs(v);
+            }
+        }
+        if (bound > 16777216.0)
+            return fail(ISING_ERR_INVALID_ARG, "instance %d: sum |J_ij| + sum |h_i| = %g exceeds 2^24", b, bound);
+    }
+    int rc = have_device();
+    if (rc != ISING_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    static std::once_flag lds_once;
+    static hipError_t lds_err = hipSuccess;
+    std::call_once(lds_once, [] { lds_err = brute_sort_set_lds(); });
+    if (lds_err != hipSuccess) return fail(ISING_ERR_HIP, "the sort kernel cannot use its LDS");
+
+    std::vector<int> sizes(N, N + n_inst);
+    std::sort(sizes.begin(), sizes.end());
+    sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+    for (int n : sizes) {
+        std::vector<int> members;
+        for (int b = 0; b < n_inst; ++b)
+            if (N[b] == n) members.push_back(b);
+        const int nb = (int)members.size();
+        BruteBufs buf;
+        double *dJ = nullptr, *dh = nullptr, *dD = nullptr, *dT = nullptr, *dE = nullptr;
+        unsigned long long *dmin = nullptr, *dcnt = nullptr;
+        BruteRec* drec = nullptr;
+        int *dlist = nullptr, *dn = nullptr;
+        uint64_t* dbits = nullptr;
+        if ((rc = buf.get(&dJ, (size_t)nb * n * n)) || (rc = buf.get(&dh, (size_t)nb * n)) ||
+            (rc = buf.get(&dD, (size_t)nb * BF_DSTRIDE)) || (rc = buf.get(&dT, nb)) || (rc = buf.get(&dmin, nb)) ||
+            (rc = buf.get(&dcnt, nb)) || (rc = buf.get(&drec, (size_t)nb * BF_CAP)) || (rc = buf.get(&dlist, nb)) ||
+            (rc = buf.get(&dn, nb)) || (rc = buf.get(&dbits, (size_t)nb * K)) || (rc = buf.get(&dE, (size_t)nb * K)))
+            return rc;
+        {
+            std::vector<double> Jh((size_t)nb * n * n), hh((size_t)nb * n);
+            std::vector<int> lst(nb);
+            for (int k = 0; k < nb; ++k) {
+                std::memcpy(Jh.data() + (size_t)k * n * n, J[members[k]], sizeof(double) * n * n);
+                std::memcpy(hh.data() + (size_t)k * n, h[members[k]], sizeof(double) * n);
+                lst[k] = k;
+            }
+            std::vector<unsigned long long> big(nb, ~0ull);
+            HIP_TRY(hipMemcpyAsync(dJ, Jh.data(), sizeof(double) * Jh.size(), hipMemcpyHostToDevice, st));
+            HIP_TRY(hipMemcpyAsync(dh, hh.data(), sizeof(double) * hh.size(), hipMemcpyHostToDevice, st));
+            HIP_TRY(hipMemcpyAsync(dlist, lst.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
+            HIP_TRY(hipMemcpyAsync(dmin, big.data(), sizeof(unsigned long long) * nb, hipMemcpyHostToDevice, st));
+            HIP_TRY(hipStreamSynchronize(st));   // the host vectors go out of scope
+        }
+        BruteArgs a{};
+        a.N = n;
+        a.n_list = nb;
+        a.list = dlist;
+        a.J = dJ;
+        a.h = dh;
+        a.D = dD;
+        a.T = dT;
+        a.emin = dmin;
+        a.count = dcnt;
+        a.rec = drec;
+        hipError_t e = launch_brute_table(a, st);
+        if (e == hipSuccess) e = launch_brute_pass(a, BF_MIN, st);
+        if (e != hipSuccess) return fail(ISING_ERR_HIP, "enumeration launch failed: %s", hipGetErrorString(e));
+        // the lowest energy of every instance, from its order-preserving image
+        std::vector<unsigned long long> omin(nb);
+        HIP_TRY(hipMemcpyAsync(omin.data(), dmin, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        std::vector<double> emin(nb);
+        for (int k = 0; k < nb; ++k) {
+            const unsigned long long o = omin[k];
+            const unsigned long long u = (o >> 63) ? (o & 0x7FFFFFFFFFFFFFFFull) : ~o;
+            std::memcpy(&emin[k], &u, 8);
+        }
+        // a threshold T_k per instance with want <= #{E <= T_k} <= BF_CAP: grow the
+        // distance above the minimum fourfold until enough states lie below it,
+        // then bisect while too many do
+        const double total = std::ldexp(1.0, n);
+        const long long want = (long long)std::min<double>(K, total);
+        std::vector<double> T(nb, INFINITY);
+        if (total > BF_CAP) {
+            std::vector<double> lo(nb, -1.0), hi(nb, -1.0), d(nb);
+            std::vector<int> open;
+            for (int k = 0; k < nb; ++k) {
+                double scale = 0.0;
+                for (int i = 0; i < n; ++i) scale = std::max(scale, std::fabs(h[members[k]][i]));
+                for (size_t q = 0; q < (size_t)n * n; ++q) scale = std::max(scale, std::fabs(J[members[k]][q]));
+                d[k] = std::max(scale, 1.0) * std::ldexp(1.0, -6);
+                open.push_back(k);
+            }
+            d.resize(nb);
+            for (int it = 0; !open.empty(); ++it) {
+                if (it > 400) return fail(ISING_ERR_HIP, "threshold search did not converge");
+                for (int k = 0; k < nb; ++k) T[k] = -INFINITY;
+                for (int k : open) T[k] = emin[k] + d[k];
+                HIP_TRY(hipMemcpyAsync(dT, T.data(), sizeof(double) * nb, hipMemcpyHostToDevice, st));
+                HIP_TRY(hipMemsetAsync(dcnt, 0, sizeof(unsigned long long) * nb, st));
+                BruteArgs c = a;
+                c.n_list = (int)open.size();
+                HIP_TRY(hipMemcpyAsync(dlist, open.data(), sizeof(int) * open.size(), hipMemcpyHostToDevice, st));
+                e = launch_brute_pass(c, BF_COUNT, st);
+                if (e != hipSuccess) return fail(ISING_ERR_HIP, "count launch failed: %s", hipGetErrorString(e));
+                std::vector<unsigned long long> cnt(nb);
+                HIP_TRY(hipMemcpyAsync(cnt.data(), dcnt, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                std::vector<int> still;
+                for (int k : open) {
+                    const long long c2 = (long long)cnt[k];
+                    if (c2 >= want && c2 <= BF_CAP) {
+                        lo[k] = d[k];   // final
+                        continue;
+                    }
+                    if (c2 < want) lo[k] = d[k];
+                    else hi[k] = d[k];
+                    if (hi[k] < 0) {
+                        d[k] *= 4.0;
+                    } else {
+                        const double lo_k = std::max(lo[k], 0.0);
+                        if (hi[k] - lo_k <= std::ldexp(1.0, -23))
+                            return fail(ISING_ERR_CAPACITY,
+                                        "instance %d: more than %d states tie at its %lld-th lowest energy",
+                                        members[k], BF_CAP, want);
+                        d[k] = 0.5 * (lo_k + hi[k]);
+                    }
+                    still.push_back(k);
+                }
+                open.swap(still);
+            }
+            for (int k = 0; k < nb; ++k) T[k] = emin[k] + lo[k];
+        }
+        std::vector<int> all(nb);
+        for (int k = 0; k < nb; ++k) all[k] = k;
+        HIP_TRY(hipMemcpyAsync(dlist, all.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(dT, T.data(), sizeof(double) * nb, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemsetAsync(dcnt, 0, sizeof(unsigned long long) * nb, st));
+        e = launch_brute_pass(a, BF_COLLECT, st);
+        if (e == hipSuccess) e = launch_brute_sort(a, K, dbits, dE, dn, st);
+        if (e != hipSuccess) return fail(ISING_ERR_HIP, "collect launch failed: %s", hipGetErrorString(e));
+        std::vector<unsigned long long> cnt(nb);
+        std::vector<int> nout(nb);
+        std::vector<uint64_t> ob((size_t)nb * K);
+        std::vector<double> oE((size_t)nb * K);
+        HIP_TRY(hipMemcpyAsync(cnt.data(), dcnt, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(nout.data(), dn, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(ob.data(), dbits, sizeof(uint64_t) * ob.size(), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(oE.data(), dE, sizeof(double) * oE.size(), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int k = 0; k < nb; ++k) {
+            if (cnt[k] > (unsigned long long)BF_CAP || (long long)nout[k] < want)
+                return fail(ISING_ERR_HIP, "instance %d: %llu states collected for %lld", members[k], cnt[k], want);
+            const int b = members[k];
+            std::memcpy(bits_out + (size_t)b * K, ob.data() + (size_t)k * K, sizeof(uint64_t) * nout[k]);
+            std::memcpy(E_out + (size_t)b * K, oE.data() + (size_t)k * K, sizeof(double) * nout[k]);
+            count[b] = nout[k];
+        }
+    }
+    return ISING_OK;
+}

@@ -482,4 +482,39 @@ hipError_t launch_mlp_adam(float* P, float* m, float* v, const float* g, float l
 hipError_t launch_mlp_forward(const float* P, const float* X, long long n, float* z, hipStream_t st);
 hipError_t launch_final(const Layout& lay, hipStream_t st);
 
+// ------------------------------------------------------------------ exhaustive enumeration (k_brute.hip)
+constexpr int BF_NL = 8;                 // low sites walked in Gray order by one thread
+constexpr int BF_DSTRIDE = 1 << BF_NL;   // table entries per instance
+constexpr int BF_CAP = 8192;             // records per instance collected for the final sort
+constexpr int BF_KMAX = 4096;            // lowest states returned per instance at most
+constexpr int BF_NMAX = 40;              // 2^N states, one 64-bit word each
+enum { BF_MIN = 0, BF_COUNT = 1, BF_COLLECT = 2 };
+
+struct BruteRec {
+    double E;
+    uint64_t psi;
+};
+static_assert(sizeof(BruteRec) == 16, "record layout");
+
+// All instances of one size N; instance b of the group at J + b*N*N, h + b*N.
+struct BruteArgs {
+    int N;
+    int n_list;                  // instances processed by this launch
+    const int* list;             // [n_list] their indices in the group
+    const double* J;             // [nb][N][N] couplings J_ij (symmetric, zero diagonal)
+    const double* h;             // [nb][N]
+    double* D;                   // [nb][BF_DSTRIDE] Gray-walk table of the low sites
+    const double* T;             // [nb] thresholds (count and collect passes)
+    unsigned long long* emin;    // [nb] order-preserving image of the lowest energy
+    unsigned long long* count;   // [nb] states counted or collected
+    BruteRec* rec;               // [nb][BF_CAP]
+};
+
+int brute_low_sites(int N);
+hipError_t launch_brute_table(const BruteArgs& a, hipStream_t st);
+hipError_t launch_brute_pass(const BruteArgs& a, int mode, hipStream_t st);
+hipError_t brute_sort_set_lds();
+hipError_t launch_brute_sort(const BruteArgs& a, int K, uint64_t* out_bits, double* out_E, int* out_n,
+                             hipStream_t st);
+
 }  // namespace qi

@@ -20,7 +20,7 @@ def declared_symbols():
     for fn in os.listdir(inc):
         if fn.endswith(".h"):
             src = open(os.path.join(inc, fn)).read()
-            out |= set(re.findall(r"\b(ising_(?:search|mlp)_[a-z_]+)\s*\(", src))
+            out |= set(re.findall(r"\b(ising_[a-z0-9_]+)\s*\(", src))
     return out
 
 
