@@ -64,6 +64,12 @@ def load(path: str):
     L.qo_step_fields.argtypes = L.qo_step.argtypes
     L.qo_step_proposed_fields.restype = ctypes.c_int
     L.qo_step_proposed_fields.argtypes = L.qo_step_proposed.argtypes
+    L.qo_step_h1.restype = ctypes.c_int
+    L.qo_step_h1.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                             ctypes.c_int, _u64p, _dp, _u8p, _u64p, _dp, _u8p, _ip]
+    L.qo_search_h1.restype = ctypes.c_int
+    L.qo_search_h1.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                               ctypes.c_int, _u64p, _u64p, _dp, _ip, _ip]
     L.qo_num_threads.restype = ctypes.c_int
     L.qo_num_threads.argtypes = []
     return L
@@ -129,10 +135,14 @@ def field_change(J, h, x, sites) -> float:
     return lib().qo_field_change(len(h), _d(J), _d(h), _u64(x), len(s), s.ctypes.data_as(_ip))
 
 
-def step(J, h, M, bits, E=None, front=None, literal=False, fields=False):
+H1_FLIPS, H1_SINGLES, H1_EXCHANGE = 0, 1, 2
+
+
+def step(J, h, M, bits, E=None, front=None, literal=False, fields=False, h1=H1_FLIPS):
     """One synchronous step.  Returns (bits, E, front, n_new).  fields=True takes
     every energy change from the parent's local fields (O(1) per flip instead of
-    O(N)); the result is the same."""
+    O(N)); the result is the same.  h1 selects the neighbourhood: single and
+    pair flips (0), single flips only (1), exchanges of unequal spins (2)."""
     J, h = _prep(J, h)
     N = len(h)
     W = _W(N)
@@ -149,10 +159,14 @@ def step(J, h, M, bits, E=None, front=None, literal=False, fields=False):
     oE = np.zeros(M, dtype=np.float64)
     of = np.zeros(M, dtype=np.uint8)
     nn = ctypes.c_int(0)
-    fn = lib().qo_step_fields if fields else lib().qo_step
-    r = fn(N, _d(J), _d(h), M, 1 if literal else 0, n, _u64(bits), Ep,
-                      front.ctypes.data_as(_u8p), _u64(ob), _d(oE), of.ctypes.data_as(_u8p),
-                      ctypes.byref(nn))
+    if h1 == H1_FLIPS:
+        fn = lib().qo_step_fields if fields else lib().qo_step
+        r = fn(N, _d(J), _d(h), M, 1 if literal else 0, n, _u64(bits), Ep,
+               front.ctypes.data_as(_u8p), _u64(ob), _d(oE), of.ctypes.data_as(_u8p), ctypes.byref(nn))
+    else:
+        r = lib().qo_step_h1(N, _d(J), _d(h), M, 1 if literal else 0, 1 if fields else 0, int(h1), n,
+                             _u64(bits), Ep, front.ctypes.data_as(_u8p), _u64(ob), _d(oE),
+                             of.ctypes.data_as(_u8p), ctypes.byref(nn))
     if r < 0:
         raise MemoryError("qo_step failed")
     k = nn.value
@@ -189,7 +203,7 @@ def step_proposed(J, h, M, bits, E, parents, pair_lists, fields=False):
     return ob[:k], oE[:k], of[:k], r
 
 
-def search(J, h, M, x0, max_iters=1 << 30, literal=False):
+def search(J, h, M, x0, max_iters=1 << 30, literal=False, fields=False, h1=H1_FLIPS):
     """One search from x0.  Returns (bits, E, iters, stable)."""
     J, h = _prep(J, h)
     N = len(h)
@@ -199,8 +213,12 @@ def search(J, h, M, x0, max_iters=1 << 30, literal=False):
     oE = np.zeros(M, dtype=np.float64)
     nn = ctypes.c_int(0)
     it = ctypes.c_int(0)
-    r = lib().qo_search(N, _d(J), _d(h), M, int(max_iters), 1 if literal else 0, _u64(x0),
-                        _u64(ob), _d(oE), ctypes.byref(nn), ctypes.byref(it))
+    if h1 == H1_FLIPS and not fields:
+        r = lib().qo_search(N, _d(J), _d(h), M, int(max_iters), 1 if literal else 0, _u64(x0),
+                            _u64(ob), _d(oE), ctypes.byref(nn), ctypes.byref(it))
+    else:
+        r = lib().qo_search_h1(N, _d(J), _d(h), M, int(max_iters), 1 if literal else 0, 1 if fields else 0,
+                               int(h1), _u64(x0), _u64(ob), _d(oE), ctypes.byref(nn), ctypes.byref(it))
     if r < 0:
         raise MemoryError("qo_search failed")
     k = nn.value

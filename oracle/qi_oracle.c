@@ -43,6 +43,15 @@
  *     flipped state, which makes N = 600 and N = 1000 steps affordable.
  * The two are pinned against each other and against Eq. 1 by the tests.
  *
+ * The perturbation H1 decides the neighbourhood (Sec. VI names two others
+ * besides the one- and two-spin flips of Eq. 16):
+ *   h1 = 0  sigma^x_i and sigma^x_i sigma^x_j: all single and pair flips;
+ *   h1 = 1  sigma^x_i only (the J = 1 case): the N single flips;
+ *   h1 = 2  the XX interaction sum_{i<j} (sigma^x_i sigma^x_j + sigma^y_i sigma^y_j):
+ *           it exchanges the spins of sites i and j, which changes the state only
+ *           when they differ, and then it is the pair flip of i and j; the number
+ *           of down spins (the total sigma^z) is conserved.
+ *
  * Exactness: inputs on the 2^-24 grid with modest magnitudes make every sum
  * here exact in FP64, so the result does not depend on summation order.
  */
@@ -209,21 +218,23 @@ static double change_of(int N, const double *J, const double *h, const uint64_t 
     return F ? field_change(N, J, x, F, nflip, sites) : qo_flip_change(N, J, h, x, nflip, sites);
 }
 
-/* Offer the neighbourhood of parent x (energy Ex): single flips, then pairs i<j.
-   F: the local fields of x, or NULL to evaluate each change afresh. */
-static void offer_children(klist *L, int N, const double *J, const double *h,
+/* Offer the neighbourhood of parent x (energy Ex) under H1 mode h1: single
+   flips, then pairs i<j.  F: the local fields of x, or NULL to evaluate each
+   change afresh. */
+static void offer_children(klist *L, int N, const double *J, const double *h, int h1,
                            const uint64_t *x, double Ex, uint64_t *child, const double *F)
 {
     int W = words_of(N);
     int sites[2];
-    for (int i = 0; i < N; ++i) {
+    for (int i = 0; i < N && h1 != 2; ++i) {
         memcpy(child, x, sizeof(uint64_t) * W);
         child[i >> 6] ^= (uint64_t)1 << (i & 63);
         sites[0] = i;
         klist_offer(L, Ex + change_of(N, J, h, x, F, 1, sites), child, 1);
     }
-    for (int i = 0; i < N; ++i) {
+    for (int i = 0; i < N && h1 != 1; ++i) {
         for (int j = i + 1; j < N; ++j) {
+            if (h1 == 2 && spin_of(x, i) == spin_of(x, j)) continue;   /* the exchange leaves x as it is */
             memcpy(child, x, sizeof(uint64_t) * W);
             child[i >> 6] ^= (uint64_t)1 << (i & 63);
             child[j >> 6] ^= (uint64_t)1 << (j & 63);
@@ -242,7 +253,7 @@ static void offer_children(klist *L, int N, const double *J, const double *h,
  * S_t; otherwise only those with in_front set.  Returns the number of new
  * states (0 means the set is stable), or -1 on allocation failure.
  */
-static int step_impl(int N, const double *J, const double *h, int M, int literal, int use_fields,
+static int step_impl(int N, const double *J, const double *h, int M, int literal, int use_fields, int h1,
                      int n_in, const uint64_t *in_bits, const double *in_E, const uint8_t *in_front,
                      uint64_t *out_bits, double *out_E, uint8_t *out_front, int *n_out)
 {
@@ -275,7 +286,7 @@ static int step_impl(int N, const double *J, const double *h, int M, int literal
                 if (!literal && !in_front[k]) continue;
                 const uint64_t *x = in_bits + (size_t)k * W;
                 if (F) local_fields(N, J, h, x, F);
-                offer_children(&part[tid], N, J, h, x, E_in[k], child, F);
+                offer_children(&part[tid], N, J, h, h1, x, E_in[k], child, F);
             }
             free(F);
             free(child);
@@ -313,7 +324,7 @@ int qo_step(int N, const double *J, const double *h, int M, int literal,
             int n_in, const uint64_t *in_bits, const double *in_E, const uint8_t *in_front,
             uint64_t *out_bits, double *out_E, uint8_t *out_front, int *n_out)
 {
-    return step_impl(N, J, h, M, literal, 0, n_in, in_bits, in_E, in_front, out_bits, out_E, out_front, n_out);
+    return step_impl(N, J, h, M, literal, 0, 0, n_in, in_bits, in_E, in_front, out_bits, out_E, out_front, n_out);
 }
 
 /* qo_step with every energy change taken from the parent's local fields. */
@@ -321,7 +332,17 @@ int qo_step_fields(int N, const double *J, const double *h, int M, int literal,
                    int n_in, const uint64_t *in_bits, const double *in_E, const uint8_t *in_front,
                    uint64_t *out_bits, double *out_E, uint8_t *out_front, int *n_out)
 {
-    return step_impl(N, J, h, M, literal, 1, n_in, in_bits, in_E, in_front, out_bits, out_E, out_front, n_out);
+    return step_impl(N, J, h, M, literal, 1, 0, n_in, in_bits, in_E, in_front, out_bits, out_E, out_front, n_out);
+}
+
+/* qo_step (use_fields = 0) or qo_step_fields (1) under H1 mode h1 (0, 1, 2, see the top of this file). */
+int qo_step_h1(int N, const double *J, const double *h, int M, int literal, int use_fields, int h1,
+               int n_in, const uint64_t *in_bits, const double *in_E, const uint8_t *in_front,
+               uint64_t *out_bits, double *out_E, uint8_t *out_front, int *n_out)
+{
+    if (h1 < 0 || h1 > 2) return -1;
+    return step_impl(N, J, h, M, literal, use_fields, h1, n_in, in_bits, in_E, in_front, out_bits, out_E,
+                     out_front, n_out);
 }
 
 /*
@@ -413,8 +434,9 @@ int qo_step_proposed_fields(int N, const double *J, const double *h, int M,
                               out_bits, out_E, out_front, n_out);
 }
 
-int qo_search(int N, const double *J, const double *h, int M, int max_iters, int literal,
-              const uint64_t *x0, uint64_t *out_bits, double *out_E, int *n_out, int *iters)
+static int search_impl(int N, const double *J, const double *h, int M, int max_iters, int literal,
+                       int use_fields, int h1, const uint64_t *x0, uint64_t *out_bits, double *out_E,
+                       int *n_out, int *iters)
 {
     int W = words_of(N);
     size_t cap = (size_t)M;
@@ -433,7 +455,7 @@ int qo_search(int N, const double *J, const double *h, int M, int max_iters, int
         int t = 0, stable = 0;
         while (t < max_iters) {
             int nn = 0;
-            int n_new = qo_step(N, J, h, M, literal, n, cb, cE, cf, nb, nE, nf, &nn);
+            int n_new = step_impl(N, J, h, M, literal, use_fields, h1, n, cb, cE, cf, nb, nE, nf, &nn);
             if (n_new < 0) { t = -1; break; }
             ++t;
             if (n_new == 0) { stable = 1; break; }
@@ -452,6 +474,20 @@ int qo_search(int N, const double *J, const double *h, int M, int max_iters, int
     }
     free(cb); free(nb); free(cE); free(nE); free(cf); free(nf);
     return rc;
+}
+
+int qo_search(int N, const double *J, const double *h, int M, int max_iters, int literal,
+              const uint64_t *x0, uint64_t *out_bits, double *out_E, int *n_out, int *iters)
+{
+    return search_impl(N, J, h, M, max_iters, literal, 0, 0, x0, out_bits, out_E, n_out, iters);
+}
+
+/* qo_search under H1 mode h1, with the field (1) or afresh (0) energy changes. */
+int qo_search_h1(int N, const double *J, const double *h, int M, int max_iters, int literal, int use_fields,
+                 int h1, const uint64_t *x0, uint64_t *out_bits, double *out_E, int *n_out, int *iters)
+{
+    if (h1 < 0 || h1 > 2) return -1;
+    return search_impl(N, J, h, M, max_iters, literal, use_fields, h1, x0, out_bits, out_E, n_out, iters);
 }
 
 /* Alg. 4 merge: the M lowest distinct states of the union of several lists. */

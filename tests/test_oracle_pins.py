@@ -366,6 +366,81 @@ def test_field_step_proposed_equals_step_proposed():
         assert np.array_equal(u, v)
 
 
+# ---------------------------------------------------------------- other choices of H1 (Sec. VI)
+def neighbourhood_h1(psi, N, h1):
+    """psi and the states H1 connects it to: single flips (h1 = 1), or the
+    exchange of two unequal spins (h1 = 2, the XX interaction)."""
+    if h1 == 1:
+        return [psi] + [psi ^ (1 << i) for i in range(N)]
+    return [psi] + [psi ^ (1 << i) ^ (1 << j) for i in range(N) for j in range(i + 1, N)
+                    if ((psi >> i) & 1) != ((psi >> j) & 1)]
+
+
+@pytest.mark.parametrize("h1", [1, 2])
+@pytest.mark.parametrize("seed", range(8))
+def test_h1_step_is_lowest_M_of_enumerated_union(h1, seed):
+    rng = np.random.default_rng(100 + seed)
+    N = int(rng.integers(3, 10))
+    dist = ["sk", "pmj", "uniform", "sk_h0"][seed % 4]
+    inst = wl.make_instance(N, 5100 + seed, 1, dist)
+    table = spectrum_table(inst.J, inst.h)
+    M = int(rng.integers(1, 2 ** N + 3))
+    n_in = int(rng.integers(1, min(M, 2 ** N) + 1))
+    S = [int(v) for v in rng.choice(2 ** N, n_in, replace=False)]
+    S.sort(key=lambda p: (table[p], p))
+    U = set()
+    for p in S:
+        U.update(neighbourhood_h1(p, N, h1))
+    want = sorted(U, key=lambda p: (table[p], p))[:M]
+    bits = np.array([[p] for p in S], dtype=np.uint64)
+    for fields in (False, True):
+        ob, oE, of, n_new = oracle.step(inst.J, inst.h, M, bits, literal=True, fields=fields, h1=h1)
+        assert [int(x) for x in ob[:, 0]] == want
+        assert [float(e) for e in oE] == [table[p] for p in want]
+        assert [int(f) for f in of] == [0 if p in S else 1 for p in want]
+        assert n_new == sum(1 for p in want if p not in S)
+
+
+@pytest.mark.parametrize("h1", [1, 2])
+def test_h1_frontier_expansion_equals_literal(h1):
+    for k, N in enumerate((8, 13, 70)):
+        inst = wl.make_instance(N, 6100 + k, 2, ("sk", "pmj", "sk")[k])
+        for x0 in inst.init_bits:
+            a = oracle.search(inst.J, inst.h, 20, x0, literal=True, h1=h1)
+            b = oracle.search(inst.J, inst.h, 20, x0, literal=False, fields=True, h1=h1)
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+            assert a[2] == b[2] and a[3] and b[3]
+
+
+def test_exchange_conserves_down_spins_and_fills_its_sector():
+    """The XX search never leaves the sector of its initial state; with M at
+    least the sector's size it ends with the whole sector in (E, psi) order
+    (the brute force restricted to that sector)."""
+    from math import comb
+    N = 10
+    inst = wl.make_instance(N, 6200, 3, "uniform")
+    table = spectrum_table(inst.J, inst.h)
+    for x0 in inst.init_bits:
+        nd = bin(int(x0[0])).count("1")
+        sector = sorted((p for p in range(2 ** N) if bin(p).count("1") == nd), key=lambda p: (table[p], p))
+        b, E, it, stable = oracle.search(inst.J, inst.h, comb(N, nd), x0, h1=2)
+        assert stable and [int(x) for x in b[:, 0]] == sector
+        b, E, it, stable = oracle.search(inst.J, inst.h, 7, x0, h1=2)
+        assert all(bin(int(x)).count("1") == nd for x in b[:, 0])
+
+
+@pytest.mark.parametrize("h1", [1, 2])
+def test_h1_M1_is_descent_to_a_local_minimum(h1):
+    """M = 1: the search ends where no state that H1 connects to is lower."""
+    for k in range(4):
+        inst = wl.make_instance(12, 6300 + k, 1, "sk")
+        table = spectrum_table(inst.J, inst.h)
+        b, E, it, stable = oracle.search(inst.J, inst.h, 1, inst.init_bits[0], h1=h1)
+        p = int(b[0, 0])
+        assert stable and E[0] == table[p]
+        assert all((table[q], q) >= (table[p], p) for q in neighbourhood_h1(p, 12, h1))
+
+
 def test_search_stops_at_iteration_cap():
     inst = wl.make_instance(40, 9500, 1, "sk")
     b, E, iters, stable = oracle.search(inst.J, inst.h, 20, inst.init_bits[0], max_iters=2)
@@ -387,6 +462,10 @@ MUTANTS = {
     "field_drops_h": ("double f = h[k];", "double f = 0.0;"),
     "field_wrong_index": ("4.0 * J[(size_t)i * N + j] * si * sj", "4.0 * J[(size_t)i * N + i] * si * sj"),
     "field_single_sign": ("double d = -2.0 * si * F[i];", "double d = 2.0 * si * F[i];"),
+    "exchange_keeps_equal_spins": ("if (h1 == 2 && spin_of(x, i) == spin_of(x, j)) continue;",
+                                   "if (h1 == 2 && spin_of(x, i) != spin_of(x, j)) continue;"),
+    "exchange_keeps_singles": ("for (int i = 0; i < N && h1 != 2; ++i) {", "for (int i = 0; i < N; ++i) {"),
+    "singles_mode_keeps_pairs": ("for (int i = 0; i < N && h1 != 1; ++i) {", "for (int i = 0; i < N; ++i) {"),
 }
 
 
@@ -398,6 +477,9 @@ def _core_pins_pass() -> bool:
             test_step_is_lowest_M_of_enumerated_union(s)
         test_brute_force_equals_definition("pmj")
         test_field_change_equals_energy_difference(65, "sk")
+        for s in range(2):
+            test_h1_step_is_lowest_M_of_enumerated_union(1, s)
+            test_h1_step_is_lowest_M_of_enumerated_union(2, s)
     except AssertionError:
         return False
     return True
