@@ -62,10 +62,22 @@ enum {
                                          ising_search_get_proposals (B*L*M*K*4 bytes) */
     ISING_FLAG_SITE_BOUND = 2,        /* plain and split forms: skip pair flips that a bound proves
                                          cannot enter (not in the paper; see below) */
-    ISING_FLAG_FP16_SCAN = 4          /* split form: the pair scan in packed FP16 (two pairs per
+    ISING_FLAG_FP16_SCAN = 4,         /* split form: the pair scan in packed FP16 (two pairs per
                                          instruction) with a slack for FP16 rounding; every admitted
                                          pair is still re-scored in FP64, so the kept sets are the
                                          same (see the split-form section below) */
+    ISING_FLAG_SINGLE_FLIPS = 8,      /* plain form: H1 = sum_i sigma^x_i only (the J = 1 choice of
+                                         Sec. VI): the neighbourhood of a state is the state and its
+                                         N single flips; O(N) per expanded state */
+    ISING_FLAG_EXCHANGE = 16          /* plain form: H1 = sum_{i<j} (sigma^x_i sigma^x_j +
+                                         sigma^y_i sigma^y_j), the XX interaction of Sec. VI: the
+                                         neighbourhood is the state and the exchanges of two unequal
+                                         spins (the pair flips with s_i != s_j); the number of down
+                                         spins is conserved, so every initial state of an instance
+                                         must have the same number (one sector per instance; give an
+                                         instance again with other initial states for another
+                                         sector), and ising_search_set_search keeps a search in its
+                                         sector */
 };
 
 /*

@@ -31,6 +31,8 @@ FORM_LEARNED = 2
 FLAG_RECORD_PROPOSALS = 1
 FLAG_SITE_BOUND = 2
 FLAG_FP16_SCAN = 4
+FLAG_SINGLE_FLIPS = 8
+FLAG_EXCHANGE = 16
 SCORER_NETWORK = 0
 SCORER_FIELDS = 1
 SCORER_UNIFORM = 2

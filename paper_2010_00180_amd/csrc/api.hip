@@ -193,8 +193,17 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     if (cfg->M < 1 || cfg->M > 1024) return fail(ISING_ERR_INVALID_ARG, "M=%d outside [1, 1024]", cfg->M);
     if (cfg->form != ISING_FORM_PLAIN && cfg->form != ISING_FORM_SPLIT_BF16 && cfg->form != ISING_FORM_LEARNED)
         return fail(ISING_ERR_INVALID_ARG, "form %d is unknown (0 plain, 1 split-bf16, 2 learned)", cfg->form);
-    if (cfg->flags & ~(ISING_FLAG_RECORD_PROPOSALS | ISING_FLAG_SITE_BOUND | ISING_FLAG_FP16_SCAN))
+    if (cfg->flags & ~(ISING_FLAG_RECORD_PROPOSALS | ISING_FLAG_SITE_BOUND | ISING_FLAG_FP16_SCAN |
+                       ISING_FLAG_SINGLE_FLIPS | ISING_FLAG_EXCHANGE))
         return fail(ISING_ERR_INVALID_ARG, "unknown flag bits 0x%x", cfg->flags);
+    const bool h1_singles = (cfg->flags & ISING_FLAG_SINGLE_FLIPS) != 0;
+    const bool h1_exchange = (cfg->flags & ISING_FLAG_EXCHANGE) != 0;
+    if (h1_singles && h1_exchange)
+        return fail(ISING_ERR_INVALID_ARG, "single flips and exchanges are two different choices of H1");
+    if ((h1_singles || h1_exchange) && cfg->form != ISING_FORM_PLAIN)
+        return fail(ISING_ERR_INVALID_ARG, "the single-flip and exchange neighbourhoods run in the plain form only");
+    if (h1_singles && (cfg->flags & ISING_FLAG_SITE_BOUND))
+        return fail(ISING_ERR_INVALID_ARG, "the site bound skips pair flips, which the single-flip neighbourhood has none of");
     if ((cfg->flags & ISING_FLAG_FP16_SCAN) && cfg->form != ISING_FORM_SPLIT_BF16)
         return fail(ISING_ERR_INVALID_ARG, "the FP16 scan belongs to the split form");
     if ((cfg->flags & ISING_FLAG_RECORD_PROPOSALS) && cfg->form != ISING_FORM_LEARNED)
@@ -237,11 +246,18 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
         if (bound > 16777216.0)
             return fail(ISING_ERR_INVALID_ARG, "instance %d: sum |J_ij| + sum |h_i| = %g exceeds 2^24", b, bound);
         const int W = words_of(n);
+        int downs0 = -1;
         for (int l = 0; l < L; ++l) {
             const uint64_t* x = init_bits[b] + (size_t)l * W;
             const int tail = n & 63;
             if (tail && (x[W - 1] >> tail))
                 return fail(ISING_ERR_INVALID_ARG, "initial state %d of instance %d has bits at positions >= N", l, b);
+            int downs = 0;
+            for (int w = 0; w < W; ++w) downs += __builtin_popcountll(x[w]);
+            if (h1_exchange && downs0 >= 0 && downs != downs0)
+                return fail(ISING_ERR_INVALID_ARG, "exchanges conserve the number of down spins: the initial states of "
+                            "instance %d lie in different sectors (%d and %d down spins)", b, downs0, downs);
+            downs0 = downs;
         }
     }
 
@@ -425,6 +441,7 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     lay.Jn16 = dJn;
     lay.sb = sb ? 1 : 0;
     lay.h16 = h16 ? 1 : 0;
+    lay.h1 = h1_singles ? H1_SINGLES : (h1_exchange ? H1_EXCHANGE : H1_FLIPS);
     // states per scan item chosen each step unless given, tuned, or the scan
     // serves only the states the site bound leaves (or ranked ones)
     lay.sc_auto = (cfg->states_per_item == 0 && !sb && cfg->form != ISING_FORM_LEARNED) ? 1 : 0;
@@ -1032,9 +1049,26 @@ extern "C" int ising_search_set_search(ising_search_t* s, int32_t search, const 
     const int n = s->N[search / lay.L];
     const int W = words_of(n);
     const int tail = n & 63;
+    int sector = -1;
+    if (lay.h1 == H1_EXCHANGE) {
+        // the sector of the search: the number of down spins of its initial state
+        std::vector<uint64_t> w0(lay.Wmax);
+        HIP_TRY(hipMemcpyAsync(w0.data(), s->x0 + (size_t)search * lay.Wmax, sizeof(uint64_t) * lay.Wmax,
+                               hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        sector = 0;
+        for (int w = 0; w < W; ++w) sector += __builtin_popcountll(w0[w]);
+    }
     for (int k = 0; k < count; ++k) {
         if (tail && (bits[(size_t)k * W + W - 1] >> tail))
             return fail(ISING_ERR_INVALID_ARG, "state %d has bits at positions >= N", k);
+        if (sector >= 0) {
+            int downs = 0;
+            for (int w = 0; w < W; ++w) downs += __builtin_popcountll(bits[(size_t)k * W + w]);
+            if (downs != sector)
+                return fail(ISING_ERR_INVALID_ARG, "state %d has %d down spins; the search's sector has %d", k, downs,
+                            sector);
+        }
         for (int q = 0; q < k; ++q)
             if (std::memcmp(bits + (size_t)k * W, bits + (size_t)q * W, W * sizeof(uint64_t)) == 0)
                 return fail(ISING_ERR_INVALID_ARG, "states %d and %d are equal", q, k);

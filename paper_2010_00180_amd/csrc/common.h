@@ -102,6 +102,10 @@ struct Layout {
     int* nm_code;            // [S][M] parent slot code
     uint32_t* nm_pair;       // [S][M] i | j << 16
     int* nm_slot;            // [S][M] slot taken by the new state
+    // the perturbation H1 that defines the neighbourhood (Sec. VI): H1_FLIPS
+    // single and pair flips (Eq. 16), H1_SINGLES single flips only, H1_EXCHANGE
+    // pair flips of unequal spins only (the XX interaction)
+    int h1;
     // split-bf16 form
     int form;                // 0 plain, 1 split-bf16
     const float* J32;        // per instance, fl32(4J) (same layout as J4)
@@ -146,6 +150,8 @@ struct Layout {
 enum { CTR_PAIRS = 0, CTR_SINGLES = 1, CTR_FRONTIER = 2, CTR_SURV = 3, CTR_RETRY = 4, CTR_STEPS = 5,
        CTR_FALLBACK = 6, CTR_SCORED = 7, CTR_LEARNED = 8, CTR_TRACE = 9, CTR_BOUNDED = 10 };
 constexpr int SB_CAP = 256;          // most sites a state may keep for the site-bound evaluation
+enum { H1_FLIPS = 0, H1_SINGLES = 1, H1_EXCHANGE = 2 };
+
 enum { FLAG_ACTIVE = 0, FLAG_OVERFLOW = 1, FLAG_STUCK = 2, FLAG_RETRY_MODE = 3, FLAG_FIRST = 4 };
 
 __host__ __device__ inline int words_of(int N) { return (N + 63) >> 6; }
@@ -199,6 +205,8 @@ __device__ inline int site_bound_pairs(const Layout& lay, int b, int s, int code
 {
     const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
     const double T = c - Em;
+    // the exchange neighbourhood has no single flips and only pairs of unequal spins
+    const bool xch = lay.h1 == H1_EXCHANGE;
     auto bit = [&](int i) -> uint32_t { return (uint32_t)((x[i >> 6] >> (i & 63)) & 1ull); };
     auto lane_rank = [&](uint64_t m) -> int {
         return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -251,7 +259,7 @@ __device__ inline int site_bound_pairs(const Layout& lay, int b, int s, int code
 #pragma unroll
         for (int k = 0; k < SB_AREG; ++k) {
             const int i = 64 * k + (int)lane;
-            if (i < N && Em + areg[k] <= c) hits |= 1u << k;
+            if (!xch && i < N && Em + areg[k] <= c) hits |= 1u << k;
             if (__builtin_amdgcn_ballot_w64((hits >> k) & 1u)) any_hit = true;
         }
         if (r > 32) {
@@ -285,7 +293,7 @@ __device__ inline int site_bound_pairs(const Layout& lay, int b, int s, int code
             }
             base += __builtin_popcountll(m);
             const double Ec = Em + a;
-            record(i < N && Ec <= c, Ec, (uint32_t)i | (SINGLE << 16));
+            record(!xch && i < N && Ec <= c, Ec, (uint32_t)i | (SINGLE << 16));
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -328,7 +336,7 @@ __device__ inline int site_bound_pairs(const Layout& lay, int b, int s, int code
                 const double sj = (e >> 15) ? -1.0 : 1.0;
                 jv[k] = j;
                 xv[k] = fma(sv4[BP[k]], sj * coupling(iv[BP[k]], j), sa[q]);
-                kp[k] = xv[k] <= T - av[BP[k]];
+                kp[k] = xv[k] <= T - av[BP[k]] && (!xch || sv4[BP[k]] != sj);
             }
         }
         // one atomic reserves the places of the state's singles and pairs
@@ -409,7 +417,7 @@ __device__ inline int site_bound_pairs(const Layout& lay, int b, int s, int code
                     const int i = (int)(ei & 0x7FFFu), j = (int)(ej & 0x7FFFu);
                     const double ai = sa[p];
                     xv[u] = fma((ei >> 15) ? -1.0 : 1.0, ((ej >> 15) ? -1.0 : 1.0) * coupling(i, j), sa[q]);
-                    kp[u] = xv[u] <= T - ai;
+                    kp[u] = xv[u] <= T - ai && (!xch || (ei >> 15) != (ej >> 15));
                     ev[u] = (Em + ai) + xv[u];
                     pr[u] = (uint32_t)i | ((uint32_t)j << 16);
                     cnt += kp[u] ? 1 : 0;

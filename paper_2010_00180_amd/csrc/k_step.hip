@@ -273,6 +273,24 @@ __device__ inline int pilot_diff(const uint64_t* xa, const uint64_t* xb, int W, 
     return n;
 }
 
+// Bitonic sort of one (value, index) per lane across the wave, ascending by
+// (value, index).
+__device__ inline void wave_sort64(double& best, int& bi, int lane)
+{
+    for (int k = 2; k <= 64; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const double ob = __shfl_xor(best, j, 64);
+            const int oi = __shfl_xor(bi, j, 64);
+            const bool other_less = ob < best || (ob == best && oi < bi);
+            // in an ascending run the lower lane of a pair keeps the smaller
+            const bool keep_small = ((lane & k) == 0) == ((lane & j) == 0);
+            if (other_less == keep_small) {
+                best = ob;
+                bi = oi;
+            }
+        }
+}
+
 __device__ inline void cand_sites(uint32_t id, int* out, int& n)
 {
     // id = pilot << 26 | single << 25 | i << 12 | j
@@ -349,19 +367,25 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
     const int N = lay.N[b], Np = lay.Npad[b];
     const int W = words_of(N);
     // a ranking step offers every single flip but only ranked pairs, so its
-    // pilots contribute their lightest single flips only
-    const int npil = ranked ? NPILOT : NPIL;
+    // pilots contribute their lightest single flips only; so do the pilots
+    // of the single-flip neighbourhood.  Pilots of the exchange neighbourhood
+    // offer pairs of one up and one down spin among their lightest sites.
+    const bool single_pilots = ranked || lay.h1 == H1_SINGLES;
+    const bool xch = lay.h1 == H1_EXCHANGE;
+    const int npil = single_pilots ? NPILOT : NPIL;
     const int np = nfresh < npil ? nfresh : npil;
     // few pilots take more sites each, up to twice M candidates as the pool allows
     int KW = PKW;
     while (KW < 64 && np * (KW * (KW + 1) / 2) < 2 * M && np * ((KW + 1) * (KW + 2) / 2) <= POOL) ++KW;
     if (KW > N) KW = N;
-    const int nc = ranked ? (N < PRANK ? N : PRANK) : KW * (KW + 1) / 2;
+    int KX = 8;   // exchange: up and down sites per pilot
+    while (KX < 64 && np * KX * KX < 2 * M && np * (KX + 1) * (KX + 1) <= POOL) ++KX;
+    const int nc = single_pilots ? (N < PRANK ? N : PRANK) : (xch ? KX * KX : KW * (KW + 1) / 2);
     if (nc * np < M) {   // too few candidates to bound anything
         if (threadIdx.x == 0) lay.cut[s] = ecut;
         return;
     }
-    if (ranked) {
+    if (single_pilots) {
         for (int p = 0; p < np; ++p) {
             const uint64_t* xp = lay.bits + (q0 + pslot[p]) * lay.Wmax;
             const double* Fp = lay.F + (q0 + pslot[p]) * lay.Npmax;
@@ -376,6 +400,75 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
                 pid[p * nc + t] = ((uint32_t)p << 26) | (1u << 25) | (idx[t] << 12);
             }
             __syncthreads();
+        }
+    } else if (xch) {
+        const double* Jb = J4 + lay.joff[b];
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        // the up and the down sites of each wave's pilot, in key/idx
+        double* const aW = key + 128 * wave;
+        uint32_t* const iW = idx + 128 * wave;
+        if (threadIdx.x == 0) tmp[1] = 0;
+        __syncthreads();
+        for (int p = wave; p < np; p += 4) {
+            const uint64_t* xp = lay.bits + (q0 + pslot[p]) * lay.Wmax;
+            const double* Fp = lay.F + (q0 + pslot[p]) * lay.Npmax;
+            const double Ep = lay.E[q0 + pslot[p]];
+            // the lane's lightest up site and lightest down site (first of equals)
+            const uint64_t xw = lane < W ? xp[lane] : 0ull;
+            double bu = INFINITY, bd = INFINITY;
+            int iu = 0x7FFFFFFF, id = 0x7FFFFFFF;
+            for (int i0 = 0; i0 < N; i0 += 512) {
+                double f[8];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) f[r] = Fp[min(i0 + 64 * r, Np - 64) + lane];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int ib = i0 + 64 * r, i = ib + lane;
+                    if (ib < N) {
+                        const bool neg = __builtin_amdgcn_inverse_ballot_w64(word_of_lane(xw, ib >> 6));
+                        const double a = -2.0 * (neg ? -1.0 : 1.0) * f[r];
+                        if (i < N && neg && a < bd) {
+                            bd = a;
+                            id = i;
+                        }
+                        if (i < N && !neg && a < bu) {
+                            bu = a;
+                            iu = i;
+                        }
+                    }
+                }
+            }
+            wave_sort64(bu, iu, lane);
+            wave_sort64(bd, id, lane);
+            const int cu = __builtin_popcountll(__builtin_amdgcn_ballot_w64(bu < INFINITY));
+            const int cd = __builtin_popcountll(__builtin_amdgcn_ballot_w64(bd < INFINITY));
+            if (cu < KX || cd < KX) {
+                if (lane == 0) atomicOr(&tmp[1], 1);   // too few sites of one spin: no pilot cut
+            }
+            if (lane < KX) {
+                aW[lane] = bu;
+                iW[lane] = (uint32_t)iu;
+                aW[64 + lane] = bd;
+                iW[64 + lane] = (uint32_t)id;
+            }
+            wave_sync();
+            if (cu >= KX && cd >= KX) {
+                for (int t = lane; t < nc; t += 64) {
+                    const int a = t / KX, c = t % KX;
+                    int i = (int)iW[a], j = (int)iW[64 + c];
+                    if (i > j) { const int x = i; i = j; j = x; }
+                    // one up and one down spin: s_i s_j = -1
+                    const double v = aW[a] + aW[64 + c] - Jb[(size_t)i * Np + j];
+                    pE[p * nc + t] = Ep + v;
+                    pid[p * nc + t] = ((uint32_t)p << 26) | ((uint32_t)i << 12) | (uint32_t)j;
+                }
+            }
+            wave_sync();   // aW is rewritten for the wave's next pilot
+        }
+        __syncthreads();
+        if (tmp[1]) {
+            if (threadIdx.x == 0) lay.cut[s] = ecut;
+            return;
         }
     } else {
         const double* Jb = J4 + lay.joff[b];
@@ -411,19 +504,7 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
                     }
                 }
             }
-            // bitonic sort of the 64 (a, i) across the wave, ascending
-            for (int k = 2; k <= 64; k <<= 1)
-                for (int j = k >> 1; j > 0; j >>= 1) {
-                    const double ob = __shfl_xor(best, j, 64);
-                    const int oi = __shfl_xor(bi, j, 64);
-                    const bool other_less = ob < best || (ob == best && oi < bi);
-                    // in an ascending run the lower lane of a pair keeps the smaller
-                    const bool keep_small = ((lane & k) == 0) == ((lane & j) == 0);
-                    if (other_less == keep_small) {
-                        best = ob;
-                        bi = oi;
-                    }
-                }
+            wave_sort64(best, bi, lane);
             if (lane < KW) {
                 aW[lane] = best;
                 iW[lane] = (uint32_t)bi;
@@ -539,6 +620,8 @@ __global__ __launch_bounds__(1024) void k_plan(Layout lay, long long* __restrict
     const int t = threadIdx.x;
     const int per = (lay.B + 1023) / 1024;
     const int b0 = t * per;
+    // single flips only: no pair is scanned
+    const bool scanned = lay.h1 != H1_SINGLES;
     __shared__ int sc_all;
     if (lay.sc_auto) {
         // states per scan item, chosen each step: the largest power of two up
@@ -547,7 +630,8 @@ __global__ __launch_bounds__(1024) void k_plan(Layout lay, long long* __restrict
         // states as the balance of the grid allows
         __shared__ long long wsum[1024];
         long long w = 0;
-        for (int b = b0; b < b0 + per && b < lay.B; ++b) w += (long long)lay.fr_count[b] * scan_tiles(lay, lay.N[b]);
+        for (int b = b0; b < b0 + per && b < lay.B; ++b)
+            w += scanned ? (long long)lay.fr_count[b] * scan_tiles(lay, lay.N[b]) : 0;
         wsum[t] = w;
         __syncthreads();
         for (int off = 512; off > 0; off >>= 1) {
@@ -569,11 +653,11 @@ __global__ __launch_bounds__(1024) void k_plan(Layout lay, long long* __restrict
         const long long Q = lay.lr_count[b];
         const long long N = lay.N[b];
         const int sc = lay.sc_auto ? sc_all : lay.scb[b];
-        items += (P + sc - 1) / sc * tiles_of((int)N);
+        items += scanned ? (P + sc - 1) / sc * tiles_of((int)N) : 0;
         fr += P + Q;
         lr += Q;
         // with the site bound the pairs are counted once the entries are sorted out
-        pairs += (lay.sb ? 0 : P * (N * (N - 1) / 2)) + Q * proposals_of(lay, N);
+        pairs += (lay.sb || !scanned ? 0 : P * (N * (N - 1) / 2)) + Q * proposals_of(lay, N);
         scored += Q * (N * (N - 1) / 2);
         singles += (P + Q) * N;
     }
@@ -599,7 +683,7 @@ __global__ __launch_bounds__(1024) void k_plan(Layout lay, long long* __restrict
         const long long P = lay.fr_count[b];
         const long long Q = lay.lr_count[b];
         const int sc = lay.sc_auto ? sc_all : lay.scb[b];
-        run_i += (P + sc - 1) / sc * tiles_of(lay.N[b]);
+        run_i += scanned ? (P + sc - 1) / sc * tiles_of(lay.N[b]) : 0;
         run_f += P + Q;
         run_l += Q;
     }
@@ -651,6 +735,7 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63;
     const int retry_mode = lay.flags[FLAG_RETRY_MODE];
+    const bool singles = lay.h1 != H1_EXCHANGE;
     // XCD x (blocks x, x + 8, ...) takes the x-th contiguous eighth of the
     // entries, so the states it prepares at once share one L2 for their
     // couplings
@@ -723,8 +808,10 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
                     const double a = i < N ? -2.0 * (neg ? -1.0 : 1.0) * Fv[r] : 0.0;
                     ar[r] = a;
                     A[i] = a;
-                    // a ranked state's singles go with its pairs
-                    nhit += __builtin_popcountll(__builtin_amdgcn_ballot_w64(!ranked && i < N && Em + a <= c));
+                    // a ranked state's singles go with its pairs; the exchange
+                    // neighbourhood has no single flips
+                    nhit += __builtin_popcountll(
+                        __builtin_amdgcn_ballot_w64(singles && !ranked && i < N && Em + a <= c));
                 }
             }
             if (nhit) {
@@ -735,7 +822,7 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
                 for (int r = 0; r < PREP_BLOCKS; ++r) {
                     const int i = i0 + 64 * r + (int)lane;
                     const double Ec = Em + ar[r];
-                    const bool hit = i < N && Ec <= c;
+                    const bool hit = singles && i < N && Ec <= c;
                     const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
                     if (m) {
                         if (hit) {
@@ -789,6 +876,10 @@ __device__ inline void flush_stage(const Layout& lay, Surv* stage, int& n, int s
     n = 0;
 }
 
+// XCH: the exchange neighbourhood; a pair counts only when its two spins differ
+// (the running minimum still covers every pair of the group, so it only
+// admits groups; the exact pass applies the condition).
+template <bool XCH>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_scan(Layout lay, const double* __restrict__ J4,
                                              const double* __restrict__ Abuf,
                                              const FrRec* __restrict__ recs,
@@ -930,7 +1021,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 #pragma unroll
                             for (int u = 0; u < 8; ++u) {
                                 const double x = fma(si, __longlong_as_double((long long)Jb[g + u]), a8[u]);
-                                const uint64_t m = __builtin_amdgcn_ballot_w64(x <= rr);
+                                bool pass = x <= rr;
+                                if (XCH) pass = pass && ((si < 0.0) != (((wj >> (g + u)) & 1u) != 0));
+                                const uint64_t m = __builtin_amdgcn_ballot_w64(pass);
                                 if (m) {
                                     if (nstage > STAGE - 64) flush_stage(lay, stage, nstage, s);
                                     if ((m >> lane) & 1ull) {
@@ -1863,8 +1956,13 @@ hipError_t launch_prep(const Layout& lay, hipStream_t st, bool count)
 hipError_t launch_scan(const Layout& lay, int scan_grid, hipStream_t st)
 {
     if (lay.form == 1) return launch_scan32(lay, scan_grid, st);
-    hipLaunchKernelGGL(k_scan, dim3(scan_grid), dim3(64), 0, st, lay, lay.J4, (const double*)lay.A,
-                       (const FrRec*)lay.rec, (const uint64_t*)lay.fbits);
+    if (lay.h1 == H1_SINGLES) return hipSuccess;   // no pair flips to scan
+    if (lay.h1 == H1_EXCHANGE)
+        hipLaunchKernelGGL(k_scan<true>, dim3(scan_grid), dim3(64), 0, st, lay, lay.J4, (const double*)lay.A,
+                           (const FrRec*)lay.rec, (const uint64_t*)lay.fbits);
+    else
+        hipLaunchKernelGGL(k_scan<false>, dim3(scan_grid), dim3(64), 0, st, lay, lay.J4, (const double*)lay.A,
+                           (const FrRec*)lay.rec, (const uint64_t*)lay.fbits);
     return hipGetLastError();
 }
 

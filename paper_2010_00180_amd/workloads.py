@@ -157,6 +157,20 @@ def custom(Ns: Sequence[int], L: int, M: int, config: int = 9, dist: str = "sk",
     return Workload(f"custom_{dist}", config, inst, M=M, L=L)
 
 
+def in_sector(w: Workload, n_down: Sequence[int], seed: int = 0) -> Workload:
+    """The same instances with new initial states: for instance b, L states
+    with exactly n_down[b] down spins each, at uniformly drawn sites (one
+    sector of the total sigma^z per instance, for the exchange neighbourhood)."""
+    out = []
+    for k, inst in enumerate(w.instances):
+        rng = np.random.Generator(np.random.PCG64(seed_for(w.config, 700 + 31 * seed + k)))
+        sigma = np.zeros((w.L, inst.N), dtype=np.int64)
+        for l in range(w.L):
+            sigma[l, rng.choice(inst.N, int(n_down[k]), replace=False)] = 1
+        out.append(dataclasses.replace(inst, init_bits=pack_bits(sigma)))
+    return Workload(w.name + "_sector", w.config, out, M=w.M, L=w.L)
+
+
 # Initial parameters of the learned form's scoring network (4545 values in the
 # order W1[64][4], b1[64], W2[64][64], b2[64], w3[64], b3): a seeded He-style
 # draw, used as the starting point of training and as an untrained baseline.

@@ -50,7 +50,8 @@ def _good(N=10, L=2):
 
 
 @pytest.mark.parametrize("case", ["M0", "Mbig", "form", "flags", "L0", "N0", "Nbig", "asym", "diag",
-                                  "nan", "offgrid", "stray", "bound"])
+                                  "nan", "offgrid", "stray", "bound", "h1_both", "h1_split", "h1_sb", "sector",
+                                  "unknown_flag"])
 def test_init_rejects_invalid_arguments(case):
     inst = _good()
     J, h, x = inst.J.copy(), inst.h.copy(), inst.init_bits.copy()
@@ -64,6 +65,19 @@ def test_init_rejects_invalid_arguments(case):
         cfg.form = 7
     elif case == "flags":
         cfg.flags = 4
+    elif case == "h1_both":
+        cfg.flags = binding.FLAG_SINGLE_FLIPS | binding.FLAG_EXCHANGE
+    elif case == "h1_split":
+        cfg.flags = binding.FLAG_SINGLE_FLIPS
+        cfg.form = binding.FORM_SPLIT_BF16
+    elif case == "h1_sb":
+        cfg.flags = binding.FLAG_SINGLE_FLIPS | binding.FLAG_SITE_BOUND
+    elif case == "sector":
+        cfg.flags = binding.FLAG_EXCHANGE
+        x[0, 0] = np.uint64(0b1)
+        x[1, 0] = np.uint64(0b11)
+    elif case == "unknown_flag":
+        cfg.flags = 32
     elif case == "L0":
         L = 0
     elif case == "N0":

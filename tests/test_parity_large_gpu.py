@@ -60,12 +60,12 @@ def index_of_states(bits):
     return {bytes(np.ascontiguousarray(b).tobytes()): k for k, b in enumerate(bits)}
 
 
-def oracle_next(s, inst, M, before, sid, learned, literal=True):
+def oracle_next(s, inst, M, before, sid, learned, literal=True, h1=0):
     """The oracle's step from the GPU's set `before` of search sid; for the
     learned form, from the proposals the GPU recorded in its last step."""
     bb, bE, bf = before
     if not learned:
-        return oracle.step(inst.J, inst.h, M, bb, bE, bf, literal=literal, fields=True)
+        return oracle.step(inst.J, inst.h, M, bb, bE, bf, literal=literal, fields=True, h1=h1)
     mode, props = s.get_proposals(sid)
     if mode == 1:
         return oracle.step(inst.J, inst.h, M, bb, bE, literal=True, fields=True)
@@ -75,7 +75,7 @@ def oracle_next(s, inst, M, before, sid, learned, literal=True):
     return oracle.step_proposed(inst.J, inst.h, M, bb, bE, par, [c for _, c in props], fields=True)
 
 
-def large_parity(w, tag, checked, every=(), cap=3000, scorer=None, params=None, autotune=False, **kw):
+def large_parity(w, tag, checked, every=(), cap=3000, scorer=None, params=None, autotune=False, h1=0, **kw):
     """Step a handle to the end; check the sampled searches against the oracle
     at the selected steps (the searches in `every` at every step); return the
     handle's statistics."""
@@ -107,15 +107,15 @@ def large_parity(w, tag, checked, every=(), cap=3000, scorer=None, params=None, 
                 continue
             stops = not after[2].any()
             if k in every:
-                o = oracle_next(s, inst, w.M, before, k, learned, literal=False)
+                o = oracle_next(s, inst, w.M, before, k, learned, literal=False, h1=h1)
                 same(after, o, f"{tag} search {k} step {t}")
                 n_checks += 1
             elif t <= 3 or t % 20 == 0 or stops:
                 if stops and not learned and last_checked[k] < t - 1 and prev is not None:
                     # the last step that brought new states
-                    same(before, oracle_next(s, inst, w.M, prev, k, False), f"{tag} search {k} step {t - 1}")
+                    same(before, oracle_next(s, inst, w.M, prev, k, False, h1=h1), f"{tag} search {k} step {t - 1}")
                     n_checks += 1
-                o = oracle_next(s, inst, w.M, before, k, learned)
+                o = oracle_next(s, inst, w.M, before, k, learned, h1=h1)
                 same(after, o, f"{tag} search {k} step {t}")
                 last_checked[k] = t
                 n_checks += 1
@@ -131,7 +131,7 @@ def large_parity(w, tag, checked, every=(), cap=3000, scorer=None, params=None, 
     for k in checked:
         inst = w.instances[k // w.L]
         gb, gE, _ = s.get_search(k)
-        _, _, _, nn = oracle.step(inst.J, inst.h, w.M, gb, gE, literal=True, fields=True)
+        _, _, _, nn = oracle.step(inst.J, inst.h, w.M, gb, gE, literal=True, fields=True, h1=h1)
         assert nn == 0, f"{tag} search {k}: final set is not a fixed point of the exact step"
     # the Alg. 4 merge of every instance from the GPU's final sets
     for b, inst in enumerate(w.instances):
