@@ -70,6 +70,12 @@ def load(path: str):
     L.qo_search_h1.restype = ctypes.c_int
     L.qo_search_h1.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                ctypes.c_int, _u64p, _u64p, _dp, _ip, _ip]
+    L.qo_bf_search.restype = ctypes.c_int
+    L.qo_bf_search.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _u64p,
+                               _u64p, _dp, _u8p, _ip, _ip, _ip]
+    L.qo_bf_multi.restype = ctypes.c_int
+    L.qo_bf_multi.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                              _u64p, _u64p, _dp, _ip, _ip]
     L.qo_num_threads.restype = ctypes.c_int
     L.qo_num_threads.argtypes = []
     return L
@@ -261,3 +267,47 @@ def brute_lowest(J, h, K):
 
 def num_threads() -> int:
     return lib().qo_num_threads()
+
+
+def bf_search(J, h, K, I, x0, h1=H1_FLIPS):
+    """Alg. 3 (with Alg. 2's list update) from x0, a list of K + 1 entries and I
+    iterations.  Returns (bits (n, W), E (n,), used (n,), born (n,), expanded):
+    the real entries in list order and the number of iterations that expanded
+    a state."""
+    J, h = _prep(J, h)
+    N = len(h)
+    W = _W(N)
+    x0 = np.ascontiguousarray(x0, dtype=np.uint64).reshape(W)
+    cap = K + 1
+    ob = np.zeros((cap, W), dtype=np.uint64)
+    oE = np.zeros(cap, dtype=np.float64)
+    ou = np.zeros(cap, dtype=np.uint8)
+    obn = np.zeros(cap, dtype=np.int32)
+    nn = ctypes.c_int(0)
+    ex = ctypes.c_int(0)
+    r = lib().qo_bf_search(N, _d(J), _d(h), int(h1), int(K), int(I), _u64(x0), _u64(ob), _d(oE),
+                           ou.ctypes.data_as(_u8p), obn.ctypes.data_as(_ip), ctypes.byref(nn), ctypes.byref(ex))
+    if r < 0:
+        raise MemoryError("qo_bf_search failed")
+    k = nn.value
+    return ob[:k], oE[:k], ou[:k], obn[:k], ex.value
+
+
+def bf_multi(J, h, K, I, x0s, h1=H1_FLIPS):
+    """Alg. 4: len(x0s) searches merged.  Returns (bits, E, expanded per search)."""
+    J, h = _prep(J, h)
+    N = len(h)
+    W = _W(N)
+    x0s = np.ascontiguousarray(x0s, dtype=np.uint64).reshape(-1, W)
+    L = x0s.shape[0]
+    cap = K + 1
+    ob = np.zeros((cap, W), dtype=np.uint64)
+    oE = np.zeros(cap, dtype=np.float64)
+    ex = np.zeros(L, dtype=np.int32)
+    nn = ctypes.c_int(0)
+    r = lib().qo_bf_multi(N, _d(J), _d(h), int(h1), int(K), int(I), L, _u64(x0s), _u64(ob), _d(oE),
+                          ctypes.byref(nn), ex.ctypes.data_as(_ip))
+    if r < 0:
+        raise MemoryError("qo_bf_multi failed")
+    k = nn.value
+    return ob[:k], oE[:k], ex

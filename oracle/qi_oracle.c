@@ -564,3 +564,188 @@ int qo_num_threads(void)
     return 1;
 #endif
 }
+
+/*
+ * ------------------------------------------------------------------ best-first search (Sec. III)
+ * The paper's own sequential form of the method: Alg. 3 (QI single search)
+ * with the list update of Alg. 2, and Alg. 4 (QI multi search).
+ *
+ * The list holds K + 1 entries in energy order; equal energies keep their
+ * order of arrival, because a new entry goes after every entry of equal
+ * energy.  Entries start as placeholders (the largest integer and the largest
+ * real number); each real entry carries a flag telling whether it has been
+ * expanded.  A flipped state enters when it is not in the list and its energy
+ * is below the last entry's, which it then replaces.
+ *
+ * Alg. 3: for each of I iterations, the first entry in energy order that has
+ * not been expanded is marked and expanded: its single flips (sites 0 .. N-1)
+ * and then its pair flips ((0,1), (0,2), .., (N-2,N-1)) are offered to the
+ * list one after the other, each with its energy from the parent's in O(N).
+ * Readings: a placeholder is never expanded (when every real entry has been
+ * expanded the iteration does nothing); h1 selects the flips offered as in
+ * offer_children (1: single flips only; 2: exchanges of unequal spins, the
+ * exchange of two equal spins giving back the parent, which the list already
+ * holds).
+ *
+ * Alg. 4: L single searches; the first one's list is the result list, and the
+ * entries of every later list, in that list's energy order, are offered to it
+ * with the same rule (each state with its own energy and flag).
+ */
+typedef struct {
+    int cap;            /* K + 1 */
+    int W;
+    double *E;          /* energy order; +INFINITY for a placeholder */
+    uint64_t *x;        /* words of each entry */
+    uint8_t *real;      /* 0 for a placeholder */
+    uint8_t *used;      /* expanded */
+    int *born;          /* iteration at which the entry arrived (0 = initial) */
+} bflist;
+
+static int bflist_init(bflist *B, int cap, int W)
+{
+    B->cap = cap; B->W = W;
+    B->E = (double *)malloc(sizeof(double) * (size_t)cap);
+    B->x = (uint64_t *)calloc((size_t)cap * W, sizeof(uint64_t));
+    B->real = (uint8_t *)calloc((size_t)cap, 1);
+    B->used = (uint8_t *)calloc((size_t)cap, 1);
+    B->born = (int *)calloc((size_t)cap, sizeof(int));
+    if (!B->E || !B->x || !B->real || !B->used || !B->born) return -1;
+    for (int k = 0; k < cap; ++k) B->E[k] = INFINITY;
+    return 0;
+}
+
+static void bflist_free(bflist *B)
+{
+    free(B->E); free(B->x); free(B->real); free(B->used); free(B->born);
+}
+
+static int bflist_has(const bflist *B, const uint64_t *x)
+{
+    for (int k = 0; k < B->cap; ++k)
+        if (B->real[k] && memcmp(B->x + (size_t)k * B->W, x, sizeof(uint64_t) * B->W) == 0) return 1;
+    return 0;
+}
+
+/* Offer a state that is not in the list: it enters if E is below the last
+   entry's energy, after every entry of equal or lower energy. */
+static void bflist_offer(bflist *B, const uint64_t *x, double E, uint8_t used, int born)
+{
+    int last = B->cap - 1;
+    if (!(E < B->E[last])) return;
+    int pos = 0;
+    while (pos < last && B->E[pos] <= E) ++pos;
+    for (int k = last; k > pos; --k) {
+        B->E[k] = B->E[k - 1];
+        B->real[k] = B->real[k - 1];
+        B->used[k] = B->used[k - 1];
+        B->born[k] = B->born[k - 1];
+        memcpy(B->x + (size_t)k * B->W, B->x + (size_t)(k - 1) * B->W, sizeof(uint64_t) * B->W);
+    }
+    B->E[pos] = E;
+    B->real[pos] = 1;
+    B->used[pos] = used;
+    B->born[pos] = born;
+    memcpy(B->x + (size_t)pos * B->W, x, sizeof(uint64_t) * B->W);
+}
+
+static void bf_single(int N, const double *J, const double *h, int h1, int I, const uint64_t *x0,
+                      bflist *B, uint64_t *child, int *expanded)
+{
+    int W = words_of(N);
+    bflist_offer(B, x0, qo_energy(N, J, h, x0), 0, 0);
+    int done = 0;
+    for (int it = 1; it <= I; ++it) {
+        int k = 0;
+        while (k < B->cap && !(B->real[k] && !B->used[k])) ++k;
+        if (k == B->cap) continue;
+        B->used[k] = 1;
+        ++done;
+        uint64_t *x = child + W;   /* the parent, kept apart from the list (its entry may move) */
+        memcpy(x, B->x + (size_t)k * W, sizeof(uint64_t) * W);
+        double Ex = B->E[k];
+        int sites[2];
+        for (int i = 0; i < N && h1 != 2; ++i) {
+            memcpy(child, x, sizeof(uint64_t) * W);
+            child[i >> 6] ^= (uint64_t)1 << (i & 63);
+            if (bflist_has(B, child)) continue;
+            sites[0] = i;
+            bflist_offer(B, child, Ex + qo_flip_change(N, J, h, x, 1, sites), 0, it);
+        }
+        for (int i = 0; i < N && h1 != 1; ++i) {
+            for (int j = i + 1; j < N; ++j) {
+                if (h1 == 2 && spin_of(x, i) == spin_of(x, j)) continue;
+                memcpy(child, x, sizeof(uint64_t) * W);
+                child[i >> 6] ^= (uint64_t)1 << (i & 63);
+                child[j >> 6] ^= (uint64_t)1 << (j & 63);
+                if (bflist_has(B, child)) continue;
+                sites[0] = i; sites[1] = j;
+                bflist_offer(B, child, Ex + qo_flip_change(N, J, h, x, 2, sites), 0, it);
+            }
+        }
+    }
+    *expanded = done;
+}
+
+static void bf_copy_out(const bflist *B, uint64_t *out_x, double *out_E, uint8_t *out_used, int *out_born,
+                        int *n_out)
+{
+    int n = 0;
+    for (int k = 0; k < B->cap; ++k) {
+        if (!B->real[k]) continue;
+        memcpy(out_x + (size_t)n * B->W, B->x + (size_t)k * B->W, sizeof(uint64_t) * B->W);
+        out_E[n] = B->E[k];
+        if (out_used) out_used[n] = B->used[k];
+        if (out_born) out_born[n] = B->born[k];
+        ++n;
+    }
+    *n_out = n;
+}
+
+/*
+ * Alg. 3 from x0 with a list of K + 1 entries and I iterations.  Output: the
+ * real entries in list order (at most K + 1): words, energies, expanded flags,
+ * arrival iterations; *expanded = iterations that expanded a state.  Returns
+ * 0, or -1 on allocation failure.
+ */
+int qo_bf_search(int N, const double *J, const double *h, int h1, int K, int I, const uint64_t *x0,
+                 uint64_t *out_x, double *out_E, uint8_t *out_used, int *out_born, int *n_out, int *expanded)
+{
+    int W = words_of(N);
+    bflist B = {0};
+    uint64_t *child = (uint64_t *)malloc(sizeof(uint64_t) * 2 * W);
+    if (!child || bflist_init(&B, K + 1, W) != 0) { free(child); bflist_free(&B); return -1; }
+    bf_single(N, J, h, h1, I, x0, &B, child, expanded);
+    bf_copy_out(&B, out_x, out_E, out_used, out_born, n_out);
+    free(child);
+    bflist_free(&B);
+    return 0;
+}
+
+/*
+ * Alg. 4: L searches from x0[l] (L*W words), merged.  Output as qo_bf_search
+ * (the merged list); expanded[l] per search.  Returns 0 or -1.
+ */
+int qo_bf_multi(int N, const double *J, const double *h, int h1, int K, int I, int L, const uint64_t *x0,
+                uint64_t *out_x, double *out_E, int *n_out, int *expanded)
+{
+    int W = words_of(N);
+    bflist R = {0}, B = {0};
+    uint64_t *child = (uint64_t *)malloc(sizeof(uint64_t) * 2 * W);
+    int rc = -1;
+    if (child && bflist_init(&R, K + 1, W) == 0 && bflist_init(&B, K + 1, W) == 0) {
+        bf_single(N, J, h, h1, I, x0, &R, child, &expanded[0]);
+        for (int l = 1; l < L; ++l) {
+            for (int k = 0; k < B.cap; ++k) { B.E[k] = INFINITY; B.real[k] = 0; B.used[k] = 0; B.born[k] = 0; }
+            bf_single(N, J, h, h1, I, x0 + (size_t)l * W, &B, child, &expanded[l]);
+            for (int k = 0; k < B.cap; ++k)
+                if (B.real[k] && !bflist_has(&R, B.x + (size_t)k * W))
+                    bflist_offer(&R, B.x + (size_t)k * W, B.E[k], B.used[k], B.born[k]);
+        }
+        bf_copy_out(&R, out_x, out_E, NULL, NULL, n_out);
+        rc = 0;
+    }
+    free(child);
+    bflist_free(&R);
+    bflist_free(&B);
+    return rc;
+}
