@@ -372,6 +372,45 @@ int ising_mlp_train(float *params, float *m, float *v, const float *feat, const 
 int ising_brute_lowest(int32_t n_inst, const int32_t *N, const double *const *J, const double *const *h,
                        int32_t K, uint64_t *bits_out, double *E_out, int32_t *count, void *stream);
 
+/*
+ * ---------------------------------------------------------------- best-first search (Alg. 2-4)
+ * The paper's own sequential form of the method (Sec. III), one GPU block per
+ * search: Alg. 3 (QI single search) keeps a list of K + 1 entries in energy
+ * order (equal energies in order of arrival) and, I times, expands the first
+ * entry not yet expanded, offering its single flips (sites 0 .. N-1) and then
+ * its pair flips ((0,1), (0,2), .., (N-2,N-1)) one after the other with the
+ * update of Alg. 2 (a state enters when the list does not hold it and its
+ * energy is below the last entry's); Alg. 4 (QI multi search) runs L such
+ * searches and merges their lists, in order, with the same update.  Readings:
+ * placeholder entries are never expanded; the merge offers every state with
+ * its own energy.  flags may hold ISING_FLAG_SINGLE_FLIPS or
+ * ISING_FLAG_EXCHANGE (the other H1 choices of Sec. VI; exchanges of equal
+ * spins give the parent back and are skipped).
+ *
+ *   n_inst, N, J, h   as for ising_search_init, with 1 <= N[b] <= 64
+ *   L                 searches per instance; init_bits[b] holds L words
+ *   K, I              list of K + 1 entries (K + 1 <= 2048, fewer with large N:
+ *                     the list, its double buffer and the children must fit
+ *                     in 160 KB of LDS), I >= 0 iterations
+ *   merged_bits/E     caller buffers of n_inst*(K+1): instance b's merged list
+ *                     at b*(K+1), merged_count[b] real entries, in list order
+ *   search_*          NULL, or caller buffers of n_inst*L*(K+1) (count: n_inst*L)
+ *                     with each search's own final list, its expanded flags
+ *                     and the iteration at which each entry arrived (0 = the
+ *                     initial state); search_bits, search_E and search_count
+ *                     go together, used and born may be NULL
+ *   expanded          NULL or n_inst*L: iterations that expanded a state
+ *   kernel_ms         NULL or the device time of the search and merge kernels
+ * Device memory is allocated for the call and freed before it returns; the
+ * call synchronises the stream.  Errors: INVALID_ARG, NO_DEVICE,
+ * OUT_OF_MEMORY, HIP.
+ */
+int ising_bestfirst(int32_t n_inst, const int32_t *N, const double *const *J, const double *const *h, int32_t L,
+                    const uint64_t *const *init_bits, int32_t K, int32_t I, int32_t flags, uint64_t *merged_bits,
+                    double *merged_E, int32_t *merged_count, uint64_t *search_bits, double *search_E,
+                    uint8_t *search_used, int32_t *search_born, int32_t *search_count, int32_t *expanded,
+                    float *kernel_ms, void *stream);
+
 /* Frees all device memory of the handle.  NULL is accepted. */
 void ising_search_destroy(ising_search_t *s);
 

@@ -64,6 +64,7 @@ EXPORTED = (
     "ising_mlp_train",
     "ising_mlp_loss_grad_noalloc",
     "ising_brute_lowest",
+    "ising_bestfirst",
 )
 
 
@@ -171,6 +172,9 @@ def load(path: str = LIB_PATH):
     L.ising_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
     L.ising_mlp_loss_grad.restype = ctypes.c_int
     L.ising_mlp_loss_grad.argtypes = [vp, vp, vp, i64, f32, vp, vp, vp, i64, vp]
+    L.ising_bestfirst.restype = ctypes.c_int
+    L.ising_bestfirst.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(vp), i32,
+                                  ctypes.POINTER(vp), i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.ising_brute_lowest.restype = ctypes.c_int
     L.ising_brute_lowest.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp, vp,
                                      ctypes.POINTER(i32), vp]
@@ -235,6 +239,60 @@ def brute_lowest(Js, hs, K: int, stream: Optional[int] = None):
     _check(L.ising_brute_lowest(B, Narr, Jp, hp, int(K), bits.ctypes.data, E.ctypes.data, cnt,
                                 ctypes.c_void_p(stream) if stream else None))
     return [(bits[b, :cnt[b]].reshape(-1, 1).copy(), E[b, :cnt[b]].copy()) for b in range(B)]
+
+
+def bestfirst(Js, hs, init_bits, K: int, I: int, flags: int = 0, searches: bool = False,
+              stream: Optional[int] = None):
+    """Alg. 3 / Alg. 4 on the GPU.  init_bits[b]: L initial states (one word
+    each, N <= 64).  Returns a dict: 'merged' = [(bits (n, 1), E (n,))] per
+    instance, 'expanded' (B, L), 'kernel_ms'; with searches=True also
+    'searches' = [[(bits, E, used, born)] * L] per instance."""
+    L = load()
+    B = len(hs)
+    keep = []
+    Jp = (ctypes.c_void_p * B)()
+    hp = (ctypes.c_void_p * B)()
+    xp = (ctypes.c_void_p * B)()
+    Ns = []
+    nL = None
+    for b in range(B):
+        Jb = np.ascontiguousarray(Js[b], dtype=np.float64)
+        hb = np.ascontiguousarray(hs[b], dtype=np.float64)
+        xb = np.ascontiguousarray(np.asarray(init_bits[b], dtype=np.uint64).reshape(-1))
+        if nL is None:
+            nL = len(xb)
+        elif len(xb) != nL:
+            raise ValueError("every instance needs the same number of initial states")
+        keep += [Jb, hb, xb]
+        Jp[b], hp[b], xp[b] = Jb.ctypes.data, hb.ctypes.data, xb.ctypes.data
+        Ns.append(len(hb))
+    K1 = int(K) + 1
+    mb = np.zeros((B, K1), np.uint64)
+    mE = np.zeros((B, K1), np.float64)
+    mc = np.zeros(B, np.int32)
+    ex = np.zeros((B, nL), np.int32)
+    ms = ctypes.c_float(0.0)
+    if searches:
+        sb = np.zeros((B, nL, K1), np.uint64)
+        sE = np.zeros((B, nL, K1), np.float64)
+        su = np.zeros((B, nL, K1), np.uint8)
+        sn = np.zeros((B, nL, K1), np.int32)
+        sc = np.zeros((B, nL), np.int32)
+        sptr = [sb.ctypes.data, sE.ctypes.data, su.ctypes.data, sn.ctypes.data, sc.ctypes.data]
+    else:
+        sptr = [None] * 5
+    if stream is None:
+        stream = current_stream_handle()
+    _check(L.ising_bestfirst(B, (ctypes.c_int32 * B)(*Ns), Jp, hp, int(nL), xp, int(K), int(I), int(flags),
+                             mb.ctypes.data, mE.ctypes.data, mc.ctypes.data, *sptr, ex.ctypes.data,
+                             ctypes.byref(ms), ctypes.c_void_p(stream) if stream else None))
+    out = {"merged": [(mb[b, :mc[b]].reshape(-1, 1).copy(), mE[b, :mc[b]].copy()) for b in range(B)],
+           "expanded": ex, "kernel_ms": ms.value}
+    if searches:
+        out["searches"] = [[(sb[b, l, :sc[b, l]].reshape(-1, 1).copy(), sE[b, l, :sc[b, l]].copy(),
+                             su[b, l, :sc[b, l]].copy(), sn[b, l, :sc[b, l]].copy()) for l in range(nL)]
+                           for b in range(B)]
+    return out
 
 
 class IsingSearch:

@@ -7,7 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = ["csrc/api.hip", "csrc/k_init.hip", "csrc/k_step.hip", "csrc/k_split.hip", "csrc/k_learn.hip",
-           "csrc/k_mlp.hip", "csrc/k_brute.hip"]
+           "csrc/k_mlp.hip", "csrc/k_brute.hip",
+           "csrc/k_bestfirst.hip"]
 OUT = os.path.join(HERE, "lib", "libising_search.so")
 
 HIPCC_FLAGS = [

@@ -1658,3 +1658,178 @@ extern "C" int ising_brute_lowest(int32_t n_inst, const int32_t* N, const double
     }
     return ISING_OK;
 }
+
+// ------------------------------------------------------------------ best-first search (Alg. 2-4)
+extern "C" int ising_bestfirst(int32_t n_inst, const int32_t* N, const double* const* J, const double* const* h,
+                               int32_t L, const uint64_t* const* init_bits, int32_t K, int32_t I, int32_t flags,
+                               uint64_t* merged_bits, double* merged_E, int32_t* merged_count,
+                               uint64_t* search_bits, double* search_E, uint8_t* search_used, int32_t* search_born,
+                               int32_t* search_count, int32_t* expanded, float* kernel_ms, void* stream)
+{
+    g_err.clear();
+    if (n_inst < 1) return fail(ISING_ERR_INVALID_ARG, "n_inst=%d < 1", n_inst);
+    if (L < 1) return fail(ISING_ERR_INVALID_ARG, "L=%d < 1", L);
+    if ((long long)n_inst * L > (1 << 24)) return fail(ISING_ERR_INVALID_ARG, "too many searches");
+    if (K < 0 || K + 1 > BFS_K1MAX) return fail(ISING_ERR_INVALID_ARG, "K=%d outside [0, %d]", K, BFS_K1MAX - 1);
+    if (I < 0) return fail(ISING_ERR_INVALID_ARG, "I=%d < 0", I);
+    if (flags & ~(ISING_FLAG_SINGLE_FLIPS | ISING_FLAG_EXCHANGE))
+        return fail(ISING_ERR_INVALID_ARG, "flags 0x%x: only the H1 flags apply", flags);
+    if ((flags & ISING_FLAG_SINGLE_FLIPS) && (flags & ISING_FLAG_EXCHANGE))
+        return fail(ISING_ERR_INVALID_ARG, "single flips and exchanges are two different choices of H1");
+    if (!N || !J || !h || !init_bits || !merged_bits || !merged_E || !merged_count)
+        return fail(ISING_ERR_INVALID_ARG, "NULL array argument");
+    const int h1 = (flags & ISING_FLAG_SINGLE_FLIPS) ? H1_SINGLES : ((flags & ISING_FLAG_EXCHANGE) ? H1_EXCHANGE : H1_FLIPS);
+    int nmax = 0;
+    for (int b = 0; b < n_inst; ++b) {
+        if (N[b] < 1 || N[b] > BFS_NMAX)
+            return fail(ISING_ERR_INVALID_ARG, "N[%d]=%d outside [1, %d]", b, N[b], BFS_NMAX);
+        if (!J[b] || !h[b] || !init_bits[b]) return fail(ISING_ERR_INVALID_ARG, "NULL pointer for instance %d", b);
+        nmax = std::max(nmax, (int)N[b]);
+        const int n = N[b];
+        double bound = 0.0;
+        for (int i = 0; i < n; ++i) {
+            if (!on_grid(h[b][i]))
+                return fail(ISING_ERR_INVALID_ARG, "h[%d][%d]=%g is not a finite multiple of 2^-24", b, i, h[b][i]);
+            bound += std::fabs(h[b][i]);
+            if (J[b][(size_t)i * n + i] != 0.0)
+                return fail(ISING_ERR_INVALID_ARG, "J[%d] has a nonzero diagonal at %d", b, i);
+            for (int j = i + 1; j < n; ++j) {
+                const double v = J[b][(size_t)i * n + j];
+                if (!on_grid(v))
+                    return fail(ISING_ERR_INVALID_ARG, "J[%d][%d,%d]=%g is not a finite multiple of 2^-24", b, i, j, v);
+                if (v != J[b][(size_t)j * n + i])
+                    return fail(ISING_ERR_INVALID_ARG, "J[%d] is not symmetric at (%d,%d)", b, i, j);
+                bound += std::fabs(v);
+            }
+        }
+        if (bound > 16777216.0)
+            return fail(ISING_ERR_INVALID_ARG, "instance %d: sum |J_ij| + sum |h_i| = %g exceeds 2^24", b, bound);
+        for (int l = 0; l < L; ++l)
+            if (n < 64 && (init_bits[b][l] >> n))
+                return fail(ISING_ERR_INVALID_ARG, "initial state %d of instance %d has bits at positions >= N", l, b);
+    }
+    const int K1 = K + 1;
+    const int nchild = (h1 == H1_EXCHANGE ? 0 : nmax) + (h1 == H1_SINGLES ? 0 : nmax * (nmax - 1) / 2);
+    int C = 1;
+    while (C < std::max(nchild, K1)) C <<= 1;
+    const size_t lds = bestfirst_lds_bytes(K1, C);
+    if (lds > BFS_LDS_MAX)
+        return fail(ISING_ERR_INVALID_ARG, "a list of %d entries with N=%d needs %zu bytes of LDS (at most %zu)", K1,
+                    nmax, lds, BFS_LDS_MAX);
+    int rc = have_device();
+    if (rc != ISING_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = bestfirst_set_lds(lds);
+    if (e != hipSuccess) return fail(ISING_ERR_HIP, "the best-first kernels cannot use %zu bytes of LDS", lds);
+
+    const size_t S = (size_t)n_inst * L;
+    std::vector<long long> joff(n_inst);
+    long long jtot = 0;
+    for (int b = 0; b < n_inst; ++b) {
+        joff[b] = jtot;
+        jtot += (long long)N[b] * N[b];
+    }
+    BruteBufs buf;   // freed on every exit path
+    int *dN = nullptr, *dborn = nullptr, *dexp = nullptr;
+    long long* djoff = nullptr;
+    double *dJ = nullptr, *dh = nullptr, *dE = nullptr, *dmE = nullptr;
+    uint64_t *dx0 = nullptr, *dpsi = nullptr, *dmpsi = nullptr;
+    uint8_t* dused = nullptr;
+    if ((rc = buf.get(&dN, n_inst)) || (rc = buf.get(&djoff, n_inst)) || (rc = buf.get(&dJ, (size_t)jtot)) ||
+        (rc = buf.get(&dh, (size_t)n_inst * 64)) || (rc = buf.get(&dx0, S)) || (rc = buf.get(&dpsi, S * K1)) ||
+        (rc = buf.get(&dE, S * K1)) || (rc = buf.get(&dused, S * K1)) || (rc = buf.get(&dborn, S * K1)) ||
+        (rc = buf.get(&dexp, S)) || (rc = buf.get(&dmpsi, (size_t)n_inst * K1)) || (rc = buf.get(&dmE, (size_t)n_inst * K1)))
+        return rc;
+    {
+        std::vector<double> Jh((size_t)jtot), hh((size_t)n_inst * 64, 0.0);
+        std::vector<uint64_t> xh(S);
+        for (int b = 0; b < n_inst; ++b) {
+            std::memcpy(Jh.data() + joff[b], J[b], sizeof(double) * N[b] * N[b]);
+            std::memcpy(hh.data() + (size_t)b * 64, h[b], sizeof(double) * N[b]);
+            for (int l = 0; l < L; ++l) xh[(size_t)b * L + l] = init_bits[b][l];
+        }
+        HIP_TRY(hipMemcpyAsync(dN, N, sizeof(int) * n_inst, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(djoff, joff.data(), sizeof(long long) * n_inst, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(dJ, Jh.data(), sizeof(double) * Jh.size(), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(dh, hh.data(), sizeof(double) * hh.size(), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(dx0, xh.data(), sizeof(uint64_t) * S, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    BestFirstArgs a{};
+    a.L = L;
+    a.K1 = K1;
+    a.I = I;
+    a.C = C;
+    a.h1 = h1;
+    a.N = dN;
+    a.joff = djoff;
+    a.J = dJ;
+    a.h = dh;
+    a.x0 = dx0;
+    a.out_psi = dpsi;
+    a.out_E = dE;
+    a.out_used = dused;
+    a.out_born = dborn;
+    a.out_expanded = dexp;
+    a.merged_psi = dmpsi;
+    a.merged_E = dmE;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (kernel_ms) {
+        HIP_TRY(hipEventCreate(&e0));
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return fail(ISING_ERR_HIP, "hipEventCreate failed");
+        }
+        e = hipEventRecord(e0, st);
+    }
+    if (e == hipSuccess) e = launch_bestfirst(a, n_inst, lds, st);
+    if (e == hipSuccess && kernel_ms) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess && kernel_ms) *kernel_ms = (float)elapsed_ms(e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(ISING_ERR_HIP, "best-first launch failed: %s", hipGetErrorString(e));
+    // the real entries (E < +inf) in list order
+    std::vector<uint64_t> mp((size_t)n_inst * K1);
+    std::vector<double> mE((size_t)n_inst * K1);
+    HIP_TRY(hipMemcpy(mp.data(), dmpsi, sizeof(uint64_t) * mp.size(), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(mE.data(), dmE, sizeof(double) * mE.size(), hipMemcpyDeviceToHost));
+    for (int b = 0; b < n_inst; ++b) {
+        int n = 0;
+        for (int k = 0; k < K1; ++k) {
+            const size_t q = (size_t)b * K1 + k;
+            if (!(mE[q] < INFINITY)) break;
+            merged_bits[(size_t)b * K1 + n] = mp[q];
+            merged_E[(size_t)b * K1 + n] = mE[q];
+            ++n;
+        }
+        merged_count[b] = n;
+    }
+    if (expanded) HIP_TRY(hipMemcpy(expanded, dexp, sizeof(int) * S, hipMemcpyDeviceToHost));
+    if (search_bits || search_E || search_used || search_born || search_count) {
+        if (!search_bits || !search_E || !search_count)
+            return fail(ISING_ERR_INVALID_ARG, "search_bits, search_E and search_count go together");
+        std::vector<uint64_t> sp(S * K1);
+        std::vector<double> sE(S * K1);
+        std::vector<uint8_t> su(S * K1);
+        std::vector<int> sb(S * K1);
+        HIP_TRY(hipMemcpy(sp.data(), dpsi, sizeof(uint64_t) * sp.size(), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(sE.data(), dE, sizeof(double) * sE.size(), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(su.data(), dused, su.size(), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(sb.data(), dborn, sizeof(int) * sb.size(), hipMemcpyDeviceToHost));
+        for (size_t q = 0; q < S; ++q) {
+            int n = 0;
+            for (int k = 0; k < K1; ++k) {
+                const size_t o = q * K1 + k;
+                if (!(sE[o] < INFINITY)) break;
+                search_bits[q * K1 + n] = sp[o];
+                search_E[q * K1 + n] = sE[o];
+                if (search_used) search_used[q * K1 + n] = su[o];
+                if (search_born) search_born[q * K1 + n] = sb[o];
+                ++n;
+            }
+            search_count[q] = n;
+        }
+    }
+    return ISING_OK;
+}
