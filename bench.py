@@ -8,22 +8,39 @@ timed region starts.
 
 Workload: 120 instances, N = 600, J_ij ~ N(0,1)/sqrt(N), h_i ~ N(0,1) (both on
 the 2^-24 grid), M = 120 kept states, 64 initial states per instance.  The
-headline is the split-bf16 form with its pair scan in packed FP16 (initial
-local fields on bf16 matrix cores, FP16 pair scan with a proven slack, FP64
-re-score; kept sets identical to the FP64 form); the same form with the FP32
-scan and the plain FP64 form run the same workload for comparison; the
-learned-proposal form (network trained first on traces of other instances of
-the same shape) runs a bounded sample of it, next to the plain form on the
-same sample, and its miss rate is judged against full enumeration.  The
-*_bound forms run the plain and split forms with the site bound (only pair
-flips that can pass the cut are evaluated, kept sets identical): they give the
-shortest time to solution, not an evaluation rate.  Prints one JSON line.
+headline is the split-bf16 form at its own arithmetic: initial local fields
+from J = hi + lo on the bf16 matrix cores with FP32 accumulation, the pair scan
+in FP32 with a proven slack, FP64 re-score (kept sets identical to the FP64
+form).  The same workload also runs, one timed pass each: the split form with
+its packed-FP16 scan, the plain FP64 form, and the site-bound forms (only pair
+flips that can pass the cut are evaluated: the shortest time to solution).
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Further legs, each a line of the same JSON object:
+  tts          time to solution (Eq. 17) with p1 measured against a reference
+               energy per instance: the best energy of every form and of an
+               extended run (M = 240, L = 256), labelled best known, not certified;
+               and at the N = 24, M = 8, L = 4 shape against the exact ground
+               state from the GPU enumeration (p1 and the success rate r, Sec. IV)
+  learned      the learned-proposal form (network trained first on traces of
+               other N = 600 instances) on bounded samples at N = 600 and
+               N = 1000, next to the plain form on the same samples, with its
+               miss rate against full enumeration and its MFMA roofline
+  batching     one pass of the 480-instance uneven batch (N from 100 to 600,
+               L = 32), graph-replayed steps with autotuned scan tiles
+  h1           the single-flip and XX-exchange neighbourhoods of Sec. VI
+  bestfirst    the paper's own best-first search (Alg. 2-4) on its Sec. IV
+               setting (N <= 30, J and h uniform on [-1/2, 1/2], 120 instances
+               per N): p1, r and TTS against the GPU enumeration
+  spectrum     the low-energy spectrum study of Sec. V from the GPU
+               enumeration (E1 ~ N^{3/2}, the gap, ln k against E_k - E1)
+  cpu_baseline the CPU oracle timed on the host on a bounded sample
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
 """
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -32,23 +49,38 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "pair-flip ΔE evals/s + time-to-solution/instance at N=600,M=120 vs plain"
-# MI355X vector peaks as lane-operations per second (an FMA counted once):
-# FP64 78.6 TFLOP/s = 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 flops;
-# FP32 157.3 TFLOP/s, twice that (it needs packed FP32, which these kernels do
-# not use, so the FP32 scan can reach half of its peak).
+# MI355X vector peaks as lane-operations per second (an FMA counts once):
+# FP64 78.6 TFLOP/s = 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 flops per FMA,
+# so 39.3 T FP64 lane-ops/s; FP32 157.3 TFLOP/s, 78.6 T lane-ops/s (reached
+# only with packed FP32, which these kernels do not emit: their non-packed
+# FP32 issues at the FP64 rate); packed FP16 from the same unit counts with
+# two halves per lane, 78.6 T half-lane ops/s.
 VALU_LANE_OPS_PER_S = {"f64": 256 * 4 * 16 * 2.4e9, "f32": 2 * 256 * 4 * 16 * 2.4e9,
-                       # packed FP16: two halves per lane and cycle from the same unit counts
                        "f16": 2 * 256 * 4 * 16 * 2.4e9}
-OPS_PER_PAIR = 2          # fma(s_i, s_j 4J_ij, a_j) and the compare with T - a_i (a running minimum)
+# algorithmic VALU work of one pair flip's energy change and filter: the add
+# a_i + a_j, the signed coupling term (one FMA), the compare with the cut
+OPS_PER_PAIR = 3
 FORM_DTYPE = {"plain": "f64", "split_bf16": "f32", "split_fp16": "f16", "learned": "f64", "plain_bound": "f64",
-              "split_bf16_bound": "f64"}
+              "split_bf16_bound": "f64", "split_fp16_bound": "f64"}
+FORM_CODES = {"plain": 0, "split_bf16": 1, "split_fp16": 1, "learned": 2, "plain_bound": 0, "split_bf16_bound": 1,
+              "split_fp16_bound": 1}
+# the *_bound forms run with the site bound (only the pairs that can pass the
+# cut are evaluated; identical kept sets): a time-to-solution figure, not an
+# evaluation rate
+FORM_FLAGS = {"plain_bound": 2, "split_bf16_bound": 2, "split_fp16": 4, "split_fp16_bound": 6}
+SITE_BOUND_FORMS = ("plain_bound", "split_bf16_bound", "split_fp16_bound")
+SCAN_KERNEL = {"plain": "k_scan", "split_bf16": "k_scan32", "split_fp16": "k_scan16"}
+KERNEL_SOURCE = {"k_scan": "k_step.hip", "k_scan32": "k_split.hip", "k_scan16": "k_split.hip",
+                 "k_learn": "k_learn.hip"}
+HBM_PEAK_GBS = 8000.0
+# multiply-adds of the scoring network per pair, 2 flops each: layer 1
+# (4 x 64), layer 2 (64 x 64), output (64)
+NET_FLOP_PER_PAIR = 2 * (4 * 64 + 64 * 64 + 64)
+BF16_MFMA_PEAK = 2.5e15   # MI355X dense bf16 matrix-core peak, FLOP/s
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
-
-
-KERNEL_SOURCE = {"k_scan": "k_step.hip", "k_scan32": "k_split.hip", "k_scan16": "k_split.hip", "k_learn": "k_learn.hip"}
 
 
 def source_digest(kernel="k_scan"):
@@ -73,51 +105,241 @@ def load_traffic(digest, kernel):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(w, budget_s):
+def tts_of(p1, t):
+    """Eq. 17: the time to reach the ground state with probability 0.99."""
+    if p1 <= 0.0:
+        return None
+    if p1 >= 1.0:
+        return t
+    return math.log(1.0 - 0.99) / math.log(1.0 - p1) * t
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, budget_s, single_s):
     """The CPU oracle on a bounded sample of the same workload: search 0 of
     instance 0, stepped synchronously from its initial state (each step
-    expands that step's new states) until the time budget is spent."""
+    expands that step's new states) until the time budget is spent, on every
+    host thread and then on one."""
+    import ctypes
     import numpy as np
     import oracle
     inst = w.instances[0]
     N, M = inst.N, w.M
     pairs = N * (N - 1) // 2
-    bits, E, front = inst.init_bits[:1], None, np.ones(1, np.uint8)
-    evals, steps = 0, 0
-    t0 = time.time()
-    while time.time() - t0 < budget_s:
-        expanded = int(front.sum())
-        if expanded == 0:
-            break
-        bits, E, front, _ = oracle.step(inst.J, inst.h, M, bits, E, front)
-        evals += pairs * expanded
-        steps += 1
-    secs = time.time() - t0
-    return {
+
+    def run(budget):
+        bits, E, front = inst.init_bits[:1], None, np.ones(1, np.uint8)
+        evals, steps = 0, 0
+        t0 = time.time()
+        while time.time() - t0 < budget:
+            expanded = int(front.sum())
+            if expanded == 0:
+                break
+            bits, E, front, _ = oracle.step(inst.J, inst.h, M, bits, E, front)
+            evals += pairs * expanded
+            steps += 1
+        return evals, steps, time.time() - t0
+
+    def run_single(budget):
+        # one thread: the first step's new states expanded one parent at a time
+        # (each parent's 179,700 pair flips), until the budget is spent
+        bits, E, front, _ = oracle.step(inst.J, inst.h, M, inst.init_bits[:1])
+        evals, parents = 0, 0
+        t0 = time.time()
+        while time.time() - t0 < budget:
+            one = np.zeros_like(front)
+            one[parents % len(one)] = 1
+            oracle.step(inst.J, inst.h, M, bits, E, one)
+            evals += pairs
+            parents += 1
+        return evals, parents, time.time() - t0
+
+    threads = oracle.num_threads()
+    evals, steps, secs = run(budget_s)
+    out = {
         "value": evals / secs,
         "unit": "pair-flip dE evals/s",
-        "cores": oracle.num_threads(),
+        "cores": threads,
         "kind": "oracle",
-        "sample": (f"instance 0 search 0 of the same workload stepped from its initial state for {steps} "
+        "cpu_model": cpu_model(),
+        "sample": (f"instance 0 search 0 of the N=600 workload stepped from its initial state for {steps} "
                    f"synchronous steps (each expanding that step's new states): {evals} pair flips, O(N) "
-                   f"flipped-site energy change each, {secs:.1f} s"),
+                   f"flipped-site energy change each, {secs:.1f} s on {threads} threads"),
+    }
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(1)
+        e1, p1, t1 = run_single(single_s)
+        gomp.omp_set_num_threads(threads)
+        out["single_core_value"] = e1 / t1
+        out["single_core_sample"] = (f"one thread: {p1} states of the same search's first step expanded one at a "
+                                     f"time, {e1} pair flips, {t1:.1f} s")
+    except OSError:
+        out["single_core_value"] = None
+    return out
+
+
+# ---------------------------------------------------------------- the C3 workload, one form
+def measure(binding, torch, w, form, steps, warmup, batching=False):
+    """Complete passes of the method over the batch with one form; device-timed."""
+    s = binding.IsingSearch.from_workload(w, timing=1, persistent=1 if batching else 0,
+                                          form=FORM_CODES[form], flags=FORM_FLAGS.get(form, 0))
+    torch.cuda.synchronize()
+    tuned = [False]
+
+    def one_pass():
+        s.reset()
+        if batching and not tuned[0]:
+            s.step()
+            s.autotune()
+            tuned[0] = True
+        it, stable = s.run()
+        s.get_states(0)
+        return it, stable
+
+    for k in range(warmup):
+        it, stable = one_pass()
+        log(f"[{form}] warmup {k}: {it} iterations, stable={stable}")
+    st0 = s.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    for k in range(steps):
+        it, stable = one_pass()
+        iters.append(it)
+        log(f"[{form}] step {k}: {it} iterations, stable={stable}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st1 = s.stats()
+    d = {k: st1[k] - st0[k] for k in st1 if isinstance(st1[k], (int, float))}
+    pairs = d["pair_evals"]
+    scan_s = d["scan_ms"] / 1e3
+    launches = max(d["scan_launches"], 1)
+    E1 = [float(s.get_states(b)[1][0]) for b in range(len(w.instances))]
+    tiles = s.tuning()
+    s.destroy()
+    torch.cuda.synchronize()
+    if batching:
+        # the steps are replayed graphs: no per-kernel times
+        roofline = None
+    elif form in SITE_BOUND_FORMS:
+        # the preparation kernel evaluates the bounded states: its algorithmic
+        # bytes are the F row of each expanded state (8N) and one FP32 coupling
+        # per evaluated pair (4)
+        prep_s = d["prep_ms"] / 1e3
+        N = w.instances[0].N
+        nbytes = d["frontier_states"] * 8 * N + 4 * pairs
+        gbs = nbytes / prep_s / 1e9 if prep_s > 0 else 0.0
+        roofline = {
+            "kernel": "k_prep32 (site bound)" if FORM_CODES[form] == 1 else "k_prep (site bound)",
+            "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "avg_launch_ms": d["prep_ms"] / launches,
+            "bytes_model": "8N per expanded state (its F row) + 4 per evaluated pair (an FP32 coupling)",
+        }
+    else:
+        ops_per_s = OPS_PER_PAIR * pairs / scan_s if scan_s > 0 else 0.0
+        peak = VALU_LANE_OPS_PER_S[FORM_DTYPE[form]]
+        roofline = {
+            "kernel": SCAN_KERNEL[form], "bound": "alu",
+            "achieved": ops_per_s / 1e12, "peak": peak / 1e12, "unit": "T lane-ops/s",
+            "frac": ops_per_s / peak,
+            "avg_launch_ms": d["scan_ms"] / launches,
+            "ops_per_pair": OPS_PER_PAIR,
+        }
+        if FORM_DTYPE[form] == "f32":
+            roofline["frac_of_nonpacked_fp32_rate"] = ops_per_s / VALU_LANE_OPS_PER_S["f64"]
+    return {
+        "wall": wall, "steps": steps, "warmup": warmup, "pairs": pairs,
+        "value": pairs / wall,
+        "ms_per_step": 1e3 * wall / steps,
+        "time_per_instance_s": wall / steps / len(w.instances),
+        "iterations": iters,
+        "E1": E1,
+        "mean_E1": sum(E1) / len(E1),
+        "scan_kernel_evals_per_s": pairs / scan_s if scan_s > 0 else None,
+        "kernel_ms_per_step": {k: d[k + "_ms"] / steps for k in ("scan", "merge", "frontier", "prep", "init", "step")},
+        "survivors": d["survivors"], "retries": d["retries"],
+        "rescore_rejections": d["fallbacks"],
+        "split_field_err": st1.get("split_field_err"),
+        "scan_states_per_item": sorted(set(zip([i.N for i in w.instances], tiles))),
+        "bounded_states": d.get("bounded_states", 0),
+        "expanded_states": d["frontier_states"],
+        "roofline": roofline,
     }
 
 
-FORM_CODES = {"plain": 0, "split_bf16": 1, "split_fp16": 1, "learned": 2, "plain_bound": 0, "split_bf16_bound": 1}
-# the *_bound forms run with the site bound (only the pairs that can pass the
-# cut are evaluated; identical kept sets): a time-to-solution figure, not an
-# evaluation rate
-FORM_FLAGS = {"plain_bound": 2, "split_bf16_bound": 2, "split_fp16": 4}
-SITE_BOUND_FORMS = ("plain_bound", "split_bf16_bound")
-SCAN_KERNEL = {"plain": "k_scan", "split_bf16": "k_scan32", "split_fp16": "k_scan16"}
-HBM_PEAK_GBS = 8000.0
-# multiply-adds of the scoring network per pair, counted as 2 flops each:
-# layer 1 (4 x 64), layer 2 (64 x 64), output (64)
-NET_FLOP_PER_PAIR = 2 * (4 * 64 + 64 * 64 + 64)
-BF16_MFMA_PEAK = 2.5e15   # MI355X dense bf16 matrix-core peak, FLOP/s
+def reference_energies(binding, torch, w, M, L, chunk=40):
+    """The lowest energy per instance of an extended run (larger M and L, the
+    split form with the site bound), in chunks of instances."""
+    from paper_2010_00180_amd.workloads import Workload, make_instance
+    out = []
+    t0 = time.perf_counter()
+    for c0 in range(0, len(w.instances), chunk):
+        insts = [make_instance(i.N, i.seed, L, i.dist) for i in w.instances[c0:c0 + chunk]]
+        wx = Workload("ref", w.config, insts, M=M, L=L)
+        s = binding.IsingSearch.from_workload(wx, form=1, flags=2)
+        s.run()
+        out += [float(s.get_states(b)[1][0]) for b in range(len(insts))]
+        s.destroy()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
 
 
+def tts_table(results, E_ref):
+    """p1 against E_ref and Eq. 17 per form."""
+    out = {}
+    for f, r in results.items():
+        hit = [a == b for a, b in zip(r["E1"], E_ref)]
+        p1 = sum(hit) / len(hit)
+        t = r["time_per_instance_s"]
+        tt = tts_of(p1, t)
+        out[f] = {"p1": p1, "instances": len(hit), "not_reached": len(hit) - sum(hit),
+                  "t_per_instance_s": t, "tts_s": tt, "tts_note": None if tt is not None else "not reached"}
+    return out
+
+
+def c1_shape_tts(binding, torch, workloads, n_inst=120):
+    """120 instances of the N = 24, M = 8, L = 4 shape against the exact lowest
+    states of each (GPU enumeration): p1, the success rate r of the M lowest
+    (Sec. IV), TTS (Eq. 17)."""
+    import numpy as np
+    insts = [workloads.make_instance(24, workloads.seed_for(1, k), 4) for k in range(n_inst)]
+    w = workloads.Workload("c1_shape", 1, insts, M=8, L=4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    exact = binding.brute_lowest([i.J for i in insts], [i.h for i in insts], 8)
+    torch.cuda.synchronize()
+    t_brute = time.perf_counter() - t0
+    s = binding.IsingSearch.from_workload(w, timing=1)
+    s.run()
+    s.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.run()
+    res = [s.get_states(b) for b in range(n_inst)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s.destroy()
+    p1 = float(np.mean([gE[0] == eE[0] for (gb, gE), (eb, eE) in zip(res, exact)]))
+    r = float(np.mean([np.mean([int(x) in {int(y) for y in gb[:, 0]} for x in eb[:, 0]])
+                       for (gb, gE), (eb, eE) in zip(res, exact)]))
+    t = wall / n_inst
+    return {"instances": n_inst, "N": 24, "M": 8, "L": 4, "form": "plain",
+            "E_ref": "exact: the GPU enumeration of all 2^24 states", "p1": p1, "r_of_8_lowest": r,
+            "t_per_instance_s": t, "tts_s": tts_of(p1, t), "enumeration_s": t_brute}
+
+
+# ---------------------------------------------------------------- learned form
 def train_network(binding, torch, workloads, seed=1):
     """Traces of plain runs on instances of the measured shape that are not in
     the measured workload, then FP32 training on the device (Adam)."""
@@ -185,8 +407,8 @@ def judge_miss_rate(binding, torch, inst, L, M, scorer, params, max_steps):
     return {"mean": float(np.mean(rates)) if rates else None, "judged_search_steps": len(rates)}
 
 
-def measure_learned(binding, torch, w, params, steps):
-    """Complete passes of the learned form, and of the plain form on the same instances."""
+def measure_learned(binding, torch, w, params, E_ref=None):
+    """One complete pass of the learned form and of the plain form on the same instances."""
     out = {}
     for form in ("plain", "learned"):
         s = binding.IsingSearch.from_workload(w, timing=1, form=FORM_CODES[form])
@@ -195,12 +417,8 @@ def measure_learned(binding, torch, w, params, steps):
         st0 = s.stats()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        iters = []
-        for k in range(steps):
-            s.reset()
-            it, stable = s.run()
-            s.get_states(0)
-            iters.append(it)
+        it, stable = s.run()
+        s.get_states(0)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         st1 = s.stats()
@@ -208,29 +426,29 @@ def measure_learned(binding, torch, w, params, steps):
         finals = [s.get_search(k)[0].tobytes() for k in range(len(w.instances) * w.L)]
         E1 = [float(s.get_states(b)[1][0]) for b in range(len(w.instances))]
         s.destroy()
-        out[form] = {"wall": wall, "d": d, "iters": iters, "finals": finals, "E1": E1}
+        out[form] = {"wall": wall, "d": d, "iters": it, "finals": finals, "E1": E1}
     lr, pl = out["learned"], out["plain"]
     d = lr["d"]
     learn_s = d["learn_ms"] / 1e3
     flops = NET_FLOP_PER_PAIR * d["scored_pairs"]
-    return {
-        "instances": len(w.instances), "L": w.L, "M": w.M, "steps": steps,
+    n = len(w.instances)
+    ref = E_ref if E_ref is not None else [min(a, b) for a, b in zip(lr["E1"], pl["E1"])]
+    res = {
+        "instances": n, "N": w.instances[0].N, "L": w.L, "M": w.M,
         "value": d["pair_evals"] / lr["wall"],
         "unit": "exact pair-flip dE evals/s",
         "scored_pairs_per_s": d["scored_pairs"] / lr["wall"],
-        "ms_per_step": 1e3 * lr["wall"] / steps,
-        "time_per_instance_s": lr["wall"] / steps / len(w.instances),
-        "plain_time_per_instance_s_same_sample": pl["wall"] / steps / len(w.instances),
-        "exact_pair_evals_per_pass": d["pair_evals"] / steps,
-        "plain_exact_pair_evals_per_pass": pl["d"]["pair_evals"] / steps,
+        "time_per_instance_s": lr["wall"] / n,
+        "plain_time_per_instance_s_same_sample": pl["wall"] / n,
+        "exact_pair_evals_per_pass": d["pair_evals"],
+        "plain_exact_pair_evals_per_pass": pl["d"]["pair_evals"],
         "exact_evals_saved_factor": pl["d"]["pair_evals"] / max(d["pair_evals"], 1),
         "iterations": lr["iters"], "plain_iterations": pl["iters"],
         "full_enumeration_steps": d["fallbacks"], "ranked_states": d["ranked_states"], "retries": d["retries"],
-        "mean_E1": sum(lr["E1"]) / len(lr["E1"]), "plain_mean_E1": sum(pl["E1"]) / len(pl["E1"]),
-        "same_E1_as_plain": lr["E1"] == pl["E1"],
+        "mean_E1": sum(lr["E1"]) / n, "plain_mean_E1": sum(pl["E1"]) / n,
         "fraction_of_searches_ending_unlike_plain": sum(a != b for a, b in zip(lr["finals"], pl["finals"])) /
                                                      len(pl["finals"]),
-        "kernel_ms_per_step": {k: d[k + "_ms"] / steps for k in ("learn", "scan", "merge", "frontier", "prep")},
+        "kernel_ms": {k: d[k + "_ms"] for k in ("learn", "scan", "merge", "frontier", "prep")},
         "roofline": {
             "kernel": "k_learn", "bound": "mfma",
             "achieved": flops / learn_s / 1e12 if learn_s > 0 else None,
@@ -240,101 +458,139 @@ def measure_learned(binding, torch, w, params, steps):
             "flop_per_scored_pair": NET_FLOP_PER_PAIR,
         },
     }
+    for tag, E1, wall in (("learned", lr["E1"], lr["wall"]), ("plain", pl["E1"], pl["wall"])):
+        p1 = sum(a == b for a, b in zip(E1, ref)) / n
+        res[f"tts_{tag}"] = {"p1": p1, "t_per_instance_s": wall / n, "tts_s": tts_of(p1, wall / n)}
+    res["E_ref"] = ("the C3 reference energies (best known, not certified)" if E_ref is not None else
+                    "the lower of the two forms' lowest energies on this sample (best known, not certified)")
+    return res
 
 
-def measure(binding, torch, w, form, steps, warmup, batching, copy_gib):
-    """Complete passes of the method over the batch with one form; device-timed."""
-    s = binding.IsingSearch.from_workload(w, timing=1, persistent=1 if batching else 0,
-                                          form=FORM_CODES[form], flags=FORM_FLAGS.get(form, 0))
-    torch.cuda.synchronize()
-    tuned = [False]
-
-    def one_pass():
-        s.reset()
-        if batching and not tuned[0]:
-            s.step()
-            s.autotune()
-            tuned[0] = True
+# ---------------------------------------------------------------- other choices of H1 (Sec. VI)
+def measure_h1(binding, torch, workloads, w, E_ref, quick):
+    import numpy as np
+    out = {}
+    for name, flags, wx in (("single_flips", 8, w),
+                            ("exchange_half_filled", 16, workloads.in_sector(w, [i.N // 2 for i in w.instances])),
+                            ("exchange_half_filled_bound", 18,
+                             workloads.in_sector(w, [i.N // 2 for i in w.instances]))):
+        s = binding.IsingSearch.from_workload(wx, timing=1, flags=flags)
+        st0 = s.stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         it, stable = s.run()
-        s.get_states(0)
-        return it, stable
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st1 = s.stats()
+        E1 = [float(s.get_states(b)[1][0]) for b in range(len(wx.instances))]
+        s.destroy()
+        d = {k: st1[k] - st0[k] for k in ("pair_evals", "single_evals", "frontier_states")}
+        r = {"instances": len(wx.instances), "N": wx.instances[0].N, "M": wx.M, "L": wx.L, "iterations": it,
+             "time_per_instance_s": wall / len(wx.instances), "mean_E1": float(np.mean(E1)),
+             "single_evals_per_s": d["single_evals"] / wall, "pair_evals_per_s": d["pair_evals"] / wall,
+             "expanded_states": d["frontier_states"]}
+        if flags == 8:
+            p1 = sum(a == b for a, b in zip(E1, E_ref)) / len(E1)
+            r["p1_against_pair_flip_reference"] = p1
+            r["tts_s"] = tts_of(p1, r["time_per_instance_s"])
+        else:
+            r["sector"] = "N/2 down spins (total sigma^z = 0); energies are the sector's lowest, not the global"
+        out[name] = r
+    if not quick:
+        # the paper's large-N regime for single flips
+        wl = workloads.custom([4096] * 8, L=4, M=120, config=61)
+        s = binding.IsingSearch.from_workload(wl, flags=8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, stable = s.run()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = s.stats()
+        s.destroy()
+        out["single_flips_n4096"] = {"instances": 8, "N": 4096, "M": 120, "L": 4, "iterations": it,
+                                     "time_per_instance_s": wall / 8, "single_evals_per_s": st["single_evals"] / wall}
+    return out
 
-    for k in range(warmup):
-        it, stable = one_pass()
-        log(f"[{form}] warmup {k}: {it} iterations, stable={stable}")
-    st0 = s.stats()
-    torch.cuda.synchronize()
+
+# ---------------------------------------------------------------- best-first search (Alg. 2-4, Sec. IV)
+def bestfirst_studies(binding, torch, workloads, sizes):
+    """The paper's Sec. IV setting: 120 instances per N with J and h uniform on
+    [-1/2, 1/2]; p1 and r against the GPU enumeration's 120 lowest states."""
+    import numpy as np
+    out = {"per_N": {}, "note": "single: (L, phi_1) = (1, 0), I = K = a K0; multi: L = N random initial "
+                                "states, K = K0, I = a N; K0 = N(N+1)/2 + 1; r = fraction of the 120 lowest "
+                                "states found; times are GPU kernel time per instance"}
+    for N in sizes:
+        insts = [workloads.make_instance(N, workloads.seed_for(7, 1000 * N + k), N, "uniform") for k in range(120)]
+        Js, hs = [i.J for i in insts], [i.h for i in insts]
+        exact = binding.brute_lowest(Js, hs, 120)
+        K0 = N * (N + 1) // 2 + 1
+        rows = {}
+        cfgs = [("single", a, 1, a * K0, a * K0) for a in (1, 2, 3, 10) if a * K0 + 1 <= 2048]
+        cfgs += [("multi", a, N, K0, max(1, int(round(a * N)))) for a in (0.1, 0.2, 0.3, 0.5, 1.0)]
+        for kind, a, L, K, I in cfgs:
+            x0s = [[0] for _ in insts] if L == 1 else [i.init_bits[:L, 0] for i in insts]
+            res = binding.bestfirst(Js, hs, x0s, K, I)
+            p1 = float(np.mean([res["merged"][b][1][0] == exact[b][1][0] for b in range(120)]))
+            r = float(np.mean([np.mean([int(x) in {int(y) for y in res["merged"][b][0][:, 0]}
+                                        for x in exact[b][0][:, 0]]) for b in range(120)]))
+            t = res["kernel_ms"] / 1e3 / 120
+            rows[f"{kind}_a{a}"] = {"L": L, "K": K, "I": I, "LI": L * I, "p1": p1, "r": r,
+                                    "t_per_instance_s": t, "tts_s": tts_of(p1, t)}
+        out["per_N"][N] = rows
+    return out
+
+
+# ---------------------------------------------------------------- spectrum (Sec. V)
+def spectrum_study(binding, torch, workloads, sizes, K=1024):
+    """E1 = a N^{3/2} + b, the gap E2 - E1 against 1/N, and ln k = -a x^2 + b x
+    with x = E_k - E1, from the exact K lowest states of 120 instances per N."""
+    import numpy as np
+    per = {}
     t0 = time.perf_counter()
-    iters = []
-    for k in range(steps):
-        it, stable = one_pass()
-        iters.append(it)
-        log(f"[{form}] step {k}: {it} iterations, stable={stable}")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st1 = s.stats()
-    wall = t1 - t0
-    d = {k: st1[k] - st0[k] for k in st1 if isinstance(st1[k], (int, float))}
-    pairs = d["pair_evals"]
-    scan_s = d["scan_ms"] / 1e3
-    launches = max(d["scan_launches"], 1)
-    ops_per_s = OPS_PER_PAIR * pairs / scan_s if scan_s > 0 else 0.0
-    peak = VALU_LANE_OPS_PER_S[FORM_DTYPE[form]]
-    E1 = [float(s.get_states(b)[1][0]) for b in range(len(w.instances))]
-    tiles = s.tuning()
-    if copy_gib > 0:
-        n = int(copy_gib * (1 << 30)) // 8
-        src = torch.ones(n, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"calibration copy: {n * 8} bytes read, {n * 8} bytes written")
-    s.destroy()
-    torch.cuda.synchronize()
-    if form in SITE_BOUND_FORMS:
-        # the preparation kernel evaluates the bounded states: its algorithmic
-        # bytes are the F row of each expanded state (8N) and one FP32 coupling
-        # per evaluated pair (4)
-        prep_s = d["prep_ms"] / 1e3
-        N = w.instances[0].N
-        nbytes = d["frontier_states"] * 8 * N + 4 * pairs
-        gbs = nbytes / prep_s / 1e9 if prep_s > 0 else 0.0
-        roofline = {
-            "kernel": "k_prep32 (site bound)" if FORM_CODES[form] == 1 else "k_prep (site bound)",
-            "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-            "avg_launch_ms": d["prep_ms"] / launches,
-            "bytes_model": "8N per expanded state (its F row) + 4 per evaluated pair (an FP32 coupling)",
-        }
-    else:
-        roofline = {
-            "kernel": SCAN_KERNEL[form],
-            "bound": "alu",
-            "achieved": ops_per_s / 1e12,
-            "peak": peak / 1e12,
-            "unit": "Tops/s",
-            "frac": ops_per_s / peak,
-            "avg_launch_ms": d["scan_ms"] / launches,
-            "ops_per_pair": OPS_PER_PAIR,
-        }
+    spectra = {}
+    for N in sizes:
+        insts = [workloads.make_instance(N, workloads.seed_for(8, 1000 * N + k), 1, "uniform") for k in range(120)]
+        got = binding.brute_lowest([i.J for i in insts], [i.h for i in insts], K)
+        Es = np.array([E[:min(K, 1 << N)] for _, E in got])
+        spectra[N] = Es
+        e1, gap = Es[:, 0], Es[:, 1] - Es[:, 0]
+        per[N] = {"mean_E1": float(e1.mean()), "se_E1": float(e1.std(ddof=1) / np.sqrt(len(e1))),
+                  "mean_gap": float(gap.mean()), "se_gap": float(gap.std(ddof=1) / np.sqrt(len(gap)))}
+    t_enum = time.perf_counter() - t0
+    Ns = np.array(sizes, float)
+    y = np.array([per[N]["mean_E1"] for N in sizes])
+    wgt = 1.0 / np.array([per[N]["se_E1"] for N in sizes])
+    A = np.stack([Ns ** 1.5, np.ones_like(Ns)], 1)
+    (a, b), *_ = np.linalg.lstsq(A * wgt[:, None], y * wgt, rcond=None)
+    cov = np.linalg.inv((A * wgt[:, None]).T @ (A * wgt[:, None]))
+    g = np.array([per[N]["mean_gap"] for N in sizes])
+    gw = 1.0 / np.array([per[N]["se_gap"] for N in sizes])
+    G = np.stack([np.ones_like(Ns), 1 / Ns, 1 / Ns ** 2], 1)
+    gc, *_ = np.linalg.lstsq(G * gw[:, None], g * gw, rcond=None)
+    gcov = np.linalg.inv((G * gw[:, None]).T @ (G * gw[:, None]))
+
+    def lnk_fit(Es, xmax=4.5):
+        x = (Es - Es[:, :1]).mean(0)
+        k = np.arange(1, len(x) + 1)
+        sel = (x <= xmax) & (k > 1)
+        X = np.stack([-x[sel] ** 2, x[sel]], 1)
+        (aa, bb), *_ = np.linalg.lstsq(X, np.log(k[sel]), rcond=None)
+        return float(aa), float(bb), int(sel.sum())
+
+    fits = {N: lnk_fit(spectra[N]) for N in sizes if (1 << N) >= K}
+    big = max(fits)
     return {
-        "wall": wall, "steps": steps, "warmup": warmup, "pairs": pairs,
-        "value": pairs / wall,
-        "ms_per_step": 1e3 * wall / steps,
-        "time_per_instance_s": wall / steps / len(w.instances),
-        "iterations": iters,
-        "E1": E1,
-        "mean_E1": sum(E1) / len(E1),
-        "scan_kernel_evals_per_s": pairs / scan_s if scan_s > 0 else None,
-        "kernel_ms_per_step": {k: d[k + "_ms"] / steps for k in ("scan", "merge", "frontier", "prep", "init", "step")},
-        "survivors": d["survivors"], "retries": d["retries"], "fallbacks": d["fallbacks"],
-        "split_field_err": st1.get("split_field_err"),
-        "scan_states_per_item": sorted(set(zip([i.N for i in w.instances], tiles))),
-        "scan_states_per_item_note": "those of the last step: unless fixed or tuned, every step "
-                                     "chooses a power of two in [16, 256] from its work",
-        "bounded_states": d.get("bounded_states", 0),
-        "expanded_states": d["frontier_states"],
-        "roofline": roofline,
+        "instances_per_N": 120, "distribution": "J_ij, h_i uniform on [-1/2, 1/2] on the 2^-24 grid",
+        "sizes": sizes, "K": K, "enumeration_s": t_enum,
+        "per_N": per,
+        "E1_fit": {"a": float(a), "a_se": float(math.sqrt(cov[0, 0])), "b": float(b), "b_se": float(math.sqrt(cov[1, 1])),
+                   "paper": {"a": -0.218, "a_err": 0.001, "b": 0.79, "b_err": 0.14}},
+        "gap_at_inverse_N_0": {"value": float(gc[0]), "se": float(math.sqrt(gcov[0, 0])),
+                               "paper": {"value": 0.41, "err": 0.12}},
+        "lnk_fit_largest_N": {"N": big, "a": fits[big][0], "b": fits[big][1], "points": fits[big][2],
+                              "paper_N30": {"a": 0.0927, "b": 1.783}},
+        "lnk_fit_per_N": {N: {"a": v[0], "b": v[1]} for N, v in fits.items()},
     }
 
 
@@ -344,20 +600,17 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--instances", type=int, default=0, help="reduce the instance count (0 = the full workload)")
-    ap.add_argument("--workload", choices=["c3", "c4"], default="c3",
-                    help="c3: 120 x N=600, L=64 (the metric's workload); c4: 480 instances of uneven N, "
-                         "L=32, run as the batching form (persistent graph, autotuned tiles)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--forms", default="split_fp16,split_bf16,plain,split_bf16_bound,plain_bound,learned",
-                    help="comma list of forms to time; the first gives the headline value")
-    ap.add_argument("--learned-instances", type=int, default=2,
-                    help="instances of the workload the learned form runs on (a bounded sample)")
+    ap.add_argument("--cpu-single-seconds", type=float, default=5.0)
+    ap.add_argument("--forms", default="split_bf16,split_fp16,plain,split_bf16_bound,plain_bound,split_fp16_bound",
+                    help="comma list of forms timed on the N=600 workload; the first gives the headline value")
+    ap.add_argument("--legs", default="tts,learned,batching,h1,bestfirst,spectrum",
+                    help="comma list of the further legs to run (empty for none)")
+    ap.add_argument("--quick", action="store_true", help="smaller studies (for profiling runs)")
+    ap.add_argument("--extra-steps", type=int, default=1, help="timed passes for the forms after the first")
     ap.add_argument("--judge-steps", type=int, default=40,
                     help="ranking steps judged against full enumeration per scorer (one instance, L=16)")
-    ap.add_argument("--extra-steps", type=int, default=1, help="timed passes for the forms after the first")
-    ap.add_argument("--copy-gib", type=float, default=0.0,
-                    help="after the timed region, copy this many GiB with torch (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -369,56 +622,91 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    batching = args.workload == "c4"
-    if batching:
-        w = workloads.c4_uneven(n_instances=args.instances or 480)
-    else:
-        w = workloads.c3_n600(n_instances=args.instances or 120)
+    w = workloads.c3_n600(n_instances=args.instances or 120)
     log(f"workload {w.name}: {len(w.instances)} instances, L={w.L}, M={w.M}")
-    forms = [f for f in args.forms.split(",") if f] if not batching else ["plain"]
-    if forms[0] == "learned":
-        print("the learned form runs on a sample; put plain or split_bf16 first", file=sys.stderr)
-        sys.exit(2)
+    forms = [f for f in args.forms.split(",") if f]
+    legs = {x for x in args.legs.split(",") if x}
     results = {}
-    learned = None
     for fi, form in enumerate(forms):
         steps = args.steps if fi == 0 else max(1, args.extra_steps)
         warmup = args.warmup if fi == 0 else 0
-        if form == "learned":
-            import numpy as np
-            log("[learned] tracing and training the scoring network")
-            params, tinfo = train_network(binding, torch, workloads)
-            log(f"[learned] {tinfo}")
-            sample = workloads.c3_n600(n_instances=max(1, args.learned_instances))
-            log(f"[learned] timing {len(sample.instances)} instances")
-            learned = measure_learned(binding, torch, sample, params, max(1, args.extra_steps))
-            learned["training"] = tinfo
-            inst0 = sample.instances[0]
-            judge = {}
-            for name, sc, pr in (("network", binding.SCORER_NETWORK, params),
-                                 ("untrained_network", binding.SCORER_NETWORK, workloads.network_params(1).astype(np.float32)),
-                                 ("fields", binding.SCORER_FIELDS, None),
-                                 ("uniform", binding.SCORER_UNIFORM, None)):
-                log(f"[learned] judging the {name} ranking")
-                judge[name] = judge_miss_rate(binding, torch, inst0, 16, sample.M, sc, pr, args.judge_steps)
-            learned["miss_rate_vs_full_enumeration"] = judge
-            learned["miss_rate_note"] = ("ranking steps of instance 0, searches 0-15, first "
-                                         f"{args.judge_steps} steps: |S_full minus S_ranked| / |S_full|, S_full = the "
-                                         "exact step from the same kept set expanding the same states; K = 8N")
-            continue
-        results[form] = measure(binding, torch, w, form, steps, warmup, batching, args.copy_gib if fi == 0 else 0)
+        results[form] = measure(binding, torch, w, form, steps, warmup)
     head = results[forms[0]]
+    plain = results.get("plain")
+
+    tts = None
+    E_ref = [min(r["E1"][b] for r in results.values()) for b in range(len(w.instances))]
+    if "tts" in legs:
+        log("[tts] extended reference run")
+        ext, t_ext = reference_energies(binding, torch, w, M=240, L=256)
+        E_ref = [min(a, b) for a, b in zip(E_ref, ext)]
+        tts = {
+            "E_ref": ("best known, not certified: per instance the lowest energy of every form above and of an "
+                      "extended run (split form with the site bound, M = 240, L = 256)"),
+            "extended_run_s": t_ext,
+            "instances_improved_by_extended_run": sum(a < b for a, b in zip(ext, head["E1"])),
+            "by_form": tts_table(results, E_ref),
+        }
+        log("[tts] N=24 shape against the enumeration")
+        tts["n24_m8_l4"] = c1_shape_tts(binding, torch, workloads)
+
+    learned = None
+    if "learned" in legs:
+        import numpy as np
+        log("[learned] tracing and training the scoring network")
+        params, tinfo = train_network(binding, torch, workloads)
+        learned = {"training": tinfo}
+        n600 = 16 if not args.quick else 4
+        s600 = workloads.Workload("c3_sample", 3, [workloads.make_instance(600, i.seed, 8) for i in w.instances[:n600]],
+                                  M=120, L=8)
+        log(f"[learned] N=600, {n600} instances of the workload with L=8")
+        learned["n600"] = measure_learned(binding, torch, s600, params, E_ref[:n600])
+        n1k = 4 if not args.quick else 1
+        log(f"[learned] N=1000, {n1k} instances with L=8")
+        learned["n1000"] = measure_learned(binding, torch, workloads.c5_learned(1000, n_instances=n1k, L=8), params)
+        inst0 = w.instances[0]
+        judge = {}
+        for name, sc, pr in (("network", binding.SCORER_NETWORK, params),
+                             ("untrained_network", binding.SCORER_NETWORK,
+                              workloads.network_params(1).astype(np.float32)),
+                             ("fields", binding.SCORER_FIELDS, None),
+                             ("uniform", binding.SCORER_UNIFORM, None)):
+            log(f"[learned] judging the {name} ranking")
+            judge[name] = judge_miss_rate(binding, torch, inst0, 16, w.M, sc, pr, args.judge_steps)
+        learned["miss_rate_vs_full_enumeration"] = judge
+        learned["miss_rate_note"] = ("ranking steps of instance 0, searches 0-15, first "
+                                     f"{args.judge_steps} steps: |S_full minus S_ranked| / |S_full|, S_full = the "
+                                     "exact step from the same kept set expanding the same states; K = 8N")
+
+    batching = None
+    if "batching" in legs:
+        log("[batching] 480 instances of uneven N")
+        wb = workloads.c4_uneven(n_instances=480 if not args.quick else 96)
+        r = measure(binding, torch, wb, "plain", 1, 1, batching=True)
+        batching = {k: v for k, v in r.items() if k not in ("E1", "wall", "pairs")}
+        batching["workload"] = (f"{wb.name}: {len(wb.instances)} instances, N drawn from 100..600 (step 100), "
+                                f"L={wb.L}, M={wb.M}, plain form, graph-replayed steps, scan tiles autotuned per N "
+                                f"in the untimed first pass")
+        batching["unit"] = "pair-flip dE evals/s"
+        batching["roofline_note"] = ("steps run as replayed graphs, timed as a whole (kernel_ms_per_step.step); "
+                                     "the scan's own rate is the one of the N=600 forms")
+
+    h1 = measure_h1(binding, torch, workloads, w, E_ref, args.quick) if "h1" in legs else None
+    bestfirst = (bestfirst_studies(binding, torch, workloads, [16, 20, 24, 30] if not args.quick else [16])
+                 if "bestfirst" in legs else None)
+    spectrum = (spectrum_study(binding, torch, workloads, list(range(10, 31, 2)) if not args.quick else [10, 12, 14])
+                if "spectrum" in legs else None)
 
     cpu = None
-    if not args.no_cpu and not batching:
+    if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(w, args.cpu_seconds)
+        cpu = cpu_baseline(w, args.cpu_seconds, args.cpu_single_seconds)
 
-    digest = source_digest(head["roofline"]["kernel"])
-    traffic = load_traffic(digest, head["roofline"]["kernel"])
     roof = dict(head["roofline"])
-    roof["traffic"] = traffic
+    digest = source_digest(roof["kernel"]) if roof["kernel"] in KERNEL_SOURCE else None
+    roof["traffic"] = load_traffic(digest, roof["kernel"]) if digest else None
     roof["source_digest"] = digest
+    head_tts = tts["by_form"][forms[0]] if tts else None
     out = {
         "metric": METRIC,
         "value": head["value"],
@@ -430,34 +718,33 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": FORM_DTYPE[forms[0]] if not batching else "f64",
+        "dtype": FORM_DTYPE[forms[0]],
         "data": "synthetic",
         "config": {
             "workload": (f"{w.name}: {len(w.instances)} instances N=600 J~N(0,1)/sqrt(N) h~N(0,1) on the 2^-24 grid, "
-                         f"M={w.M} kept, L={w.L} initial states each, {forms[0]} form (kept sets identical to the FP64 "
-                         f"form), run to stable") if not batching else
-                        (f"{w.name}: {len(w.instances)} instances with N drawn from 100..600 (step 100), same "
-                         f"distributions, M={w.M}, L={w.L}, batching form: persistent graph-replayed steps, "
-                         f"autotuned scan tiles per N, run to stable"),
-            "instances": len(w.instances), "N": 600 if not batching else "100..600", "M": w.M, "L": w.L,
-            "form": forms[0] if not batching else "plain, batching (persistent + autotuned)",
+                         f"M={w.M} kept, L={w.L} initial states each, {forms[0]} form (kept sets identical to the "
+                         f"FP64 form), run to stable"),
+            "instances": len(w.instances), "N": 600, "M": w.M, "L": w.L, "form": forms[0],
         },
         "time_per_instance_s": head["time_per_instance_s"],
-        "tts_per_instance_s": head["time_per_instance_s"],
-        "tts_note": "p1 = 1 against the best energy this run finds (no certified reference at N=600), so TTS = t",
+        "tts_per_instance_s": head_tts["tts_s"] if head_tts else None,
+        "p1": head_tts["p1"] if head_tts else None,
+        "vs_plain": ({"evals_per_s": head["value"] / plain["value"],
+                      "time_per_instance": plain["time_per_instance_s"] / head["time_per_instance_s"]}
+                     if plain else None),
         "iterations": head["iterations"],
         "mean_E1": head["mean_E1"],
         "scan_kernel_evals_per_s": head["scan_kernel_evals_per_s"],
         "kernel_ms_per_step": head["kernel_ms_per_step"],
-        "survivors": head["survivors"],
-        "retries": head["retries"],
-        "scan_states_per_item": head["scan_states_per_item"],
-        "scan_states_per_item_note": head["scan_states_per_item_note"],
         "roofline": roof,
         "forms": {f: {k: v for k, v in r.items() if k not in ("E1", "wall", "pairs")} for f, r in results.items()},
         "forms_same_E1": all(r["E1"] == head["E1"] for r in results.values()),
-        "tts_per_instance_s_by_form": {f: r["time_per_instance_s"] for f, r in results.items()},
+        "tts": tts,
         "learned": learned,
+        "batching": batching,
+        "h1": h1,
+        "bestfirst": bestfirst,
+        "spectrum": spectrum,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -218,3 +218,11 @@ def test_learned_at_measured_sizes(N, scorer):
     params = wl.network_params(7).astype(np.float32) if scorer == binding.SCORER_NETWORK else None
     large_parity(w, f"learned n{N} scorer {scorer}", list(range(w.n_searches)), form=LEARNED, scorer=scorer,
                  params=params)
+
+
+@pytest.mark.parametrize("N,M,L", [(100, 600, 2), (64, 1024, 2), (300, 600, 2)])
+def test_large_kept_sets(N, M, L):
+    """Kept sets of 600 and 1024 states (the merge's multi-pass sort, the
+    frontier's widened pool prefix), every search checked."""
+    w = wl.custom([N], L=L, M=M, config=42, seed_offset=N + M)
+    large_parity(w, f"M={M} N={N}", list(range(w.n_searches)), every=[0])
