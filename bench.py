@@ -608,6 +608,9 @@ def main():
     ap.add_argument("--legs", default="tts,learned,batching,h1,bestfirst,spectrum",
                     help="comma list of the further legs to run (empty for none)")
     ap.add_argument("--quick", action="store_true", help="smaller studies (for profiling runs)")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="after the first form's timed passes, copy this many GiB with torch (the reference "
+                         "kernel of a counter calibration)")
     ap.add_argument("--extra-steps", type=int, default=1, help="timed passes for the forms after the first")
     ap.add_argument("--judge-steps", type=int, default=40,
                     help="ranking steps judged against full enumeration per scorer (one instance, L=16)")
@@ -631,6 +634,15 @@ def main():
         steps = args.steps if fi == 0 else max(1, args.extra_steps)
         warmup = args.warmup if fi == 0 else 0
         results[form] = measure(binding, torch, w, form, steps, warmup)
+        if fi == 0 and args.copy_gib > 0:
+            n = int(args.copy_gib * (1 << 30)) // 8
+            src = torch.ones(n, dtype=torch.float64, device="cuda")
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            log(f"calibration copy: {n * 8} bytes read, {n * 8} bytes written")
+            del src, dst
     head = results[forms[0]]
     plain = results.get("plain")
 
