@@ -115,7 +115,9 @@ typedef struct {
     uint64_t frontier_states;  /* states expanded, summed over steps */
     uint64_t survivors;        /* candidates that passed the scan's cut, summed over steps */
     uint64_t retries;          /* re-scans of a search after its candidate buffer filled */
-    uint64_t fallbacks;        /* split form: states re-scanned in FP64; learned form: full scans */
+    uint64_t fallbacks;        /* split form: pairs admitted by the reduced-precision scan and then
+                                  rejected by the FP64 re-score; learned form: full-enumeration steps
+                                  (search-steps that evaluated every pair) */
     uint64_t scan_launches;    /* launches of the pair-scan kernel */
     double scan_ms;            /* device time of the pair-scan kernel (cfg.timing = 1), summed */
     double merge_ms;           /* device time of the per-search merge, summed */
