@@ -102,10 +102,24 @@ typedef struct {
                                   scan wave 16 items; 64 with the site bound or the learned form);
                                   ising_search_autotune keeps it only if it beats the tuned tiles */
     int32_t topk_factor;       /* learned form: K = topk_factor * N pairs per state (default 8) */
-    int32_t persistent;        /* 1 = capture the kernels of one step into a hipGraph once and replay
-                                  it for every step (an internal stream is used when none is given) */
+    int32_t persistent;        /* 1 = graph mode: ising_search_step replays a hipGraph of one step's
+                                  kernels, ising_search_run a hipGraph of graph_steps steps (an internal
+                                  stream is used when none is given) */
     int32_t timing;            /* 1 = time every kernel family with hipEvents on the handle's stream */
     int32_t flags;             /* ISING_FLAG_* bits; other bits must be zero */
+    int32_t graph_steps;       /* graph mode: steps per replayed graph in ising_search_run, 1 .. 64
+                                  (0 = 8).  A step that finds every search stable, or a search whose
+                                  candidate buffer fills, makes the kernels of the graph's later steps
+                                  return at once; the host reads the flags once per graph (not once per
+                                  step) and finishes a full buffer's step with its retry passes.  The
+                                  results are those of single steps. */
+    int32_t surv_capacity;     /* candidate records per search (0 = 32768; 65536 for the learned form);
+                                  otherwise between max(2M, 64) and 2^24.  A search whose candidates
+                                  do not fit is re-scanned with the cut its stored candidates give
+                                  (stats.retries); when that cut cannot move (the stored records are
+                                  copies of fewer than M distinct states) every buffer doubles, a
+                                  device allocation inside the step, up to 2^24 records
+                                  (stats.surv_capacity); past that the step fails with CAPACITY */
 } ising_config_t;
 
 typedef struct {
@@ -132,6 +146,8 @@ typedef struct {
     double learn_ms;           /* learned form: device time of the ranking kernel, summed */
     uint64_t bounded_states;   /* site bound: expanded states whose pairs were evaluated among their
                                   bounded sites only */
+    uint64_t surv_capacity;    /* candidate records per search now: cfg.surv_capacity or its
+                                  default, doubled each time a step's candidates could not fit */
 } ising_stats_t;
 
 /*

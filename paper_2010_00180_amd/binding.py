@@ -78,6 +78,8 @@ class IsingConfig(ctypes.Structure):
         ("persistent", ctypes.c_int32),
         ("timing", ctypes.c_int32),
         ("flags", ctypes.c_int32),
+        ("graph_steps", ctypes.c_int32),
+        ("surv_capacity", ctypes.c_int32),
     ]
 
 
@@ -103,6 +105,7 @@ class IsingStats(ctypes.Structure):
         ("trace_samples", ctypes.c_uint64),
         ("learn_ms", ctypes.c_double),
         ("bounded_states", ctypes.c_uint64),
+        ("surv_capacity", ctypes.c_uint64),
     ]
 
     def as_dict(self):
@@ -300,7 +303,8 @@ class IsingSearch:
 
     def __init__(self, Ns: Sequence[int], Js, hs, init_bits, M: int, form: int = FORM_PLAIN,
                  max_iters: int = 0, states_per_item: int = 0, topk_factor: int = 8,
-                 persistent: int = 0, timing: int = 0, stream: Optional[int] = None, flags: int = 0):
+                 persistent: int = 0, timing: int = 0, stream: Optional[int] = None, flags: int = 0,
+                 graph_steps: int = 0, surv_capacity: int = 0):
         L = load()
         self.Ns = [int(n) for n in Ns]
         self.B = len(self.Ns)
@@ -328,7 +332,8 @@ class IsingSearch:
         Narr = (ctypes.c_int32 * self.B)(*self.Ns)
         cfg = IsingConfig(M=self.M, max_iters=int(max_iters), form=int(form),
                           states_per_item=int(states_per_item), topk_factor=int(topk_factor),
-                          persistent=int(persistent), timing=int(timing), flags=int(flags))
+                          persistent=int(persistent), timing=int(timing), flags=int(flags),
+                          graph_steps=int(graph_steps), surv_capacity=int(surv_capacity))
         if stream is None:
             stream = current_stream_handle()
         h = ctypes.c_void_p()

@@ -80,6 +80,10 @@ struct ising_search {
     hipStream_t own_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    // run() in persistent mode: graph_steps steps captured into one graph
+    int graph_steps = 1;
+    hipGraph_t graph_k = nullptr;
+    hipGraphExec_t gexec_k = nullptr;
 };
 
 namespace {
@@ -110,6 +114,10 @@ int dalloc(ising_search* h, T** p, size_t count)
 
 void free_all(ising_search* h)
 {
+    if (h->gexec_k) (void)hipGraphExecDestroy(h->gexec_k);
+    if (h->graph_k) (void)hipGraphDestroy(h->graph_k);
+    h->gexec_k = nullptr;
+    h->graph_k = nullptr;
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
     h->gexec = nullptr;
@@ -127,6 +135,10 @@ void free_all(ising_search* h)
 // The captured step holds the Layout by value: drop it when the layout changes.
 void drop_graph(ising_search* h)
 {
+    if (h->gexec_k) (void)hipGraphExecDestroy(h->gexec_k);
+    if (h->graph_k) (void)hipGraphDestroy(h->graph_k);
+    h->gexec_k = nullptr;
+    h->graph_k = nullptr;
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
     h->gexec = nullptr;
@@ -212,6 +224,11 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
         return fail(ISING_ERR_INVALID_ARG, "the site bound is available for the plain and split forms only");
     if (cfg->topk_factor < 0 || cfg->topk_factor > 64)
         return fail(ISING_ERR_INVALID_ARG, "topk_factor=%d outside [0, 64]", cfg->topk_factor);
+    if (cfg->graph_steps < 0 || cfg->graph_steps > MAX_GRAPH_STEPS)
+        return fail(ISING_ERR_INVALID_ARG, "graph_steps=%d outside [0, %d]", cfg->graph_steps, MAX_GRAPH_STEPS);
+    if (cfg->surv_capacity != 0 && (cfg->surv_capacity < 2 * cfg->M || cfg->surv_capacity < 64 ||
+                                    cfg->surv_capacity > MAX_SURV_CAP))
+        return fail(ISING_ERR_INVALID_ARG, "surv_capacity=%d: 0, or between max(2M, 64) and 2^24", cfg->surv_capacity);
     if (cfg->states_per_item < 0 || cfg->states_per_item > 4096)
         return fail(ISING_ERR_INVALID_ARG, "states_per_item=%d outside [0, 4096]", cfg->states_per_item);
     if (n_inst < 1) return fail(ISING_ERR_INVALID_ARG, "n_inst=%d < 1", n_inst);
@@ -308,7 +325,7 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     lay.Wmax = words_of(Nmax);
     lay.Npmax = pad_of(Nmax);
     lay.fmax = L * cfg->M;
-    lay.cap_surv = cfg->form == ISING_FORM_LEARNED ? 65536 : 32768;
+    lay.cap_surv = cfg->surv_capacity > 0 ? cfg->surv_capacity : (cfg->form == ISING_FORM_LEARNED ? 65536 : 32768);
     lay.topk = topk;
     lay.kmax = kmax;
     lay.cap_lr = cap_lr;
@@ -316,6 +333,7 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     const int sc0 = cfg->states_per_item > 0 ? cfg->states_per_item : 64;
     hd->sc_h.assign(n_inst, sc0);
     hd->persistent = cfg->persistent != 0;
+    hd->graph_steps = hd->persistent ? (cfg->graph_steps > 0 ? cfg->graph_steps : 8) : 1;
     if (hd->persistent && !hd->stream) {
         // a graph cannot be captured on the legacy default stream
         if (hipStreamCreateWithFlags(&hd->own_stream, hipStreamNonBlocking) != hipSuccess) {
@@ -369,6 +387,7 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     ALLOC(lay.item_prefix, 4 * ((size_t)n_inst + 1));
     ALLOC(lay.ctr, 16);
     ALLOC(lay.flags, 8);
+    ALLOC(lay.step_active, MAX_GRAPH_STEPS);
     ALLOC(hd->d_scb, n_inst);
     float* dJ32 = nullptr;
     uint16_t *dJhi = nullptr, *dJlo = nullptr;
@@ -736,6 +755,61 @@ static hipError_t launch_graph_pass(ising_search* h)
     return e;
 }
 
+// Doubles every search's candidate buffer, up to MAX_SURV_CAP records.  The
+// stream is idle (sync_flags waited for it), so the old buffer can go.  The
+// captured steps hold the old layout and are dropped.
+static int grow_surv(ising_search* h)
+{
+    Layout& lay = h->lay;
+    if (lay.cap_surv >= MAX_SURV_CAP)
+        return fail(ISING_ERR_CAPACITY,
+                    "a search has more candidates at its cut than %d records hold, and the buffer cannot grow",
+                    lay.cap_surv);
+    const int cap = lay.cap_surv > MAX_SURV_CAP / 2 ? MAX_SURV_CAP : 2 * lay.cap_surv;
+    Surv* grown = nullptr;
+    int rc = dalloc(h, &grown, (size_t)lay.S * cap);
+    if (rc != ISING_OK) return rc;
+    for (size_t k = 0; k < h->allocs.size(); ++k) {
+        if (h->allocs[k] == static_cast<void*>(lay.surv)) {
+            (void)hipFree(h->allocs[k]);
+            h->allocs.erase(h->allocs.begin() + (long)k);
+            break;
+        }
+    }
+    lay.surv = grown;
+    lay.cap_surv = cap;
+    drop_graph(h);
+    return ISING_OK;
+}
+
+// After a pass whose flags are on the host: re-scan the searches whose
+// candidate buffer filled, with the cut their stored candidates give, until
+// every one has committed.  A cut that cannot move (the stored records are
+// copies of fewer than M distinct states) doubles the buffer first.
+static int finish_retries(ising_search* h, bool collect)
+{
+    int guard = 0;
+    while (h->flags_h[FLAG_OVERFLOW] > 0) {
+        if (h->flags_h[FLAG_STUCK] > 0 || ++guard > 64) {
+            int rc = grow_surv(h);
+            if (rc != ISING_OK) return rc;
+            guard = 0;
+        }
+        hipError_t e = launch_pass(h, true);
+        if (e != hipSuccess) {
+            h->broken = true;
+            return fail(ISING_ERR_HIP, "retry launch failed: %s", hipGetErrorString(e));
+        }
+        int rc = sync_flags(h);
+        if (rc != ISING_OK) {
+            h->broken = true;
+            return rc;
+        }
+        if (collect) collect_times(h);
+    }
+    return ISING_OK;
+}
+
 static int do_step(ising_search* h, int32_t* n_active)
 {
     const Layout& lay = h->lay;
@@ -756,26 +830,79 @@ static int do_step(ising_search* h, int32_t* n_active)
     } else {
         collect_times(h);
     }
-    int guard = 0;
-    while (h->flags_h[FLAG_OVERFLOW] > 0) {
-        if (h->flags_h[FLAG_STUCK] > 0 || ++guard > 64)
-            return fail(ISING_ERR_CAPACITY,
-                        "a search has more tied candidates at its cut than its buffer holds (%d records)",
-                        lay.cap_surv);
-        e = launch_pass(h, true);
-        if (e != hipSuccess) {
-            h->broken = true;
-            return fail(ISING_ERR_HIP, "retry launch failed: %s", hipGetErrorString(e));
-        }
-        rc = sync_flags(h);
-        if (rc != ISING_OK) {
-            h->broken = true;
-            return rc;
-        }
-        collect_times(h);
-    }
+    rc = finish_retries(h, true);
+    if (rc != ISING_OK) return rc;
     h->final_dirty = true;
     if (n_active) *n_active = h->flags_h[FLAG_ACTIVE];
+    return ISING_OK;
+}
+
+// Up to graph_steps steps as one replayed graph.  A step that finds every
+// search stable, or a full candidate buffer, halts the later steps on the
+// device (they return at once); the full buffer's step then finishes with
+// retry passes here.  *done receives the steps taken, *n_active the active
+// searches after the last of them.
+static int do_graph_steps(ising_search* h, int32_t* done, int32_t* n_active)
+{
+    const Layout& lay = h->lay;
+    const int k = h->graph_steps;
+    hipError_t e = hipSuccess;
+    if (!h->gexec_k) {
+        const bool tm = h->timing;
+        h->timing = false;   // no events inside the captured steps
+        e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t e2 = launch_graph_begin(lay, h->stream);
+            for (int t = 0; t < k && e2 == hipSuccess; ++t) {
+                e2 = launch_pass(h, false);
+                --h->scan_launches;
+                if (e2 == hipSuccess) e2 = launch_step_end(lay, t, h->stream);
+            }
+            e = hipStreamEndCapture(h->stream, &h->graph_k);
+            if (e == hipSuccess) e = e2;
+        }
+        h->timing = tm;
+        if (e == hipSuccess) e = hipGraphInstantiate(&h->gexec_k, h->graph_k, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            h->broken = true;
+            return fail(ISING_ERR_HIP, "capture of %d steps failed: %s", k, hipGetErrorString(e));
+        }
+    }
+    if (h->timing) e = hipEventRecord(h->ev[0], h->stream);
+    if (e == hipSuccess) e = hipGraphLaunch(h->gexec_k, h->stream);
+    if (e == hipSuccess && h->timing) e = hipEventRecord(h->ev[5], h->stream);
+    int sa[MAX_GRAPH_STEPS];
+    if (e == hipSuccess) e = hipMemcpyAsync(sa, lay.step_active, sizeof(int) * k, hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) {
+        h->broken = true;
+        return fail(ISING_ERR_HIP, "graph launch failed: %s", hipGetErrorString(e));
+    }
+    int rc = sync_flags(h);
+    if (rc != ISING_OK) {
+        h->broken = true;
+        return rc;
+    }
+    if (h->timing) h->t_step += elapsed_ms(h->ev[0], h->ev[5]);
+    const bool halted = h->flags_h[FLAG_HALT] != 0;
+    const int steps = halted ? h->flags_h[FLAG_HALT_STEP] + 1 : k;
+    h->scan_launches += steps;
+    int active = sa[steps - 1];
+    if (halted) {
+        // clear the halt so that eager passes run
+        e = launch_graph_begin(lay, h->stream);
+        if (e != hipSuccess) {
+            h->broken = true;
+            return fail(ISING_ERR_HIP, "halt clear failed: %s", hipGetErrorString(e));
+        }
+        if (h->flags_h[FLAG_OVERFLOW] > 0) {
+            rc = finish_retries(h, true);
+            if (rc != ISING_OK) return rc;
+            active = h->flags_h[FLAG_ACTIVE];
+        }
+    }
+    h->final_dirty = true;
+    *done = steps;
+    *n_active = active;
     return ISING_OK;
 }
 
@@ -867,23 +994,8 @@ extern "C" int ising_search_autotune(ising_search_t* s, int32_t* n_active)
         s->broken = true;
         return rc;
     }
-    int guard = 0;
-    while (s->flags_h[FLAG_OVERFLOW] > 0) {
-        if (s->flags_h[FLAG_STUCK] > 0 || ++guard > 64)
-            return fail(ISING_ERR_CAPACITY,
-                        "a search has more tied candidates at its cut than its buffer holds (%d records)",
-                        lay.cap_surv);
-        e = launch_pass(s, true);
-        if (e != hipSuccess) {
-            s->broken = true;
-            return fail(ISING_ERR_HIP, "retry launch failed: %s", hipGetErrorString(e));
-        }
-        rc = sync_flags(s);
-        if (rc != ISING_OK) {
-            s->broken = true;
-            return rc;
-        }
-    }
+    rc = finish_retries(s, false);
+    if (rc != ISING_OK) return rc;
     s->final_dirty = true;
     if (n_active) *n_active = s->flags_h[FLAG_ACTIVE];
     return ISING_OK;
@@ -957,13 +1069,22 @@ extern "C" int ising_search_run(ising_search_t* s, int32_t max_iters, int32_t* i
     const int cap = max_iters > 0 ? max_iters : s->cfg.max_iters;
     int it = 0;
     int active = 1;
+    if (s->lay.form == ISING_FORM_LEARNED && !s->scorer_set)
+        return fail(ISING_ERR_BAD_STATE, "the learned form needs ising_search_set_scorer before stepping");
     while (it < cap && active > 0) {
-        rc = do_step(s, &active);
+        // persistent mode: graph_steps steps per replayed graph while the cap allows
+        if (s->persistent && s->graph_steps > 1 && cap - it >= s->graph_steps) {
+            int done = 0;
+            rc = do_graph_steps(s, &done, &active);
+            it += done;
+        } else {
+            rc = do_step(s, &active);
+            ++it;
+        }
         if (rc != ISING_OK) {
             if (iters_done) *iters_done = it;
             return rc;
         }
-        ++it;
     }
     if (iters_done) *iters_done = it;
     return active > 0 ? ISING_NOT_CONVERGED : ISING_OK;
@@ -1148,6 +1269,7 @@ extern "C" int ising_search_get_stats(ising_search_t* s, ising_stats_t* out)
     out->trace_samples = c[CTR_TRACE];
     out->learn_ms = s->t_learn;
     out->bounded_states = c[CTR_BOUNDED];
+    out->surv_capacity = (uint64_t)s->lay.cap_surv;
     return ISING_OK;
 }
 

@@ -97,6 +97,7 @@ struct Layout {
     long long* item_prefix;  // [4][B+1]: scan items, prepared entries, FP32 scan items, ranked entries
     unsigned long long* ctr; // [16] device counters (see CTR_*)
     int* flags;              // [8] per-step flags (see FLAG_*)
+    int* step_active;        // [MAX_GRAPH_STEPS] active searches after each step of a multi-step graph
     // new kept states of the last merge, for the field update
     int* nm_count;           // [S]
     int* nm_code;            // [S][M] parent slot code
@@ -152,7 +153,16 @@ enum { CTR_PAIRS = 0, CTR_SINGLES = 1, CTR_FRONTIER = 2, CTR_SURV = 3, CTR_RETRY
 constexpr int SB_CAP = 256;          // most sites a state may keep for the site-bound evaluation
 enum { H1_FLIPS = 0, H1_SINGLES = 1, H1_EXCHANGE = 2 };
 
-enum { FLAG_ACTIVE = 0, FLAG_OVERFLOW = 1, FLAG_STUCK = 2, FLAG_RETRY_MODE = 3, FLAG_FIRST = 4 };
+constexpr int MAX_SURV_CAP = 1 << 24;   // candidate records per search, at most
+constexpr int MAX_GRAPH_STEPS = 64;   // steps captured in one replayed graph at most
+
+// FLAG_HALT: a step of a multi-step graph found every search stable or a
+// search's candidate buffer full; the kernels of the graph's later steps then
+// return at once (FLAG_HALT_STEP holds the step), and the host takes over.
+enum { FLAG_ACTIVE = 0, FLAG_OVERFLOW = 1, FLAG_STUCK = 2, FLAG_RETRY_MODE = 3, FLAG_FIRST = 4, FLAG_HALT = 5,
+       FLAG_HALT_STEP = 6 };
+
+__device__ inline bool step_halted(const Layout& lay) { return lay.flags[FLAG_HALT] != 0; }
 
 __host__ __device__ inline int words_of(int N) { return (N + 63) >> 6; }
 __host__ __device__ inline int pad_of(int N) { return (N + TILE - 1) / TILE * TILE; }
@@ -489,6 +499,8 @@ hipError_t launch_mlp_adam(float* P, float* m, float* v, const float* g, float l
                            float c1, float c2, hipStream_t st);
 hipError_t launch_mlp_forward(const float* P, const float* X, long long n, float* z, hipStream_t st);
 hipError_t launch_final(const Layout& lay, hipStream_t st);
+hipError_t launch_graph_begin(const Layout& lay, hipStream_t st);
+hipError_t launch_step_end(const Layout& lay, int t, hipStream_t st);
 
 // ------------------------------------------------------------------ exhaustive enumeration (k_brute.hip)
 constexpr int BF_NL = 8;                 // low sites walked in Gray order by one thread

@@ -297,6 +297,7 @@ __device__ inline int lr_find(const long long* prefix, int B, long long e)
 
 __global__ __launch_bounds__(256) void k_learn(Layout lay)
 {
+    if (step_halted(lay)) return;   // a later step of a multi-step graph after a halt
     extern __shared__ __align__(16) unsigned char lr_smem[];
     __shared__ LrShared sh;
     __shared__ int hist[256];
@@ -547,6 +548,7 @@ hipError_t launch_learn(const Layout& lay, int grid, hipStream_t st)
 // the child among the new kept states (exact energy, then the Zobrist hash).
 __global__ __launch_bounds__(256) void k_trace(Layout lay, const long long* __restrict__ fr_prefix)
 {
+    if (step_halted(lay)) return;   // a later step of a multi-step graph after a halt
     const long long total = fr_prefix[lay.B];
     const int wave = threadIdx.x >> 6;
     const uint32_t lane = threadIdx.x & 63u;

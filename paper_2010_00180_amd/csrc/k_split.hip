@@ -146,6 +146,7 @@ __device__ inline _Float16 half_up(double x)
 template <bool SB, bool H16>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_prep32(Layout lay, const long long* __restrict__ fr_prefix)
 {
+    if (step_halted(lay)) return;   // a later step of a multi-step graph after a halt
     __shared__ uint16_t sb_idx[SB ? 4 : 1][SB ? SB_CAP : 1];
     __shared__ double sb_a[SB ? 4 : 1][SB ? SB_CAP : 1];
     const long long total = fr_prefix[lay.B];
@@ -328,6 +329,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                                                const uint64_t* __restrict__ fbits,
                                                const long long* __restrict__ iprefix)
 {
+    if (step_halted(lay)) return;   // a later step of a multi-step graph after a halt
     __shared__ Surv stage[STAGE];
     __shared__ float abuf[T32];   // a_j of the current state
     __shared__ double sT[64], sE[64];
@@ -544,6 +546,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                                                const uint64_t* __restrict__ fbits,
                                                const long long* __restrict__ iprefix)
 {
+    if (step_halted(lay)) return;   // a later step of a multi-step graph after a halt
     __shared__ Surv stage[STAGE];
     __shared__ uint32_t abuf[T16 / 2];   // fl16(a_j) pairs of the current state
     __shared__ double sT[64], sE[64];
@@ -806,6 +809,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // Work prefix over instances for the 64 x 128 tiles of the FP16 scan.
 __global__ __launch_bounds__(1024) void k_plan16(Layout lay, long long* __restrict__ iprefix)
 {
+    if (step_halted(lay)) return;   // a later step of a multi-step graph after a halt
     __shared__ long long part[1024];
     const int t = threadIdx.x;
     const int per = (lay.B + 1023) / 1024;
@@ -836,6 +840,7 @@ __global__ __launch_bounds__(1024) void k_plan16(Layout lay, long long* __restri
 // Work prefix over instances for the 64 x 64 tiles of the FP32 scan.
 __global__ __launch_bounds__(1024) void k_plan32(Layout lay, long long* __restrict__ iprefix)
 {
+    if (step_halted(lay)) return;   // a later step of a multi-step graph after a halt
     __shared__ long long part[1024];
     const int t = threadIdx.x;
     const int per = (lay.B + 1023) / 1024;

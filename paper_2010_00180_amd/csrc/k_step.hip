@@ -82,6 +82,7 @@ __device__ inline void wave_sync()
 // ------------------------------------------------------------------ k_step_begin
 __global__ void k_step_begin(Layout lay, int retry_mode)
 {
+    if (step_halted(lay)) return;   // a later step of a multi-step graph after a halt
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (!retry_mode && t < lay.B) {
         lay.fr_count[t] = 0;
@@ -301,6 +302,7 @@ __device__ inline void cand_sites(uint32_t id, int* out, int& n)
 
 __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __restrict__ J4, int kn)
 {
+    if (step_halted(lay)) return;   // a later step of a multi-step graph after a halt
     // key/idx: kn >= max(POOL, pow2(Npmax)) entries, in dynamic LDS, so that
     // three blocks share a CU for N up to 2048
     extern __shared__ __align__(16) unsigned char fr_dyn[];
@@ -613,6 +615,7 @@ __device__ inline long long proposals_of(const Layout& lay, long long N)
 
 __global__ __launch_bounds__(1024) void k_plan(Layout lay, long long* __restrict__ fr_prefix, int count)
 {
+    if (step_halted(lay)) return;   // a later step of a multi-step graph after a halt
     __shared__ long long part_items[1024];
     __shared__ long long part_fr[1024];
     __shared__ long long part_lr[1024];
@@ -729,6 +732,7 @@ __device__ inline int find_instance(const long long* prefix, int B, long long e)
 template <bool SB>
 __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __restrict__ fr_prefix)
 {
+    if (step_halted(lay)) return;   // a later step of a multi-step graph after a halt
     __shared__ uint16_t sb_idx[SB ? 4 : 1][SB ? SB_CAP : 1];
     __shared__ double sb_a[SB ? 4 : 1][SB ? SB_CAP : 1];
     const long long total = fr_prefix[lay.B];
@@ -885,6 +889,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                                              const FrRec* __restrict__ recs,
                                              const uint64_t* __restrict__ fbits)
 {
+    if (step_halted(lay)) return;   // a later step of a multi-step graph after a halt
     __shared__ Surv stage[STAGE];
     __shared__ double abuf[TCOL];   // a_j of the current state
     // per-state data of up to 64 states of the chunk, staged once per item
@@ -1322,6 +1327,7 @@ static_assert(MERGE_CH == 2048, "the slot bookkeeping of k_merge lives in the up
 // latency of its gathers, needs.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_merge(Layout lay, const double* __restrict__ J4)
 {
+    if (step_halted(lay)) return;   // a later step of a multi-step graph after a halt
     __shared__ uint64_t kz[2 * MERGE_CH];   // key then zk; the dedupe table before them
     __shared__ uint32_t ref[MERGE_CH];
     __shared__ uint8_t keep[MERGE_CH];
@@ -1620,7 +1626,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         // some candidates were not stored: the stored ones still bound the cut
         if (threadIdx.x == 0) {
             const double oldc = lay.cut[s];
-            const double nc = nrun == M ? key[M - 1] : oldc;
+            // never above the cut the candidates were scanned with
+            const double nc = (nrun == M && key[M - 1] < oldc) ? key[M - 1] : oldc;
             lay.cut[s] = nc;
             lay.retry[s] = 1;
             lay.nm_count[s] = 0;
@@ -1721,6 +1728,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // L2 while its new states use them.
 __global__ __launch_bounds__(256) void k_fupdate(Layout lay, const double* __restrict__ J4)
 {
+    if (step_halted(lay)) return;   // a later step of a multi-step graph after a halt
     const int groups = (lay.M + 3) / 4;
     const int s = (int)(blockIdx.x / groups);
     const int m = (int)(blockIdx.x % groups) * 4 + (threadIdx.x >> 6);
@@ -1872,6 +1880,7 @@ hipError_t launch_clear_survivors(const Layout& lay, hipStream_t st)
 // item re-signs few columns between them), and the pair count of the step.
 __global__ __launch_bounds__(256) void k_sb_list(Layout lay, int count)
 {
+    if (step_halted(lay)) return;   // a later step of a multi-step graph after a halt
     __shared__ int tmp[256];
     const int b = blockIdx.x;
     const int P = lay.fr_count[b];
@@ -1913,6 +1922,7 @@ __global__ __launch_bounds__(256) void k_sb_list(Layout lay, int count)
 // Scan items of the FP64 scan over the entries left to it.
 __global__ __launch_bounds__(1024) void k_sb_items(Layout lay)
 {
+    if (step_halted(lay)) return;   // a later step of a multi-step graph after a halt
     __shared__ long long part[1024];
     const int t = threadIdx.x;
     const int per = (lay.B + 1023) / 1024;
@@ -1975,6 +1985,41 @@ hipError_t launch_merge(const Layout& lay, hipStream_t st)
 hipError_t launch_fupdate(const Layout& lay, hipStream_t st)
 {
     hipLaunchKernelGGL(k_fupdate, dim3(lay.S * ((lay.M + 3) / 4)), dim3(256), 0, st, lay, lay.J4);
+    return hipGetLastError();
+}
+
+// Multi-step graphs: the halt flag is cleared by a kernel (the graph holds no
+// memset), and after step t the active count is recorded; a step that found
+// every search stable, or a full candidate buffer (the host then runs the
+// retry passes), halts the graph's later steps.
+__global__ void k_graph_begin(Layout lay)
+{
+    if (threadIdx.x == 0) {
+        lay.flags[FLAG_HALT] = 0;
+        lay.flags[FLAG_HALT_STEP] = -1;
+    }
+}
+
+__global__ void k_step_end(Layout lay, int t)
+{
+    if (threadIdx.x != 0 || step_halted(lay)) return;
+    const int active = lay.flags[FLAG_ACTIVE];
+    lay.step_active[t] = active;
+    if (active == 0 || lay.flags[FLAG_OVERFLOW] > 0) {
+        lay.flags[FLAG_HALT] = 1;
+        lay.flags[FLAG_HALT_STEP] = t;
+    }
+}
+
+hipError_t launch_graph_begin(const Layout& lay, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_graph_begin, dim3(1), dim3(64), 0, st, lay);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_end(const Layout& lay, int t, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, st, lay, t);
     return hipGetLastError();
 }
 

@@ -190,3 +190,18 @@ def test_training_entry_points_report_no_device():
     assert lib.ising_mlp_forward(fake, fake, 4, fake, None) == binding.ISING_ERR_NO_DEVICE
     assert lib.ising_mlp_loss_grad(fake, fake, fake, 10, 1.0, fake, None, fake, ws, None) == binding.ISING_ERR_NO_DEVICE
     assert lib.ising_mlp_loss_grad_noalloc(fake, fake, fake, 10, 1.0, fake, None, None) == binding.ISING_ERR_NO_DEVICE
+
+
+def _header_struct_fields(name):
+    """Field names, in order, of the typedef'd struct `name` in the header."""
+    text = open(os.path.join(ROOT, "include", "ising_search.h")).read()
+    m = re.search(r"typedef struct\s*\{([^{}]*)\}\s*" + name + r"\s*;", text)
+    assert m, name
+    body = re.sub(r"/\*.*?\*/", "", m.group(1), flags=re.S)
+    return [re.findall(r"(\w+)\s*$", decl.strip())[0] for decl in body.split(";") if decl.strip()]
+
+
+@pytest.mark.parametrize("cname,pyclass", [("ising_config_t", "IsingConfig"), ("ising_stats_t", "IsingStats")])
+def test_binding_structs_follow_the_header(cname, pyclass):
+    fields = [f for f, _ in getattr(binding, pyclass)._fields_]
+    assert fields == _header_struct_fields(cname)
