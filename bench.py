@@ -190,16 +190,20 @@ def cpu_baseline(w, budget_s, single_s):
 
 
 # ---------------------------------------------------------------- the C3 workload, one form
-def measure(binding, torch, w, form, steps, warmup, batching=False):
-    """Complete passes of the method over the batch with one form; device-timed."""
+def measure(binding, torch, w, form, steps, warmup, batching=False, graph_steps=0, tune=False):
+    """Complete passes of the method over the batch with one form; device-timed.
+    batching: steps replayed as graphs of graph_steps steps (0: the library's
+    default), scan tiles autotuned per N in the untimed first pass; tune alone
+    autotunes an eager run the same way."""
     s = binding.IsingSearch.from_workload(w, timing=1, persistent=1 if batching else 0,
+                                          graph_steps=graph_steps if batching else 0,
                                           form=FORM_CODES[form], flags=FORM_FLAGS.get(form, 0))
     torch.cuda.synchronize()
     tuned = [False]
 
     def one_pass():
         s.reset()
-        if batching and not tuned[0]:
+        if (batching or tune) and not tuned[0]:
             s.step()
             s.autotune()
             tuned[0] = True
@@ -696,8 +700,17 @@ def main():
         wb = workloads.c4_uneven(n_instances=480 if not args.quick else 96)
         r = measure(binding, torch, wb, "plain", 1, 1, batching=True)
         batching = {k: v for k, v in r.items() if k not in ("E1", "wall", "pairs")}
+        # the same passes with one step per graph (flags read after every
+        # step) and with eager launches, for what the multi-step graph buys
+        batching["graph_steps"] = 8
+        batching["per_graph_steps"] = {"8": {"value": r["value"], "ms_per_step": r["ms_per_step"]}}
+        for tag, kw in (("1", {"batching": True, "graph_steps": 1}), ("eager", {"tune": True})):
+            rk = measure(binding, torch, wb, "plain", 1, 1, **kw)
+            assert rk["E1"] == r["E1"], f"batching: {tag} differs from 8 steps per graph"
+            batching["per_graph_steps"][tag] = {"value": rk["value"], "ms_per_step": rk["ms_per_step"]}
+            log(f"[batching] {tag}: {rk['value']:.3e} evals/s, {rk['ms_per_step']:.1f} ms per pass")
         batching["workload"] = (f"{wb.name}: {len(wb.instances)} instances, N drawn from 100..600 (step 100), "
-                                f"L={wb.L}, M={wb.M}, plain form, graph-replayed steps, scan tiles autotuned per N "
+                                f"L={wb.L}, M={wb.M}, plain form, 8 steps per replayed graph, scan tiles autotuned per N "
                                 f"in the untimed first pass")
         batching["unit"] = "pair-flip dE evals/s"
         batching["roofline_note"] = ("steps run as replayed graphs, timed as a whole (kernel_ms_per_step.step); "

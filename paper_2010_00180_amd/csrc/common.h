@@ -15,6 +15,7 @@
 // scoring network are listed from the back of the instance's frontier list,
 // states enumerated in full from the front.
 #pragma once
+#include <type_traits>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -204,14 +205,19 @@ __host__ __device__ inline long long scan_tiles(const Layout& lay, int N)
 // (E + a_i <= c); returns the number r of such sites (r (r - 1) / 2 pairs
 // evaluated), or -1, having recorded nothing, when there are too many and the
 // state must be prepared for the full scan.  sidx (site | sign << 15) and sa
-// are this wave's LDS arrays of SB_CAP entries.  The loads are batched for
-// latency: a is held in registers (N <= 640), and the pairs are taken in 8 x 8
-// blocks (lane = 8 p + q), all ten blocks at once when r <= 32, else eight at
-// a time.
+// are this wave's LDS arrays of SB_CAP entries, stage its SB_STG survivor
+// records.  The work is a chain of dependent memory rounds, so it is cut into
+// few of them: a is held in registers (N <= 640); the pairs are taken in 8 x 8
+// blocks (lane = 8 p + q), the couplings of SB_BATCH blocks gathered at once;
+// survivors wait in LDS, and one atomic per state (or per full stage) reserves
+// their places in the search's buffer.
 constexpr int SB_AREG = 10;
+constexpr int SB_BATCH = 8;
+constexpr int SB_STG = 128;
+constexpr int SB_GRID = 2048;   // k_site_bound blocks: 8192 waves, eight per SIMD
 __device__ inline int site_bound_pairs(const Layout& lay, int b, int s, int code, double Em, double c,
                                        const uint64_t* __restrict__ x, const double* __restrict__ F,
-                                       int N, int Np, uint16_t* sidx, double* sa)
+                                       int N, int Np, uint16_t* sidx, double* sa, Surv* stage)
 {
     const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
     const double T = c - Em;
@@ -221,28 +227,43 @@ __device__ inline int site_bound_pairs(const Layout& lay, int b, int s, int code
     auto lane_rank = [&](uint64_t m) -> int {
         return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
     };
-    auto record = [&](bool keep, double E, uint32_t pair) {
+    auto wave_sync = [&]() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    // staged survivors: nst (wave-uniform) records in stage[0 .. nst)
+    int nst = 0;
+    auto flush = [&]() {
+        wave_sync();   // the stage's writes before its reads
+        int pos0 = 0;
+        if (lane == 0) pos0 = atomicAdd(&lay.surv_count[s], nst);
+        pos0 = __shfl(pos0, 0, 64);
+        Surv* const out = lay.surv + (size_t)s * lay.cap_surv;
+        for (int k = (int)lane; k < nst; k += 64)
+            if (pos0 + k < lay.cap_surv) out[pos0 + k] = stage[k];
+        wave_sync();   // its reads before it is refilled
+        nst = 0;
+    };
+    auto push = [&](bool keep, double E, uint32_t pair) {
         const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
         if (m) {
-            int pos0 = 0;
-            if (lane == 0) pos0 = atomicAdd(&lay.surv_count[s], __builtin_popcountll(m));
-            pos0 = __shfl(pos0, 0, 64);
-            const int pos = pos0 + lane_rank(m);
-            if (keep && pos < lay.cap_surv) {
+            const int n = __builtin_popcountll(m);
+            if (nst + n > SB_STG) flush();
+            if (keep) {
                 Surv rec;
                 rec.E = E;
                 rec.code = (uint32_t)code;
                 rec.pair = pair;
-                lay.surv[(size_t)s * lay.cap_surv + pos] = rec;
+                stage[nst + lane_rank(m)] = rec;
             }
+            nst += n;
         }
     };
     const double* rm = lay.rmax4 + (size_t)b * lay.Npmax;
     int r = 0;
-    uint32_t hits = 0;       // singles below the cut not yet recorded (register path, r <= 32)
-    bool any_hit = false;
-    double areg[SB_AREG];
     if (N <= 64 * SB_AREG) {
+        double areg[SB_AREG];
         double amin = INFINITY;
 #pragma unroll
         for (int k = 0; k < SB_AREG; ++k) {
@@ -265,21 +286,13 @@ __device__ inline int site_bound_pairs(const Layout& lay, int b, int s, int code
             r += __builtin_popcountll(m);
         }
         if (r > SB_CAP) return -1;
-        // single flips below the cut, as a bit mask of the lane's sites
-#pragma unroll
-        for (int k = 0; k < SB_AREG; ++k) {
-            const int i = 64 * k + (int)lane;
-            if (!xch && i < N && Em + areg[k] <= c) hits |= 1u << k;
-            if (__builtin_amdgcn_ballot_w64((hits >> k) & 1u)) any_hit = true;
-        }
-        if (r > 32) {
+        // single flips below the cut
+        if (!xch) {
 #pragma unroll
             for (int k = 0; k < SB_AREG; ++k) {
                 const int i = 64 * k + (int)lane;
-                record((hits >> k) & 1u, Em + areg[k], (uint32_t)i | (SINGLE << 16));
+                push(i < N && Em + areg[k] <= c, Em + areg[k], (uint32_t)i | (SINGLE << 16));
             }
-            hits = 0;
-            any_hit = false;
         }
     } else {
         double amin = INFINITY;
@@ -302,172 +315,61 @@ __device__ inline int site_bound_pairs(const Layout& lay, int b, int s, int code
                 sa[base + lane_rank(m)] = a;
             }
             base += __builtin_popcountll(m);
-            const double Ec = Em + a;
-            record(!xch && i < N && Ec <= c, Ec, (uint32_t)i | (SINGLE << 16));
+            if (!xch) push(i < N && Em + a <= c, Em + a, (uint32_t)i | (SINGLE << 16));
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // 4J_ij from the exact FP32 copy when there is one (half the bytes per gather)
-    const double* J4 = lay.J4 + lay.joff[b];
-    const float* J4f = lay.J4f ? lay.J4f + lay.joff[b] : nullptr;
-    auto coupling = [&](int i, int j) -> double {
-        return J4f ? (double)J4f[(size_t)i * Np + j] : J4[(size_t)i * Np + j];
-    };
+    wave_sync();   // the site list before it is read
     const int pp = (int)(lane >> 3), qq = (int)(lane & 7);
-    if (r <= 32) {
-        // rows p = 8 P + pp of the four row blocks
-        int iv[4];
-        double av[4], sv4[4];
-#pragma unroll
-        for (int P = 0; P < 4; ++P) {
-            const int p = 8 * P + pp;
-            const uint32_t e = p < r ? sidx[p] : 0u;
-            iv[P] = (int)(e & 0x7FFFu);
-            sv4[P] = (e >> 15) ? -1.0 : 1.0;
-            av[P] = p < r ? sa[p] : 0.0;
+    const int nb = (r + 7) >> 3;
+    // the 8 x 8 blocks (P, Q), P <= Q, in row order, SB_BATCH per round
+    auto next_block = [&](int& P, int& Q) {
+        if (P < nb && ++Q == nb) {
+            ++P;
+            Q = P;
         }
-        // the ten 8 x 8 blocks (P, Q), P <= Q
-        constexpr int BP[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
-        constexpr int BQ[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
-        double xv[10];
-        bool kp[10];
-        int jv[10];
-#pragma unroll
-        for (int k = 0; k < 10; ++k) {
-            const int p = 8 * BP[k] + pp, q = 8 * BQ[k] + qq;
-            kp[k] = false;
-            xv[k] = 0.0;
-            jv[k] = 0;
-            if (p < q && q < r) {
-                const uint32_t e = sidx[q];
-                const int j = (int)(e & 0x7FFFu);
-                const double sj = (e >> 15) ? -1.0 : 1.0;
-                jv[k] = j;
-                xv[k] = fma(sv4[BP[k]], sj * coupling(iv[BP[k]], j), sa[q]);
-                kp[k] = xv[k] <= T - av[BP[k]] && (!xch || sv4[BP[k]] != sj);
-            }
-        }
-        // one atomic reserves the places of the state's singles and pairs
-        int cnt = __builtin_popcount(hits);
-#pragma unroll
-        for (int k = 0; k < 10; ++k) cnt += kp[k] ? 1 : 0;
-        bool any = any_hit;
-#pragma unroll
-        for (int k = 0; k < 10; ++k) any = any || __builtin_amdgcn_ballot_w64(kp[k]) != 0;
-        if (any) {
-            int excl = cnt;
-            for (int off = 1; off < 64; off <<= 1) {
-                const int v = __shfl_up(excl, off, 64);
-                if ((int)lane >= off) excl += v;
-            }
-            const int tot = __shfl(excl, 63, 64);
-            excl -= cnt;
-            int pos0 = 0;
-            if (lane == 0) pos0 = atomicAdd(&lay.surv_count[s], tot);
-            int pos = __shfl(pos0, 0, 64) + excl;
-            Surv* out = lay.surv + (size_t)s * lay.cap_surv;
-#pragma unroll
-            for (int k = 0; k < SB_AREG; ++k) {
-                if ((hits >> k) & 1u) {
-                    if (pos < lay.cap_surv) {
-                        Surv rec;
-                        rec.E = Em + areg[k];
-                        rec.code = (uint32_t)code;
-                        rec.pair = (uint32_t)(64 * k + (int)lane) | (SINGLE << 16);
-                        out[pos] = rec;
-                    }
-                    ++pos;
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < 10; ++k) {
-                if (kp[k]) {
-                    if (pos < lay.cap_surv) {
-                        Surv rec;
-                        rec.E = (Em + av[BP[k]]) + xv[k];
-                        rec.code = (uint32_t)code;
-                        rec.pair = (uint32_t)iv[BP[k]] | ((uint32_t)jv[k] << 16);
-                        out[pos] = rec;
-                    }
-                    ++pos;
-                }
-            }
-        }
-    } else {
-        // the 8 x 8 blocks (P, Q), P <= Q, in row order, eight per batch; one
-        // atomic reserves the places of a batch's survivors
-        const int nb = (r + 7) >> 3;
+    };
+    auto pairs = [&](const auto* __restrict__ Jp) {
+        using JT = typename std::remove_cv<typename std::remove_reference<decltype(*Jp)>::type>::type;
         int P = 0, Q = 0;
         while (P < nb) {
-            int bp[8], bq[8];
+            // the couplings of the round, all loads in flight together
+            JT jc[SB_BATCH];
+            int P1 = P, Q1 = Q;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                bp[u] = P;
-                bq[u] = Q;
-                if (P < nb && ++Q == nb) {
-                    ++P;
-                    Q = P;
+            for (int u = 0; u < SB_BATCH; ++u) {
+                const int p = 8 * P1 + pp, q = 8 * Q1 + qq;
+                jc[u] = (JT)0;
+                if (P1 < nb && p < q && q < r) {
+                    const int i = (int)(sidx[p] & 0x7FFFu), j = (int)(sidx[q] & 0x7FFFu);
+                    jc[u] = Jp[(size_t)i * Np + j];
                 }
+                next_block(P1, Q1);
             }
-            double xv[8], ev[8];
-            bool kp[8];
-            uint32_t pr[8];
-            int cnt = 0;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int p = 8 * bp[u] + pp, q = 8 * bq[u] + qq;
-                kp[u] = false;
-                xv[u] = 0.0;
-                ev[u] = 0.0;
-                pr[u] = 0;
-                if (bp[u] < nb && p < q && q < r) {
+            for (int u = 0; u < SB_BATCH; ++u) {
+                const int p = 8 * P + pp, q = 8 * Q + qq;
+                bool keep = false;
+                double E = 0.0;
+                uint32_t pair = 0;
+                if (P < nb && p < q && q < r) {
                     const uint32_t ei = sidx[p], ej = sidx[q];
-                    const int i = (int)(ei & 0x7FFFu), j = (int)(ej & 0x7FFFu);
                     const double ai = sa[p];
-                    xv[u] = fma((ei >> 15) ? -1.0 : 1.0, ((ej >> 15) ? -1.0 : 1.0) * coupling(i, j), sa[q]);
-                    kp[u] = xv[u] <= T - ai && (!xch || (ei >> 15) != (ej >> 15));
-                    ev[u] = (Em + ai) + xv[u];
-                    pr[u] = (uint32_t)i | ((uint32_t)j << 16);
-                    cnt += kp[u] ? 1 : 0;
+                    const double xv = fma((ei >> 15) ? -1.0 : 1.0, ((ej >> 15) ? -1.0 : 1.0) * (double)jc[u], sa[q]);
+                    keep = xv <= T - ai && (!xch || (ei >> 15) != (ej >> 15));
+                    E = (Em + ai) + xv;
+                    pair = (ei & 0x7FFFu) | ((ej & 0x7FFFu) << 16);
                 }
-            }
-            bool any = false;
-#pragma unroll
-            for (int u = 0; u < 8; ++u) any = any || __builtin_amdgcn_ballot_w64(kp[u]) != 0;
-            if (any) {
-                int excl = cnt;
-                for (int off = 1; off < 64; off <<= 1) {
-                    const int v = __shfl_up(excl, off, 64);
-                    if ((int)lane >= off) excl += v;
-                }
-                const int tot = __shfl(excl, 63, 64);
-                excl -= cnt;
-                int pos0 = 0;
-                if (lane == 0) pos0 = atomicAdd(&lay.surv_count[s], tot);
-                int pos = __shfl(pos0, 0, 64) + excl;
-                Surv* out = lay.surv + (size_t)s * lay.cap_surv;
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    if (kp[u]) {
-                        if (pos < lay.cap_surv) {
-                            Surv rec;
-                            rec.E = ev[u];
-                            rec.code = (uint32_t)code;
-                            rec.pair = pr[u];
-                            out[pos] = rec;
-                        }
-                        ++pos;
-                    }
-                }
+                push(keep, E, pair);
+                next_block(P, Q);
             }
         }
-    }
-    // the list is rewritten by this wave's next state
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    // 4J_ij from the exact FP32 copy when there is one (half the bytes per gather)
+    if (lay.J4f) pairs(lay.J4f + lay.joff[b]);
+    else pairs(lay.J4 + lay.joff[b]);
+    if (nst > 0) flush();
+    // the list and the stage are rewritten by this wave's next state
+    wave_sync();
     return r;
 }
 

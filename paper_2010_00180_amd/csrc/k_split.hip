@@ -147,8 +147,6 @@ template <bool SB, bool H16>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_prep32(Layout lay, const long long* __restrict__ fr_prefix)
 {
     if (step_halted(lay)) return;   // a later step of a multi-step graph after a halt
-    __shared__ uint16_t sb_idx[SB ? 4 : 1][SB ? SB_CAP : 1];
-    __shared__ double sb_a[SB ? 4 : 1][SB ? SB_CAP : 1];
     const long long total = fr_prefix[lay.B];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63;
@@ -167,6 +165,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         while (fr_prefix[b + 1] <= e) ++b;
         const int f = (int)(e - fr_prefix[b]);
         const size_t fe = (size_t)b * lay.fmax + f;
+        // site bound: the states k_site_bound evaluated need nothing here
+        if (SB && lay.fr_bound[fe] != 0) continue;
         const int code = lay.fr_list[fe];
         const int s = code / (2 * lay.M);
         if (retry_mode && !lay.retry[s]) continue;
@@ -197,13 +197,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             // with the site bound the pairs are counted once the entries are sorted out
             if (!lay.sb) atomicAdd(&lay.ctr[CTR_PAIRS], (unsigned long long)N * (N - 1) / 2);
             atomicAdd(&lay.ctr[CTR_SINGLES], (unsigned long long)N);
-        }
-        // site bound: the single and pair flips of a state with few candidate
-        // sites are evaluated here, exactly in FP64, and its FP32 rows are not needed
-        if (SB) {
-            const int r = site_bound_pairs(lay, b, s, code, Em, c, x, F, N, Np, sb_idx[wave], sb_a[wave]);
-            if (lane == 0) lay.fr_bound[fe] = (uint16_t)(r + 1);
-            if (r >= 0) continue;
         }
         // slack of the FP32 threshold, from the instance's bound on |a|
         const double u = 5.9604644775390625e-08;   // 2^-24

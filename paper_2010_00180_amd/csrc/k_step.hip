@@ -725,6 +725,50 @@ __device__ inline int find_instance(const long long* prefix, int B, long long e)
     return lo;
 }
 
+// ------------------------------------------------------------------ k_site_bound
+// Site bound, before the form's preparation: one wave per frontier entry
+// evaluates the state's single flips and the pairs among its bounded sites
+// (site_bound_pairs) and records in fr_bound how it went (1 + r, or 0 when
+// the state has too many such sites and goes to the full scan).  The work
+// is a chain of dependent memory rounds per state, so the kernel is kept lean
+// enough for eight waves per SIMD: that many states are in flight per CU.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_site_bound(
+    Layout lay, const long long* __restrict__ fr_prefix)
+{
+    if (step_halted(lay)) return;   // a later step of a multi-step graph after a halt
+    __shared__ uint16_t sb_idx[4][SB_CAP];
+    __shared__ double sb_a[4][SB_CAP];
+    __shared__ Surv sb_stage[4][SB_STG];
+    const long long total = fr_prefix[lay.B];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63;
+    const int retry_mode = lay.flags[FLAG_RETRY_MODE];
+    // XCD x (blocks x, x + 8, ...) takes the x-th contiguous eighth of the
+    // entries, so the states it bounds at once share one L2 for their couplings
+    const int nx = gridDim.x >= 8 ? 8 : 1;
+    const int xcd = blockIdx.x % nx;
+    const long long seg1 = total * (xcd + 1) / nx;
+    const long long stride = (long long)(gridDim.x / nx) * 4;
+    int b = -1;   // instance of entry e: found once, then advanced (e only grows)
+    for (long long e = total * xcd / nx + (long long)(blockIdx.x / nx) * 4 + wave; e < seg1; e += stride) {
+        if (b < 0) b = find_instance(fr_prefix, lay.B, e);
+        while (fr_prefix[b + 1] <= e) ++b;
+        const size_t fe = (size_t)b * lay.fmax + (size_t)(e - fr_prefix[b]);
+        const int code = lay.fr_list[fe];
+        const int s = code / (2 * lay.M);
+        if (retry_mode && !lay.retry[s]) continue;
+        const size_t q = (size_t)code;
+        const int r = site_bound_pairs(lay, b, s, code, lay.E[q], lay.cut[s], lay.bits + q * lay.Wmax,
+                                       lay.F + q * lay.Npmax, lay.N[b], lay.Npad[b], sb_idx[wave], sb_a[wave],
+                                       sb_stage[wave]);
+        if (lane == 0) {
+            lay.fr_bound[fe] = (uint16_t)(r + 1);
+            // a retry pass counts its single flips here (the pairs in k_sb_list)
+            if (retry_mode && r >= 0) atomicAdd(&lay.ctr[CTR_SINGLES], (unsigned long long)lay.N[b]);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ k_prep
 // One wave per frontier entry: a_i = -2 s_i F_i, the per-state record the
 // scan reads (threshold T = cut - E, energy, search, slot), a copy of the
@@ -733,8 +777,6 @@ template <bool SB>
 __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __restrict__ fr_prefix)
 {
     if (step_halted(lay)) return;   // a later step of a multi-step graph after a halt
-    __shared__ uint16_t sb_idx[SB ? 4 : 1][SB ? SB_CAP : 1];
-    __shared__ double sb_a[SB ? 4 : 1][SB ? SB_CAP : 1];
     const long long total = fr_prefix[lay.B];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63;
@@ -755,6 +797,8 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
         const int P = lay.fr_count[b];
         const bool ranked = f >= P;   // learned form: a ranked entry, listed from the back
         const size_t fe = (size_t)b * lay.fmax + (ranked ? lay.fmax - lay.lr_count[b] + (f - P) : f);
+        // site bound: the states k_site_bound evaluated need nothing here
+        if (SB && lay.fr_bound[fe] != 0) continue;
         const int code = lay.fr_list[fe];
         const int s = code / (2 * lay.M);
         if (retry_mode && !lay.retry[s]) continue;
@@ -782,13 +826,6 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
             if (!lay.sb) atomicAdd(&lay.ctr[CTR_PAIRS], ranked ? (unsigned long long)proposals_of(lay, N) : all);
             atomicAdd(&lay.ctr[CTR_SINGLES], (unsigned long long)N);
             if (ranked) atomicAdd(&lay.ctr[CTR_SCORED], all);
-        }
-        // site bound: the single and pair flips of a state with few candidate
-        // sites are evaluated here, and the scan does not need its a row
-        if (SB) {
-            const int r = site_bound_pairs(lay, b, s, code, Em, c, x, F, N, Np, sb_idx[wave], sb_a[wave]);
-            if (lane == 0) lay.fr_bound[fe] = (uint16_t)(r + 1);
-            if (r >= 0) continue;
         }
         // a_i, and the single flips below the cut, in rounds of PREP_BLOCKS
         // blocks of 64 sites: the loads of a round are issued together (blocks
@@ -1949,11 +1986,15 @@ __global__ __launch_bounds__(1024) void k_sb_items(Layout lay)
 hipError_t launch_prep(const Layout& lay, hipStream_t st, bool count)
 {
     if (lay.form == 1) {
+        if (lay.sb)
+            hipLaunchKernelGGL(k_site_bound, dim3(SB_GRID), dim3(256), 0, st, lay,
+                               (const long long*)(lay.item_prefix + (lay.B + 1)));
         hipError_t e = launch_prep32(lay, st);
         if (e == hipSuccess && lay.sb) hipLaunchKernelGGL(k_sb_list, dim3(lay.B), dim3(256), 0, st, lay, count ? 1 : 0);
         return e == hipSuccess ? hipGetLastError() : e;
     }
     const long long* fr_prefix = lay.item_prefix + (lay.B + 1);
+    if (lay.sb) hipLaunchKernelGGL(k_site_bound, dim3(SB_GRID), dim3(256), 0, st, lay, fr_prefix);
     if (lay.sb) hipLaunchKernelGGL(k_prep<true>, dim3(4096), dim3(256), 0, st, lay, fr_prefix);
     else hipLaunchKernelGGL(k_prep<false>, dim3(4096), dim3(256), 0, st, lay, fr_prefix);
     if (lay.sb) {
