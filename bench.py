@@ -237,18 +237,23 @@ def measure(binding, torch, w, form, steps, warmup, batching=False, graph_steps=
         # the steps are replayed graphs: no per-kernel times
         roofline = None
     elif form in SITE_BOUND_FORMS:
-        # the preparation kernel evaluates the bounded states: its algorithmic
-        # bytes are the F row of each expanded state (8N) and one FP32 coupling
-        # per evaluated pair (4)
-        prep_s = d["prep_ms"] / 1e3
+        # k_site_bound evaluates the bounded states: its algorithmic bytes are
+        # the F row of each bounded state (8N) and one FP32 coupling per pair
+        # it evaluates (4); the few states it sends to the full scan are
+        # counted there
+        bound_s = d["bound_ms"] / 1e3
         N = w.instances[0].N
-        nbytes = d["frontier_states"] * 8 * N + 4 * pairs
-        gbs = nbytes / prep_s / 1e9 if prep_s > 0 else 0.0
+        nb = d["bounded_states"]
+        sb_pairs = pairs - (d["frontier_states"] - nb) * (N * (N - 1) // 2)
+        nbytes = nb * 8 * N + 4 * sb_pairs
+        gbs = nbytes / bound_s / 1e9 if bound_s > 0 else 0.0
         roofline = {
-            "kernel": "k_prep32 (site bound)" if FORM_CODES[form] == 1 else "k_prep (site bound)",
+            "kernel": "k_site_bound",
             "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-            "avg_launch_ms": d["prep_ms"] / launches,
-            "bytes_model": "8N per expanded state (its F row) + 4 per evaluated pair (an FP32 coupling)",
+            "avg_launch_ms": d["bound_ms"] / launches,
+            "bytes_per_launch": nbytes / launches,
+            "bytes_model": "8N per bounded state (its F row) + 4 per pair it evaluates (an FP32 coupling)",
+            "note": "latency-bound: a chain of dependent memory rounds per state, eight waves per SIMD",
         }
     else:
         ops_per_s = OPS_PER_PAIR * pairs / scan_s if scan_s > 0 else 0.0
@@ -271,7 +276,7 @@ def measure(binding, torch, w, form, steps, warmup, batching=False, graph_steps=
         "E1": E1,
         "mean_E1": sum(E1) / len(E1),
         "scan_kernel_evals_per_s": pairs / scan_s if scan_s > 0 else None,
-        "kernel_ms_per_step": {k: d[k + "_ms"] / steps for k in ("scan", "merge", "frontier", "prep", "init", "step")},
+        "kernel_ms_per_step": {k: d[k + "_ms"] / steps for k in ("scan", "merge", "frontier", "prep", "bound", "init", "step")},
         "survivors": d["survivors"], "retries": d["retries"],
         "rescore_rejections": d["fallbacks"],
         "split_field_err": st1.get("split_field_err"),

@@ -120,6 +120,17 @@ typedef struct {
                                   copies of fewer than M distinct states) every buffer doubles, a
                                   device allocation inside the step, up to 2^24 records
                                   (stats.surv_capacity); past that the step fails with CAPACITY */
+    const char *tile_cache;    /* NULL, or a text file of tuned scan tiles that ising_search_autotune
+                                  reads and appends to: one line per (device architecture, form,
+                                  flags, N, M) with the states per item it chose.  Sizes found there
+                                  are not timed again.  The path is copied; the file is created at
+                                  init when missing (INVALID_ARG if it cannot be opened to append).
+                                  Lines that do not parse are ignored. */
+    const char *mlp_weights;   /* learned form: NULL, or a file of exactly ising_mlp_num_params()
+                                  little-endian FP32 values (the parameter vector described with the
+                                  learned form) that init installs as the network scorer, as
+                                  ising_search_set_scorer(NETWORK, params, 0) would; INVALID_ARG if it
+                                  cannot be read, has another size or holds a non-finite value */
 } ising_config_t;
 
 typedef struct {
@@ -148,6 +159,8 @@ typedef struct {
                                   bounded sites only */
     uint64_t surv_capacity;    /* candidate records per search now: cfg.surv_capacity or its
                                   default, doubled each time a step's candidates could not fit */
+    double bound_ms;           /* site bound: device time of the site-bound kernel, summed (part of
+                                  prep_ms) */
 } ising_stats_t;
 
 /*
@@ -238,7 +251,10 @@ int ising_search_get_stats(ising_search_t *s, ising_stats_t *out);
  * states per item to the steps (states_per_item 0), the tuned tiles are then
  * timed against that per-step choice and the faster is kept.  Results do not
  * depend on the choice; only the time does.  Best called once the frontier is
- * full (after the first step).
+ * full (after the first step).  With cfg.tile_cache, sizes listed there for
+ * this device, form, flags and M take the listed tiles untimed (the per-step
+ * choice is then kept only if every listed size asks for it), and the sizes
+ * tuned here are appended to the file.
  */
 int ising_search_autotune(ising_search_t *s, int32_t *n_active);
 

@@ -80,6 +80,8 @@ class IsingConfig(ctypes.Structure):
         ("flags", ctypes.c_int32),
         ("graph_steps", ctypes.c_int32),
         ("surv_capacity", ctypes.c_int32),
+        ("tile_cache", ctypes.c_char_p),
+        ("mlp_weights", ctypes.c_char_p),
     ]
 
 
@@ -106,10 +108,21 @@ class IsingStats(ctypes.Structure):
         ("learn_ms", ctypes.c_double),
         ("bounded_states", ctypes.c_uint64),
         ("surv_capacity", ctypes.c_uint64),
+        ("bound_ms", ctypes.c_double),
     ]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def save_mlp_weights(path: str, params) -> None:
+    """Write the network's parameter vector as the file cfg.mlp_weights reads:
+    MLP_NPARAM little-endian FP32 values."""
+    params = np.ascontiguousarray(params, dtype="<f4").reshape(-1)
+    if params.size != MLP_NPARAM:
+        raise ValueError(f"the network has {MLP_NPARAM} parameters, got {params.size}")
+    with open(path, "wb") as f:
+        f.write(params.tobytes())
 
 
 class IsingError(RuntimeError):
@@ -304,7 +317,8 @@ class IsingSearch:
     def __init__(self, Ns: Sequence[int], Js, hs, init_bits, M: int, form: int = FORM_PLAIN,
                  max_iters: int = 0, states_per_item: int = 0, topk_factor: int = 8,
                  persistent: int = 0, timing: int = 0, stream: Optional[int] = None, flags: int = 0,
-                 graph_steps: int = 0, surv_capacity: int = 0):
+                 graph_steps: int = 0, surv_capacity: int = 0, tile_cache: Optional[str] = None,
+                 mlp_weights: Optional[str] = None):
         L = load()
         self.Ns = [int(n) for n in Ns]
         self.B = len(self.Ns)
@@ -333,7 +347,9 @@ class IsingSearch:
         cfg = IsingConfig(M=self.M, max_iters=int(max_iters), form=int(form),
                           states_per_item=int(states_per_item), topk_factor=int(topk_factor),
                           persistent=int(persistent), timing=int(timing), flags=int(flags),
-                          graph_steps=int(graph_steps), surv_capacity=int(surv_capacity))
+                          graph_steps=int(graph_steps), surv_capacity=int(surv_capacity),
+                          tile_cache=os.fsencode(tile_cache) if tile_cache else None,
+                          mlp_weights=os.fsencode(mlp_weights) if mlp_weights else None)
         if stream is None:
             stream = current_stream_handle()
         h = ctypes.c_void_p()

@@ -60,8 +60,8 @@ struct ising_search {
     int flags_h[8]{};
     // timing (cfg.timing): events around each kernel family of a step
     bool timing = false;
-    hipEvent_t ev[7]{};
-    double t_scan = 0, t_merge = 0, t_frontier = 0, t_prep = 0, t_init = 0, t_step = 0, t_learn = 0;
+    hipEvent_t ev[8]{};
+    double t_scan = 0, t_merge = 0, t_frontier = 0, t_prep = 0, t_init = 0, t_step = 0, t_learn = 0, t_bound = 0;
     // learned-proposal form
     bool scorer_set = false;
     bool record = false;
@@ -80,6 +80,9 @@ struct ising_search {
     hipStream_t own_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    // tuned scan tiles: cache file (empty = none) and the device's architecture
+    std::string tile_cache;
+    std::string arch;
     // run() in persistent mode: graph_steps steps captured into one graph
     int graph_steps = 1;
     hipGraph_t graph_k = nullptr;
@@ -183,6 +186,64 @@ int check_handle(ising_search_t* s)
     return ISING_OK;
 }
 
+// The network's parameter vector from a file of MLP_NPARAM little-endian
+// FP32 values.
+int read_weights(const char* path, std::vector<float>& out)
+{
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(ISING_ERR_INVALID_ARG, "mlp_weights %s cannot be read", path);
+    std::vector<unsigned char> raw(sizeof(float) * MLP_NPARAM + 1);
+    const size_t got = std::fread(raw.data(), 1, raw.size(), f);
+    std::fclose(f);
+    if (got != sizeof(float) * MLP_NPARAM)
+        return fail(ISING_ERR_INVALID_ARG, "mlp_weights %s: %zu bytes, expected %zu (%d FP32 values)", path, got,
+                    sizeof(float) * MLP_NPARAM, MLP_NPARAM);
+    out.assign(MLP_NPARAM, 0.f);
+    for (int k = 0; k < MLP_NPARAM; ++k) {
+        const unsigned char* b = raw.data() + 4 * k;
+        const uint32_t u = (uint32_t)b[0] | ((uint32_t)b[1] << 8) | ((uint32_t)b[2] << 16) | ((uint32_t)b[3] << 24);
+        std::memcpy(&out[k], &u, 4);
+        if (!std::isfinite(out[k])) return fail(ISING_ERR_INVALID_ARG, "mlp_weights %s: value %d is not finite", path, k);
+    }
+    return ISING_OK;
+}
+
+// Tile cache lines: "ising-tile 1 <arch> <form> <flags> <N> <M> <states per item> <per-step>".
+struct TileKey {
+    std::string arch;
+    int form, flags, N, M;
+};
+
+void read_tile_cache(const std::string& path, const TileKey& k, int& spi, int& per_step)
+{
+    spi = 0;
+    per_step = 0;
+    FILE* f = std::fopen(path.c_str(), "r");
+    if (!f) return;
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        char tag[32], arch[256];
+        int ver, form, flags, N, M, v, a;
+        if (std::sscanf(line, "%31s %d %255s %d %d %d %d %d %d", tag, &ver, arch, &form, &flags, &N, &M, &v, &a) != 9)
+            continue;
+        if (std::strcmp(tag, "ising-tile") != 0 || ver != 1) continue;
+        if (k.arch != arch || k.form != form || k.flags != flags || k.N != N || k.M != M) continue;
+        if (v != 16 && v != 32 && v != 64 && v != 128 && v != 256) continue;
+        spi = v;   // the last matching line wins
+        per_step = a != 0;
+    }
+    std::fclose(f);
+}
+
+int append_tile_cache(const std::string& path, const TileKey& k, int spi, int per_step)
+{
+    FILE* f = std::fopen(path.c_str(), "a");
+    if (!f) return fail(ISING_ERR_INVALID_ARG, "tile_cache %s cannot be opened to append", path.c_str());
+    std::fprintf(f, "ising-tile 1 %s %d %d %d %d %d %d\n", k.arch.c_str(), k.form, k.flags, k.N, k.M, spi, per_step);
+    const bool ok = std::fclose(f) == 0;
+    return ok ? ISING_OK : fail(ISING_ERR_INVALID_ARG, "tile_cache %s could not be written", path.c_str());
+}
+
 int sync_flags(ising_search* h)
 {
     HIP_TRY(hipMemcpyAsync(h->flags_h, h->lay.flags, sizeof(h->flags_h), hipMemcpyDeviceToHost, h->stream));
@@ -229,8 +290,21 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     if (cfg->surv_capacity != 0 && (cfg->surv_capacity < 2 * cfg->M || cfg->surv_capacity < 64 ||
                                     cfg->surv_capacity > MAX_SURV_CAP))
         return fail(ISING_ERR_INVALID_ARG, "surv_capacity=%d: 0, or between max(2M, 64) and 2^24", cfg->surv_capacity);
+    int rc0 = ISING_OK;
     if (cfg->states_per_item < 0 || cfg->states_per_item > 4096)
         return fail(ISING_ERR_INVALID_ARG, "states_per_item=%d outside [0, 4096]", cfg->states_per_item);
+    std::vector<float> weights;
+    if (cfg->mlp_weights) {
+        if (cfg->form != ISING_FORM_LEARNED)
+            return fail(ISING_ERR_INVALID_ARG, "mlp_weights belongs to the learned form");
+        rc0 = read_weights(cfg->mlp_weights, weights);
+        if (rc0 != ISING_OK) return rc0;
+    }
+    if (cfg->tile_cache && cfg->tile_cache[0]) {
+        FILE* f = std::fopen(cfg->tile_cache, "a");
+        if (!f) return fail(ISING_ERR_INVALID_ARG, "tile_cache %s cannot be opened to append", cfg->tile_cache);
+        std::fclose(f);
+    }
     if (n_inst < 1) return fail(ISING_ERR_INVALID_ARG, "n_inst=%d < 1", n_inst);
     if (L < 1) return fail(ISING_ERR_INVALID_ARG, "L=%d < 1", L);
     if (!N || !J || !h || !init_bits) return fail(ISING_ERR_INVALID_ARG, "NULL array argument");
@@ -657,8 +731,10 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     }
     int cus = 256;
     hipDeviceProp_t prop;
+    std::memset(&prop, 0, sizeof prop);
     if (hipGetDeviceProperties(&prop, hd->device) == hipSuccess && prop.multiProcessorCount > 0)
         cus = prop.multiProcessorCount;
+    prop.gcnArchName[sizeof(prop.gcnArchName) - 1] = 0;
     hd->scan_grid = cus * 16;
     hd->lay.scan_waves = hd->scan_grid;
     if (frontier_set_lds(lay) != hipSuccess) {
@@ -676,6 +752,19 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
         if (dalloc(hd, &tmp, (size_t)hd->learn_grid * lay.kmax) != ISING_OK) return bail(ISING_ERR_OUT_OF_MEMORY);
         lay.lr_tmp = tmp;
     }
+    if (!weights.empty()) {
+        if (hipMemcpyAsync(hd->d_mlp, weights.data(), sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice,
+                           hd->stream) != hipSuccess || hipStreamSynchronize(hd->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            return bail(fail(ISING_ERR_HIP, "copy of the network parameters failed"));
+        }
+        hd->lay.scorer = ISING_SCORER_NETWORK;
+        hd->scorer_set = true;
+    }
+    if (cfg->tile_cache) hd->tile_cache = cfg->tile_cache;
+    hd->cfg.tile_cache = nullptr;   // the caller's strings are not kept
+    hd->cfg.mlp_weights = nullptr;
+    hd->arch = prop.gcnArchName;
     {
         std::lock_guard<std::mutex> g(g_live_mu);
         g_live.insert(hd);
@@ -699,7 +788,7 @@ static hipError_t launch_pass(ising_search* h, bool retry_mode)
     if (e == hipSuccess) e = launch_step_begin(lay, retry_mode, st);
     if (e == hipSuccess && !retry_mode) e = launch_frontier_plan(lay, st);
     rec(1);
-    if (e == hipSuccess) e = launch_prep(lay, st);
+    if (e == hipSuccess) e = launch_prep(lay, st, true, tm && lay.sb ? ev[7] : nullptr);
     rec(2);
     if (e == hipSuccess) e = launch_scan(lay, h->scan_grid, st);
     if (lay.form == ISING_FORM_LEARNED) {
@@ -720,6 +809,7 @@ static void collect_times(ising_search* h)
     if (!h->timing) return;
     h->t_frontier += elapsed_ms(h->ev[0], h->ev[1]);
     h->t_prep += elapsed_ms(h->ev[1], h->ev[2]);
+    if (h->lay.sb) h->t_bound += elapsed_ms(h->ev[1], h->ev[7]);
     if (h->lay.form == ISING_FORM_LEARNED) {
         h->t_scan += elapsed_ms(h->ev[2], h->ev[6]);
         h->t_learn += elapsed_ms(h->ev[6], h->ev[3]);
@@ -948,7 +1038,23 @@ extern "C" int ising_search_autotune(ising_search_t* s, int32_t* n_active)
         if (r == hipSuccess) ms = elapsed_ms(e0, e1);
         return r;
     };
+    // sizes the cache lists take its tiles untimed
+    const bool cache = !s->tile_cache.empty();
+    std::vector<char> cached(sizes.size(), 0);
+    int cached_per_step = 1;
+    for (size_t k = 0; cache && k < sizes.size(); ++k) {
+        int v = 0, a = 0;
+        read_tile_cache(s->tile_cache, TileKey{s->arch, lay.form, s->cfg.flags, sizes[k], lay.M}, v, a);
+        if (v > 0) {
+            cached[k] = 1;
+            cached_per_step &= a;
+            for (int b = 0; b < lay.B; ++b)
+                if (s->N[b] == sizes[k]) s->sc_h[b] = v;
+        }
+    }
+    const bool all_cached = cache && std::all_of(cached.begin(), cached.end(), [](char c) { return c != 0; });
     for (size_t k = 0; k < sizes.size() && e == hipSuccess; ++k) {
+        if (cached[k]) continue;
         int best = -1;
         float best_ms = 0.f;
         for (int c : cand) {
@@ -966,7 +1072,9 @@ extern "C" int ising_search_autotune(ising_search_t* s, int32_t* n_active)
             if (s->N[b] == sizes[k]) s->sc_h[b] = best;
     }
     // the per-step choice competes with the tuned tiles on this step's frontier
-    if (e == hipSuccess && s->sc_auto_ok) {
+    if (e == hipSuccess && s->sc_auto_ok && all_cached) {
+        s->lay.sc_auto = cached_per_step;
+    } else if (e == hipSuccess && s->sc_auto_ok) {
         float ms_t = 0.f, ms_a = 0.f;
         e = scan_ms(ms_t, false);
         if (e == hipSuccess) {
@@ -974,6 +1082,20 @@ extern "C" int ising_search_autotune(ising_search_t* s, int32_t* n_active)
             e = scan_ms(ms_a, false);
         }
         if (e == hipSuccess && !(ms_a < ms_t)) s->lay.sc_auto = 0;
+    }
+    // the sizes tuned here go to the cache
+    for (size_t k = 0; cache && k < sizes.size() && e == hipSuccess; ++k) {
+        if (cached[k]) continue;
+        int v = 0;
+        for (int b = 0; b < lay.B; ++b)
+            if (s->N[b] == sizes[k]) v = s->sc_h[b];
+        rc = append_tile_cache(s->tile_cache, TileKey{s->arch, lay.form, s->cfg.flags, sizes[k], lay.M}, v,
+                               s->lay.sc_auto);
+        if (rc != ISING_OK) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return rc;
+        }
     }
     // the step itself with the chosen tiles
     float ms = 0.f;
@@ -1270,6 +1392,7 @@ extern "C" int ising_search_get_stats(ising_search_t* s, ising_stats_t* out)
     out->learn_ms = s->t_learn;
     out->bounded_states = c[CTR_BOUNDED];
     out->surv_capacity = (uint64_t)s->lay.cap_surv;
+    out->bound_ms = s->t_bound;
     return ISING_OK;
 }
 

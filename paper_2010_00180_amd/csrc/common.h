@@ -379,7 +379,8 @@ hipError_t launch_fields_for(const Layout& lay, int search, int count, hipStream
 hipError_t launch_frontier_plan(const Layout& lay, hipStream_t st);
 hipError_t launch_plan_only(const Layout& lay, hipStream_t st);      // re-plan without counting
 hipError_t launch_clear_survivors(const Layout& lay, hipStream_t st);
-hipError_t launch_prep(const Layout& lay, hipStream_t st, bool count = true);
+// after_bound, if given, is recorded once the site-bound kernel is queued
+hipError_t launch_prep(const Layout& lay, hipStream_t st, bool count = true, hipEvent_t after_bound = nullptr);
 hipError_t launch_scan(const Layout& lay, int scan_grid, hipStream_t st);
 hipError_t launch_merge(const Layout& lay, hipStream_t st);
 hipError_t launch_fupdate(const Layout& lay, hipStream_t st);

@@ -1983,18 +1983,21 @@ __global__ __launch_bounds__(1024) void k_sb_items(Layout lay)
     if (t == 1023) lay.item_prefix[lay.B] = part[1023];
 }
 
-hipError_t launch_prep(const Layout& lay, hipStream_t st, bool count)
+hipError_t launch_prep(const Layout& lay, hipStream_t st, bool count, hipEvent_t after_bound)
 {
+    const long long* fr_prefix = lay.item_prefix + (lay.B + 1);
+    if (lay.sb) {
+        hipLaunchKernelGGL(k_site_bound, dim3(SB_GRID), dim3(256), 0, st, lay, fr_prefix);
+        if (after_bound) {
+            const hipError_t e = hipEventRecord(after_bound, st);
+            if (e != hipSuccess) return e;
+        }
+    }
     if (lay.form == 1) {
-        if (lay.sb)
-            hipLaunchKernelGGL(k_site_bound, dim3(SB_GRID), dim3(256), 0, st, lay,
-                               (const long long*)(lay.item_prefix + (lay.B + 1)));
         hipError_t e = launch_prep32(lay, st);
         if (e == hipSuccess && lay.sb) hipLaunchKernelGGL(k_sb_list, dim3(lay.B), dim3(256), 0, st, lay, count ? 1 : 0);
         return e == hipSuccess ? hipGetLastError() : e;
     }
-    const long long* fr_prefix = lay.item_prefix + (lay.B + 1);
-    if (lay.sb) hipLaunchKernelGGL(k_site_bound, dim3(SB_GRID), dim3(256), 0, st, lay, fr_prefix);
     if (lay.sb) hipLaunchKernelGGL(k_prep<true>, dim3(4096), dim3(256), 0, st, lay, fr_prefix);
     else hipLaunchKernelGGL(k_prep<false>, dim3(4096), dim3(256), 0, st, lay, fr_prefix);
     if (lay.sb) {

@@ -205,3 +205,52 @@ def _header_struct_fields(name):
 def test_binding_structs_follow_the_header(cname, pyclass):
     fields = [f for f, _ in getattr(binding, pyclass)._fields_]
     assert fields == _header_struct_fields(cname)
+
+
+@pytest.mark.parametrize("case", ["not_learned", "missing", "short", "long", "nan", "cache_dir"])
+def test_init_rejects_bad_config_files(case, tmp_path):
+    """The weights file and the tile cache are checked before any device call."""
+    inst = _good()
+    cfg = binding.IsingConfig(M=8, form=binding.FORM_LEARNED)
+    good = tmp_path / "w.bin"
+    binding.save_mlp_weights(str(good), np.zeros(binding.MLP_NPARAM, np.float32))
+    path = good
+    if case == "not_learned":
+        cfg.form = binding.FORM_PLAIN
+    elif case == "missing":
+        path = tmp_path / "absent.bin"
+    elif case == "short":
+        path = tmp_path / "short.bin"
+        path.write_bytes(b"\0" * (4 * binding.MLP_NPARAM - 4))
+    elif case == "long":
+        path = tmp_path / "long.bin"
+        path.write_bytes(b"\0" * (4 * binding.MLP_NPARAM + 4))
+    elif case == "nan":
+        p = np.zeros(binding.MLP_NPARAM, np.float32)
+        p[17] = np.nan
+        path = tmp_path / "nan.bin"
+        path.write_bytes(p.astype("<f4").tobytes())
+    if case == "cache_dir":
+        cfg.tile_cache = os.fsencode(str(tmp_path / "no" / "such" / "dir" / "tiles.txt"))
+    else:
+        cfg.mlp_weights = os.fsencode(str(path))
+    rc, hnd = _init(cfg, [inst.N], [inst.J], [inst.h], 2, [inst.init_bits])
+    assert rc == binding.ISING_ERR_INVALID_ARG, (case, rc, binding.last_error())
+    assert hnd.value is None
+
+
+def test_good_config_files_pass_validation(tmp_path):
+    """Valid files get past validation (here to the missing device); the tile
+    cache is created."""
+    inst = _good()
+    w = tmp_path / "w.bin"
+    binding.save_mlp_weights(str(w), np.linspace(-1, 1, binding.MLP_NPARAM))
+    assert w.stat().st_size == 4 * binding.MLP_NPARAM
+    cache = tmp_path / "tiles.txt"
+    cfg = binding.IsingConfig(M=8, form=binding.FORM_LEARNED, mlp_weights=os.fsencode(str(w)),
+                              tile_cache=os.fsencode(str(cache)))
+    rc, hnd = _init(cfg, [inst.N], [inst.J], [inst.h], 2, [inst.init_bits])
+    assert rc in (binding.ISING_OK, binding.ISING_ERR_NO_DEVICE), binding.last_error()
+    assert cache.exists()
+    if rc == binding.ISING_OK:
+        binding.load().ising_search_destroy(hnd)
