@@ -495,7 +495,7 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
         }
     }
     const bool sb = (cfg->flags & ISING_FLAG_SITE_BOUND) != 0;
-    double* drm = nullptr;
+    float* drm = nullptr;
     if (sb) {
         ALLOC(drm, (size_t)n_inst * lay.Npmax);
         ALLOC(lay.fr_bound, (size_t)n_inst * lay.fmax);
@@ -679,19 +679,21 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
             cp(debf, ebfh.data(), sizeof(double) * n_inst);
             cp(dab, abh.data(), sizeof(double) * n_inst);
         }
-        std::vector<double> rmh;
+        std::vector<float> rmh;
         if (sb) {
-            // site bound: max_j |4J_ij| per row
-            rmh.assign((size_t)n_inst * lay.Npmax, 0.0);
+            // site bound: max_j |4J_ij| per row, rounded up to FP32
+            rmh.assign((size_t)n_inst * lay.Npmax, 0.f);
             for (int b = 0; b < n_inst; ++b) {
                 const int n = N[b];
                 for (int i = 0; i < n; ++i) {
                     double m = 0.0;
                     for (int j = 0; j < n; ++j) m = std::max(m, std::fabs(4.0 * J[b][(size_t)i * n + j]));
-                    rmh[(size_t)b * lay.Npmax + i] = m;
+                    float f = (float)m;
+                    if ((double)f < m) f = std::nextafter(f, INFINITY);
+                    rmh[(size_t)b * lay.Npmax + i] = f;
                 }
             }
-            cp(drm, rmh.data(), sizeof(double) * rmh.size());
+            cp(drm, rmh.data(), sizeof(float) * rmh.size());
         }
         std::vector<uint16_t> jnh;
         if (cfg->form == ISING_FORM_LEARNED) {

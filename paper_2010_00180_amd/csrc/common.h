@@ -87,7 +87,7 @@ struct Layout {
     // site bound (forms 0 and 1, on request): a state whose pairs can only
     // involve a few sites has them evaluated in the preparation kernel
     int sb;                  // 1 = site bound on
-    const double* rmax4;     // [B][Npmax] max_j |4J_ij| of row i
+    const float* rmax4;      // [B][Npmax] max_j |4J_ij| of row i, rounded up to FP32
     uint16_t* fr_bound;      // [B][fmax] 0 = scanned in full, else 1 + the sites kept by the bound
     int* full_list;          // [B][fmax] entries left to the scan, in frontier order
     int* full_count;         // [B]
@@ -195,6 +195,14 @@ __host__ __device__ inline long long scan_tiles(const Layout& lay, int N)
     return lay.form == 1 ? (lay.h16 ? tiles16(N) : tiles64(N)) : tiles_of(N);
 }
 
+// Word k of a state held by lane k (k < 64), as a wave-uniform value.
+__device__ inline uint64_t word_of_lane(uint64_t xw, int k)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)xw, k);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(xw >> 32), k);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // Site bound of one frontier state, evaluated by one wave.  The pair (i, j)
 // changes the energy by a_i + a_j + s_i s_j 4J_ij >= a_i + min_k a_k - max_k |4J_ik|,
 // so it can pass the cut c only if both sites satisfy
@@ -260,15 +268,23 @@ __device__ inline int site_bound_pairs(const Layout& lay, int b, int s, int code
             nst += n;
         }
     };
-    const double* rm = lay.rmax4 + (size_t)b * lay.Npmax;
+    // the bound's max |4J_ik| rounded up: a site it keeps needlessly only
+    // costs the evaluation of its pairs
+    const float* rm = lay.rmax4 + (size_t)b * lay.Npmax;
     int r = 0;
     if (N <= 64 * SB_AREG) {
+        // the state's words in one load (word k held by lane k, its bits then
+        // the lane mask of the flipped spins), and a
+        const uint64_t xw = (int)lane < words_of(N) ? x[lane] : 0ull;
         double areg[SB_AREG];
+        uint32_t negm = 0;   // bit k: site 64k + lane has s = -1
         double amin = INFINITY;
 #pragma unroll
         for (int k = 0; k < SB_AREG; ++k) {
             const int i = 64 * k + (int)lane;
-            areg[k] = i < N ? (bit(i) ? 2.0 : -2.0) * F[i] : 0.0;
+            const bool neg = 64 * k < N && __builtin_amdgcn_inverse_ballot_w64(word_of_lane(xw, k));
+            negm |= (neg ? 1u : 0u) << k;
+            areg[k] = i < N ? (neg ? 2.0 : -2.0) * F[i] : 0.0;
             if (i < N) amin = fmin(amin, areg[k]);
         }
         for (int off = 32; off > 0; off >>= 1) amin = fmin(amin, __shfl_xor(amin, off, 64));
@@ -276,11 +292,11 @@ __device__ inline int site_bound_pairs(const Layout& lay, int b, int s, int code
 #pragma unroll
         for (int k = 0; k < SB_AREG; ++k) {
             const int i = 64 * k + (int)lane;
-            const bool in = i < N && (areg[k] + amin) - rm[i] <= T;
+            const bool in = i < N && (areg[k] + amin) - (double)rm[i] <= T;
             const uint64_t m = __builtin_amdgcn_ballot_w64(in);
             const int pos = r + lane_rank(m);
             if (in && pos < SB_CAP) {
-                sidx[pos] = (uint16_t)(i | (bit(i) << 15));
+                sidx[pos] = (uint16_t)(i | (((negm >> k) & 1u) << 15));
                 sa[pos] = areg[k];
             }
             r += __builtin_popcountll(m);
@@ -300,7 +316,7 @@ __device__ inline int site_bound_pairs(const Layout& lay, int b, int s, int code
         for (int off = 32; off > 0; off >>= 1) amin = fmin(amin, __shfl_xor(amin, off, 64));
         for (int i0 = 0; i0 < N; i0 += 64) {
             const int i = i0 + (int)lane;
-            const bool in = i < N && ((bit(i) ? 2.0 : -2.0) * F[i] + amin) - rm[i] <= T;
+            const bool in = i < N && ((bit(i) ? 2.0 : -2.0) * F[i] + amin) - (double)rm[i] <= T;
             r += __builtin_popcountll(__builtin_amdgcn_ballot_w64(in));
         }
         if (r > SB_CAP) return -1;
@@ -308,7 +324,7 @@ __device__ inline int site_bound_pairs(const Layout& lay, int b, int s, int code
         for (int i0 = 0; i0 < N; i0 += 64) {
             const int i = i0 + (int)lane;
             const double a = i < N ? (bit(i) ? 2.0 : -2.0) * F[i] : 0.0;
-            const bool in = i < N && (a + amin) - rm[i] <= T;
+            const bool in = i < N && (a + amin) - (double)rm[i] <= T;
             const uint64_t m = __builtin_amdgcn_ballot_w64(in);
             if (in) {
                 sidx[base + lane_rank(m)] = (uint16_t)(i | (bit(i) << 15));
@@ -330,13 +346,14 @@ __device__ inline int site_bound_pairs(const Layout& lay, int b, int s, int code
     };
     auto pairs = [&](const auto* __restrict__ Jp) {
         using JT = typename std::remove_cv<typename std::remove_reference<decltype(*Jp)>::type>::type;
+        constexpr int NBAT = sizeof(JT) == 8 ? SB_BATCH / 2 : SB_BATCH;   // registers per round alike
         int P = 0, Q = 0;
         while (P < nb) {
             // the couplings of the round, all loads in flight together
-            JT jc[SB_BATCH];
+            JT jc[NBAT];
             int P1 = P, Q1 = Q;
 #pragma unroll
-            for (int u = 0; u < SB_BATCH; ++u) {
+            for (int u = 0; u < NBAT; ++u) {
                 const int p = 8 * P1 + pp, q = 8 * Q1 + qq;
                 jc[u] = (JT)0;
                 if (P1 < nb && p < q && q < r) {
@@ -346,7 +363,7 @@ __device__ inline int site_bound_pairs(const Layout& lay, int b, int s, int code
                 next_block(P1, Q1);
             }
 #pragma unroll
-            for (int u = 0; u < SB_BATCH; ++u) {
+            for (int u = 0; u < NBAT; ++u) {
                 const int p = 8 * P + pp, q = 8 * Q + qq;
                 bool keep = false;
                 double E = 0.0;

@@ -32,12 +32,6 @@ __device__ inline uint32_t mbcnt64(uint64_t m)
 __device__ inline int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Word k of a state held one word per lane (lane k), as a wave-uniform value.
-__device__ inline uint64_t word_of_lane(uint64_t xw, int k)
-{
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)xw, k);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(xw >> 32), k);
-    return ((uint64_t)hi << 32) | lo;
-}
 
 // blocks of 64 sites whose loads a preparation wave issues together
 constexpr int PREP_BLOCKS = 8;
