@@ -312,16 +312,29 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
 
     int Nmax = 0;
     bool j32_exact = true;   // every 4J_ij exactly representable in FP32
+    // local fields as 32-bit integers: instance b's grid 2^-g_b (the coarsest
+    // power of two that all its values are multiples of, g_b in [0, 24]) and
+    // |F_i| <= |h_i| + sum_j |J_ij| < 2^31 grid units for every instance
+    bool fq_ok = true;
+    std::vector<int> fgrid(n_inst, 0);
     for (int b = 0; b < n_inst; ++b) {
         if (N[b] < 1 || N[b] > MAX_N) return fail(ISING_ERR_INVALID_ARG, "N[%d]=%d outside [1, %d]", b, N[b], MAX_N);
         if (!J[b] || !h[b] || !init_bits[b]) return fail(ISING_ERR_INVALID_ARG, "NULL pointer for instance %d", b);
         if (N[b] > Nmax) Nmax = N[b];
         const int n = N[b];
         double bound = 0.0;
+        std::vector<double> row(n, 0.0);
+        int tz = 24;   // fewest trailing zero bits of a value in units of 2^-24
+        auto grid_of = [&](double v) {
+            const long long t = std::llabs((long long)(v * 16777216.0));
+            if (t != 0) tz = std::min(tz, __builtin_ctzll((unsigned long long)t));
+        };
         for (int i = 0; i < n; ++i) {
             if (!on_grid(h[b][i]))
                 return fail(ISING_ERR_INVALID_ARG, "h[%d][%d]=%g is not a finite multiple of 2^-24", b, i, h[b][i]);
             bound += std::fabs(h[b][i]);
+            row[i] += std::fabs(h[b][i]);
+            grid_of(h[b][i]);
             if (J[b][(size_t)i * n + i] != 0.0)
                 return fail(ISING_ERR_INVALID_ARG, "J[%d] has a nonzero diagonal at %d", b, i);
             for (int j = i + 1; j < n; ++j) {
@@ -332,10 +345,16 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
                     return fail(ISING_ERR_INVALID_ARG, "J[%d] is not symmetric at (%d,%d)", b, i, j);
                 if ((double)(float)(4.0 * v) != 4.0 * v) j32_exact = false;
                 bound += std::fabs(v);
+                row[i] += std::fabs(v);
+                row[j] += std::fabs(v);
+                grid_of(v);
             }
         }
         if (bound > 16777216.0)
             return fail(ISING_ERR_INVALID_ARG, "instance %d: sum |J_ij| + sum |h_i| = %g exceeds 2^24", b, bound);
+        fgrid[b] = 24 - tz;
+        const double rmax = *std::max_element(row.begin(), row.end());
+        if (!(std::ldexp(rmax, fgrid[b]) < 2147483648.0)) fq_ok = false;
         const int W = words_of(n);
         int downs0 = -1;
         for (int l = 0; l < L; ++l) {
@@ -444,7 +463,13 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     ALLOC(lay.bits, S * M2 * lay.Wmax);
     ALLOC(lay.E, S * M2);
     ALLOC(lay.zob, S * M2);
-    ALLOC(lay.F, S * M2 * lay.Npmax);
+    if (fq_ok) {
+        ALLOC(lay.Fq, S * M2 * lay.Npmax);
+    } else {
+        ALLOC(lay.Fd, S * M2 * lay.Npmax);
+    }
+    double* dfsc = nullptr;
+    ALLOC(dfsc, n_inst);
     ALLOC(lay.fresh, S * M2);
     ALLOC(lay.kept, S * lay.M);
     ALLOC(lay.nkept, S);
@@ -541,6 +566,7 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
     hd->sc_auto_ok = lay.sc_auto != 0;
     lay.J16 = dJ16;
     lay.rmax4 = drm;
+    lay.fsc = dfsc;
     lay.mlp = hd->d_mlp;
     lay.scorer = 0;
     lay.seed = 0;
@@ -695,6 +721,9 @@ extern "C" int ising_search_init(ising_search_t** out, const ising_config_t* cfg
             }
             cp(drm, rmh.data(), sizeof(float) * rmh.size());
         }
+        std::vector<double> fsch(n_inst, 1.0);
+        for (int b = 0; b < n_inst; ++b) fsch[b] = fq_ok ? std::ldexp(1.0, -fgrid[b]) : 1.0;
+        cp(dfsc, fsch.data(), sizeof(double) * n_inst);
         std::vector<uint16_t> jnh;
         if (cfg->form == ISING_FORM_LEARNED) {
             // bf16(sqrt(N) J_ij), rounded to nearest even, for the scoring network's features

@@ -71,7 +71,12 @@ struct Layout {
     uint64_t* bits;          // [S][2M][Wmax]
     double* E;               // [S][2M]
     uint64_t* zob;           // [S][2M]
-    double* F;               // [S][2M][Npmax]
+    // local fields of the pool slots, [S][2M][Npmax]: when every instance's
+    // fields fit, 32-bit integers in units of the instance's grid (F = Fq *
+    // fsc[b], exact), else FP64; exactly one of Fq and Fd is set
+    int32_t* Fq;
+    double* Fd;
+    const double* fsc;       // [B] grid unit of instance b (a power of two)
     uint8_t* fresh;          // [S][2M]
     int* kept;               // [S][M]
     int* nkept;              // [S]
@@ -149,6 +154,46 @@ struct Layout {
     int* out_count;          // [B]
 };
 
+// The local fields of one pool slot, read as FP64 whichever way they are held.
+struct FieldRow {
+    const int32_t* q;
+    const double* d;
+    double sc;
+    __device__ double operator[](int i) const { return q ? (double)q[i] * sc : d[i]; }
+    // K fields at idx(0 .. K-1), the loads issued together (the choice of
+    // storage is made once, outside them)
+    template <int K, typename Idx>
+    __device__ void gather(double (&v)[K], Idx idx) const
+    {
+        if (q) {
+            int32_t t[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) t[k] = q[idx(k)];
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[k] = (double)t[k] * sc;
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[k] = d[idx(k)];
+        }
+    }
+};
+
+__device__ inline FieldRow field_row(const Layout& lay, size_t slot, int b)
+{
+    FieldRow r;
+    r.q = lay.Fq ? lay.Fq + slot * lay.Npmax : nullptr;
+    r.d = lay.Fq ? nullptr : lay.Fd + slot * lay.Npmax;
+    r.sc = lay.fsc[b];
+    return r;
+}
+
+// Field i of a pool slot from its exact FP64 value (on the instance's grid).
+__device__ inline void field_store(const Layout& lay, size_t slot, int b, int i, double v)
+{
+    if (lay.Fq) lay.Fq[slot * lay.Npmax + i] = (int32_t)(v / lay.fsc[b]);
+    else lay.Fd[slot * lay.Npmax + i] = v;
+}
+
 enum { CTR_PAIRS = 0, CTR_SINGLES = 1, CTR_FRONTIER = 2, CTR_SURV = 3, CTR_RETRY = 4, CTR_STEPS = 5,
        CTR_FALLBACK = 6, CTR_SCORED = 7, CTR_LEARNED = 8, CTR_TRACE = 9, CTR_BOUNDED = 10 };
 constexpr int SB_CAP = 256;          // most sites a state may keep for the site-bound evaluation
@@ -224,7 +269,7 @@ constexpr int SB_BATCH = 8;
 constexpr int SB_STG = 128;
 constexpr int SB_GRID = 2048;   // k_site_bound blocks: 8192 waves, eight per SIMD
 __device__ inline int site_bound_pairs(const Layout& lay, int b, int s, int code, double Em, double c,
-                                       const uint64_t* __restrict__ x, const double* __restrict__ F,
+                                       const uint64_t* __restrict__ x, const FieldRow F,
                                        int N, int Np, uint16_t* sidx, double* sa, Surv* stage)
 {
     const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));

@@ -38,12 +38,12 @@ __global__ __launch_bounds__(64) void k_init_fields(Layout lay, const double* __
     }
     if (!colok) return;
     const int s = b * lay.L + lj;
-    double* F = lay.F + (size_t)(s * 2 * lay.M) * lay.Npmax;   // slot 0 of search s
+    const size_t q = (size_t)s * 2 * lay.M;   // slot 0 of search s
     const double* h = lay.h + (size_t)b * lay.Npmax;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int site = row0 + (lane >> 4) + 4 * r;
-        if (site < Np) F[site] = site < N ? h[site] + 0.25 * acc[r] : 0.0;
+        if (site < Np) field_store(lay, q, b, site, site < N ? h[site] + 0.25 * acc[r] : 0.0);
     }
 }
 
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(64) void k_seed(Layout lay, const uint64_t* __restr
     const int lane = threadIdx.x;
     const size_t q = (size_t)s * 2 * lay.M;   // slot 0
     const uint64_t* x = x0 + (size_t)s * lay.Wmax;
-    const double* F = lay.F + q * lay.Npmax;
+    const FieldRow F = field_row(lay, q, b);
     const double* h = lay.h + (size_t)b * lay.Npmax;
     double e = 0.0;
     uint64_t z = 0;
@@ -119,7 +119,6 @@ __global__ __launch_bounds__(256) void k_fields_direct(Layout lay, int search)
     const uint64_t* x = lay.bits + q * lay.Wmax;
     const double* Jb = lay.J4 + lay.joff[b];
     const double* h = lay.h + (size_t)b * lay.Npmax;
-    double* F = lay.F + q * lay.Npmax;
     __shared__ double red[256];
     double e = 0.0;
     uint64_t z = 0;
@@ -134,7 +133,7 @@ __global__ __launch_bounds__(256) void k_fields_direct(Layout lay, int search)
             e += (up ? -1.0 : 1.0) * (f + h[i]);
             if (up) z ^= lay.zkey[i];
         }
-        F[i] = f;
+        field_store(lay, q, b, i, f);
     }
     red[threadIdx.x] = e;
     __syncthreads();

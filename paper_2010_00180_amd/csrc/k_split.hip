@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void k_split_err(Layout lay, unsigned long lon
     const int s = blockIdx.x;
     const int b = s / lay.L;
     const int N = lay.N[b];
-    const double* F = lay.F + (size_t)s * 2 * lay.M * lay.Npmax;   // slot 0
+    const FieldRow F = field_row(lay, (size_t)s * 2 * lay.M, b);   // slot 0
     const float* Ft = lay.Ft + (size_t)s * lay.Npmax;
     double m = 0.0;
     for (int i = threadIdx.x; i < N; i += blockDim.x) m = fmax(m, fabs((double)Ft[i] - F[i]));
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         const double c = lay.cut[s];
         const double T = c - Em;
         const uint64_t* x = lay.bits + q * lay.Wmax;
-        const double* F = lay.F + q * lay.Npmax;
+        const FieldRow F = field_row(lay, q, b);
         const bool from_ft = first && (code % (2 * lay.M)) == 0;
         const float* Ft = lay.Ft + (size_t)s * lay.Npmax;
         double* A = lay.A + fe * lay.Npmax;
@@ -222,8 +222,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             // load is unconditional and in bounds
             double Fv[CH];
             float Ftv[CH];
-#pragma unroll
-            for (int r = 0; r < CH; ++r) Fv[r] = F[min(i0 + 64 * r, Np - 64) + (int)lane];
+            F.gather(Fv, [&](int r) { return min(i0 + 64 * r, Np - 64) + (int)lane; });
             if (from_ft) {
 #pragma unroll
                 for (int r = 0; r < CH; ++r) Ftv[r] = Ft[min(i0 + 64 * r, Np - 64) + (int)lane];
@@ -317,7 +316,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                                                const double* __restrict__ J4,
                                                const float* __restrict__ A32,
                                                const float* __restrict__ RR32,
-                                               const double* __restrict__ Fpool,
                                                const FrRec* __restrict__ recs,
                                                const uint64_t* __restrict__ fbits,
                                                const long long* __restrict__ iprefix)
@@ -391,7 +389,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     const int k = (int)(pr >> 12), rl = (int)((pr >> 6) & 63u), cl = (int)(pr & 63u);
                     const int prow = bi * TILE + rl, pcol = col0 + cl;
                     const int cd = sCode[k];
-                    const double* Frow = Fpool + (size_t)cd * lay.Npmax;
+                    const FieldRow Frow = field_row(lay, (size_t)cd, b);
                     const double sid = ((srec[k].wi >> rl) & 1ull) ? -1.0 : 1.0;
                     const double sj = ((srec[k].wj >> cl) & 1ull) ? -1.0 : 1.0;
                     const double ai = -2.0 * sid * Frow[prow];
@@ -534,7 +532,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                                                const double* __restrict__ J4,
                                                const uint16_t* __restrict__ A16,
                                                const _Float16* __restrict__ RR16,
-                                               const double* __restrict__ Fpool,
                                                const FrRec* __restrict__ recs,
                                                const uint64_t* __restrict__ fbits,
                                                const long long* __restrict__ iprefix)
@@ -627,7 +624,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     const int k = (int)(pr >> 13), rl = (int)((pr >> 7) & 63u), cl = (int)(pr & 127u);
                     const int prow = bi * TILE + rl, pcol = col0 + cl;
                     const int cd = sCode[k];
-                    const double* Frow = Fpool + (size_t)cd * lay.Npmax;
+                    const FieldRow Frow = field_row(lay, (size_t)cd, b);
                     const double sid = ((srec[k].wi >> rl) & 1ull) ? -1.0 : 1.0;
                     const uint64_t wj = cl < 64 ? srec[k].wj0 : srec[k].wj1;
                     const double sj = ((wj >> (cl & 63)) & 1ull) ? -1.0 : 1.0;
@@ -876,13 +873,13 @@ hipError_t launch_scan32(const Layout& lay, int scan_grid, hipStream_t st)
     if (lay.h16) {
         hipLaunchKernelGGL(k_plan16, dim3(1), dim3(1024), 0, st, lay, iprefix);
         hipLaunchKernelGGL(k_scan16, dim3(scan_grid), dim3(64), 0, st, lay, lay.J16, lay.J4,
-                           (const uint16_t*)lay.A32, (const _Float16*)lay.RR32, (const double*)lay.F,
+                           (const uint16_t*)lay.A32, (const _Float16*)lay.RR32,
                            (const FrRec*)lay.rec, (const uint64_t*)lay.fbits, (const long long*)iprefix);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_plan32, dim3(1), dim3(1024), 0, st, lay, iprefix);
     hipLaunchKernelGGL(k_scan32, dim3(scan_grid), dim3(64), 0, st, lay, lay.J32, lay.J4, (const float*)lay.A32,
-                       (const float*)lay.RR32, (const double*)lay.F, (const FrRec*)lay.rec,
+                       (const float*)lay.RR32, (const FrRec*)lay.rec,
                        (const uint64_t*)lay.fbits, (const long long*)iprefix);
     return hipGetLastError();
 }

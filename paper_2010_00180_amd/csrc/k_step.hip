@@ -384,7 +384,7 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
     if (single_pilots) {
         for (int p = 0; p < np; ++p) {
             const uint64_t* xp = lay.bits + (q0 + pslot[p]) * lay.Wmax;
-            const double* Fp = lay.F + (q0 + pslot[p]) * lay.Npmax;
+            const FieldRow Fp = field_row(lay, q0 + pslot[p], b);
             const double Ep = lay.E[q0 + pslot[p]];
             // the lightest sites (lowest a_i, then lowest i) in key/idx[0 ..)
             sort_prefix([&](int i, double& v, uint32_t& id) {
@@ -407,7 +407,7 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
         __syncthreads();
         for (int p = wave; p < np; p += 4) {
             const uint64_t* xp = lay.bits + (q0 + pslot[p]) * lay.Wmax;
-            const double* Fp = lay.F + (q0 + pslot[p]) * lay.Npmax;
+            const FieldRow Fp = field_row(lay, q0 + pslot[p], b);
             const double Ep = lay.E[q0 + pslot[p]];
             // the lane's lightest up site and lightest down site (first of equals)
             const uint64_t xw = lane < W ? xp[lane] : 0ull;
@@ -415,8 +415,7 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
             int iu = 0x7FFFFFFF, id = 0x7FFFFFFF;
             for (int i0 = 0; i0 < N; i0 += 512) {
                 double f[8];
-#pragma unroll
-                for (int r = 0; r < 8; ++r) f[r] = Fp[min(i0 + 64 * r, Np - 64) + lane];
+                Fp.gather(f, [&](int r) { return min(i0 + 64 * r, Np - 64) + lane; });
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
                     const int ib = i0 + 64 * r, i = ib + lane;
@@ -474,7 +473,7 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
         uint32_t* const iW = idx + 64 * wave;
         for (int p = wave; p < np; p += 4) {
             const uint64_t* xp = lay.bits + (q0 + pslot[p]) * lay.Wmax;
-            const double* Fp = lay.F + (q0 + pslot[p]) * lay.Npmax;
+            const FieldRow Fp = field_row(lay, q0 + pslot[p], b);
             const double Ep = lay.E[q0 + pslot[p]];
             // the lane's lightest site (the first of equals): rounds of 8 blocks
             // of 64 sites whose loads are issued together (blocks past Np load
@@ -485,8 +484,7 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
             int bi = 0x7FFFFFFF;
             for (int i0 = 0; i0 < N; i0 += 512) {
                 double f[8];
-#pragma unroll
-                for (int r = 0; r < 8; ++r) f[r] = Fp[min(i0 + 64 * r, Np - 64) + lane];
+                Fp.gather(f, [&](int r) { return min(i0 + 64 * r, Np - 64) + lane; });
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
                     const int ib = i0 + 64 * r, i = ib + lane;
@@ -753,7 +751,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
         if (retry_mode && !lay.retry[s]) continue;
         const size_t q = (size_t)code;
         const int r = site_bound_pairs(lay, b, s, code, lay.E[q], lay.cut[s], lay.bits + q * lay.Wmax,
-                                       lay.F + q * lay.Npmax, lay.N[b], lay.Npad[b], sb_idx[wave], sb_a[wave],
+                                       field_row(lay, q, b), lay.N[b], lay.Npad[b], sb_idx[wave], sb_a[wave],
                                        sb_stage[wave]);
         if (lane == 0) {
             lay.fr_bound[fe] = (uint16_t)(r + 1);
@@ -801,7 +799,7 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
         const double Em = lay.E[q];
         const double c = lay.cut[s];
         const uint64_t* x = lay.bits + q * lay.Wmax;
-        const double* F = lay.F + q * lay.Npmax;
+        const FieldRow F = field_row(lay, q, b);
         double* A = lay.A + fe * lay.Npmax;
         if (lane == 0) {
             FrRec r;
@@ -828,8 +826,7 @@ __global__ __launch_bounds__(256) void k_prep(Layout lay, const long long* __res
         // atomic reserves their places, then recorded
         for (int i0 = 0; i0 < Np; i0 += 64 * PREP_BLOCKS) {
             double Fv[PREP_BLOCKS];
-#pragma unroll
-            for (int r = 0; r < PREP_BLOCKS; ++r) Fv[r] = F[min(i0 + 64 * r, Np - 64) + (int)lane];
+            F.gather(Fv, [&](int r) { return min(i0 + 64 * r, Np - 64) + (int)lane; });
             double ar[PREP_BLOCKS];
             int nhit = 0;
 #pragma unroll
@@ -1776,11 +1773,44 @@ __global__ __launch_bounds__(256) void k_fupdate(Layout lay, const double* __res
     const double ci = -0.5 * spin_of(xp, i);   // -2 s_i J = -0.5 s_i (4J)
     const bool pairf = j != (int)SINGLE;
     const double cj = pairf ? -0.5 * spin_of(xp, j) : 0.0;
-    const double* Jb = J4 + lay.joff[b];
-    const double* Fp = lay.F + (size_t)code * lay.Npmax;
-    double* Fn = lay.F + ((size_t)s * 2 * lay.M + slot) * lay.Npmax;
+    const size_t qn = (size_t)s * 2 * lay.M + slot;
+    if (lay.Fq && lay.J4f) {
+        // fields in grid units, 4J exact in FP32: the changes -2 s J_ik are
+        // whole grid units, so the sums are exact
+        const double u = 1.0 / lay.fsc[b];
+        const double di = ci * u, dj = cj * u;
+        const int32_t* Fp = lay.Fq + (size_t)code * lay.Npmax;
+        int32_t* Fn = lay.Fq + qn * lay.Npmax;
+        const float* Jf = lay.J4f + lay.joff[b];
+        const float* Ji = Jf + (size_t)i * Np;
+        const float* Jj = Jf + (size_t)(pairf ? j : i) * Np;
+        // four entries per lane and load (rows are 64-entry aligned)
+#pragma unroll 2
+        for (int k = 4 * lane; k < Np; k += 256) {
+            const int4 f = *reinterpret_cast<const int4*>(Fp + k);
+            const float4 ji = *reinterpret_cast<const float4*>(Ji + k);
+            double v0 = (double)f.x + di * (double)ji.x, v1 = (double)f.y + di * (double)ji.y;
+            double v2 = (double)f.z + di * (double)ji.z, v3 = (double)f.w + di * (double)ji.w;
+            if (pairf) {
+                const float4 jj = *reinterpret_cast<const float4*>(Jj + k);
+                v0 += dj * (double)jj.x;
+                v1 += dj * (double)jj.y;
+                v2 += dj * (double)jj.z;
+                v3 += dj * (double)jj.w;
+            }
+            int4 o;
+            o.x = k < N ? (int32_t)v0 : 0;
+            o.y = k + 1 < N ? (int32_t)v1 : 0;
+            o.z = k + 2 < N ? (int32_t)v2 : 0;
+            o.w = k + 3 < N ? (int32_t)v3 : 0;
+            *reinterpret_cast<int4*>(Fn + k) = o;
+        }
+        return;
+    }
     if (lay.J4f) {
         // 4J exact in FP32: half the coupling bytes, the same sums
+        const double* Fp = lay.Fd + (size_t)code * lay.Npmax;
+        double* Fn = lay.Fd + qn * lay.Npmax;
         const float* Jf = lay.J4f + lay.joff[b];
         const float* Ji = Jf + (size_t)i * Np;
         const float* Jj = Jf + (size_t)(pairf ? j : i) * Np;
@@ -1803,12 +1833,14 @@ __global__ __launch_bounds__(256) void k_fupdate(Layout lay, const double* __res
         }
         return;
     }
+    const FieldRow Fp = field_row(lay, (size_t)code, b);
+    const double* Jb = J4 + lay.joff[b];
     const double* Ji = Jb + (size_t)i * Np;
     const double* Jj = Jb + (size_t)(pairf ? j : i) * Np;
     for (int k = lane; k < Np; k += 64) {
         double v = Fp[k] + ci * Ji[k];
         if (pairf) v += cj * Jj[k];
-        Fn[k] = k < N ? v : 0.0;
+        field_store(lay, qn, b, k, k < N ? v : 0.0);
     }
 }
 

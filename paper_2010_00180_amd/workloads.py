@@ -91,6 +91,11 @@ def make_instance(N: int, seed: int, L: int, dist: str = "sk") -> Instance:
     elif dist == "pmj":
         J[iu] = rng.choice(np.array([-1.0, 1.0]), n_up)
         h = rng.choice(np.array([-1.0, 0.0, 1.0]), N)
+    elif dist == "wide":
+        # unnormalized couplings: row sums |h_i| + sum_j |J_ij| of about 3N,
+        # beyond 2^7 on the 2^-24 grid for N >= 50
+        J[iu] = 2.0 * rng.standard_normal(n_up)
+        h = 2.0 * rng.standard_normal(N)
     elif dist == "sk_h0":
         J[iu] = rng.standard_normal(n_up) / np.sqrt(N)
         h = np.zeros(N)

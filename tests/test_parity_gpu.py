@@ -109,6 +109,19 @@ def test_ties_and_symmetry_stepwise(dist):
     stepwise_parity(w, f"ties {dist}")
 
 
+@pytest.mark.parametrize("form,flags", [(binding.FORM_PLAIN, 0), (binding.FORM_SPLIT_BF16, 0),
+                                        (binding.FORM_PLAIN, binding.FLAG_SITE_BOUND),
+                                        (binding.FORM_SPLIT_BF16, binding.FLAG_SITE_BOUND)])
+def test_wide_fields_stepwise(form, flags):
+    """Fields beyond 2^31 units of the 2^-24 grid: the library holds them in
+    FP64 instead of 32-bit integers; with them an instance of +-1 couplings
+    (grid 1, fields up to N), held as integers."""
+    w = wl.custom([60, 130], L=2, M=40, config=13, dist="wide")
+    stepwise_parity(w, f"wide fields form={form} flags={flags}", form=form, flags=flags)
+    w = wl.custom([150], L=2, M=40, config=14, dist="pmj")
+    stepwise_parity(w, f"integer fields form={form} flags={flags}", form=form, flags=flags)
+
+
 def test_uneven_sizes_one_handle():
     w = wl.custom([5, 64, 65, 100, 129], L=2, M=30, config=13)
     stepwise_parity(w, "uneven")
