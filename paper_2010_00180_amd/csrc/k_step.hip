@@ -256,13 +256,20 @@ static_assert(NPIL <= 32, "the pilot index takes the top 6 bits of a candidate i
 // returns their number, or 5 when there are more.
 __device__ inline int pilot_diff(const uint64_t* xa, const uint64_t* xb, int W, int* d)
 {
+    // the words in chunks of eight, each chunk's loads issued together
     int n = 0;
-    for (int w = 0; w < W && n <= 4; ++w) {
-        uint64_t x = xa[w] ^ xb[w];
-        while (x && n <= 4) {
-            if (n < 4) d[n] = w * 64 + __builtin_ctzll(x);
-            ++n;
-            x &= x - 1;
+    for (int w0 = 0; w0 < W && n <= 4; w0 += 8) {
+        uint64_t x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = w0 + u < W ? xa[w0 + u] ^ xb[w0 + u] : 0ull;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            uint64_t v = x[u];
+            while (v && n <= 4) {
+                if (n < 4) d[n] = (w0 + u) * 64 + __builtin_ctzll(v);
+                ++n;
+                v &= v - 1;
+            }
         }
     }
     return n;
