@@ -238,21 +238,22 @@ def measure(binding, torch, w, form, steps, warmup, batching=False, graph_steps=
         roofline = None
     elif form in SITE_BOUND_FORMS:
         # k_site_bound evaluates the bounded states: its algorithmic bytes are
-        # the F row of each bounded state (8N) and one FP32 coupling per pair
-        # it evaluates (4); the few states it sends to the full scan are
-        # counted there
+        # the F row of each bounded state (N fields of field_bytes each) and
+        # one FP32 coupling per pair it evaluates (4); the few states it sends
+        # to the full scan are counted there
         bound_s = d["bound_ms"] / 1e3
         N = w.instances[0].N
         nb = d["bounded_states"]
+        fb = int(st1["field_bytes"])
         sb_pairs = pairs - (d["frontier_states"] - nb) * (N * (N - 1) // 2)
-        nbytes = nb * 8 * N + 4 * sb_pairs
+        nbytes = nb * fb * N + 4 * sb_pairs
         gbs = nbytes / bound_s / 1e9 if bound_s > 0 else 0.0
         roofline = {
             "kernel": "k_site_bound",
             "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
             "avg_launch_ms": d["bound_ms"] / launches,
             "bytes_per_launch": nbytes / launches,
-            "bytes_model": "8N per bounded state (its F row) + 4 per pair it evaluates (an FP32 coupling)",
+            "bytes_model": f"{fb}N per bounded state (its F row) + 4 per pair it evaluates (an FP32 coupling)",
             "note": "latency-bound: a chain of dependent memory rounds per state, eight waves per SIMD",
         }
     else:

@@ -161,6 +161,10 @@ typedef struct {
                                   default, doubled each time a step's candidates could not fit */
     double bound_ms;           /* site bound: device time of the site-bound kernel, summed (part of
                                   prep_ms) */
+    uint64_t field_bytes;      /* bytes per stored local field: 4 when every instance's fields are
+                                  held as 32-bit integers of its grid (|h_i| + sum_j |J_ij| below
+                                  2^31 units of the coarsest power-of-two grid its values lie on),
+                                  else 8 (FP64); exact either way */
 } ising_stats_t;
 
 /*

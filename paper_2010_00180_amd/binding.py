@@ -109,6 +109,7 @@ class IsingStats(ctypes.Structure):
         ("bounded_states", ctypes.c_uint64),
         ("surv_capacity", ctypes.c_uint64),
         ("bound_ms", ctypes.c_double),
+        ("field_bytes", ctypes.c_uint64),
     ]
 
     def as_dict(self):

@@ -1424,6 +1424,7 @@ extern "C" int ising_search_get_stats(ising_search_t* s, ising_stats_t* out)
     out->bounded_states = c[CTR_BOUNDED];
     out->surv_capacity = (uint64_t)s->lay.cap_surv;
     out->bound_ms = s->t_bound;
+    out->field_bytes = s->lay.Fq ? 4 : 8;
     return ISING_OK;
 }
 

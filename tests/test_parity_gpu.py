@@ -117,9 +117,14 @@ def test_wide_fields_stepwise(form, flags):
     FP64 instead of 32-bit integers; with them an instance of +-1 couplings
     (grid 1, fields up to N), held as integers."""
     w = wl.custom([60, 130], L=2, M=40, config=13, dist="wide")
-    stepwise_parity(w, f"wide fields form={form} flags={flags}", form=form, flags=flags)
+    st = stepwise_parity(w, f"wide fields form={form} flags={flags}", form=form, flags=flags)
+    assert st["field_bytes"] == 8
     w = wl.custom([150], L=2, M=40, config=14, dist="pmj")
-    stepwise_parity(w, f"integer fields form={form} flags={flags}", form=form, flags=flags)
+    st = stepwise_parity(w, f"integer fields form={form} flags={flags}", form=form, flags=flags)
+    assert st["field_bytes"] == 4
+    w = wl.custom([60], L=2, M=40, config=13, dist="wide")   # this one alone fits
+    st = stepwise_parity(w, f"fitting fields form={form} flags={flags}", form=form, flags=flags)
+    assert st["field_bytes"] == 4
 
 
 def test_uneven_sizes_one_handle():
