@@ -213,9 +213,10 @@ __device__ inline bool step_halted(const Layout& lay) { return lay.flags[FLAG_HA
 __host__ __device__ inline int words_of(int N) { return (N + 63) >> 6; }
 __host__ __device__ inline int pad_of(int N) { return (N + TILE - 1) / TILE * TILE; }
 // Tiles of 64 rows x 32 columns that hold pairs i < j: row block bi meets
-// column blocks bc >= 2*bi of the nc = Npad/32 column blocks.
+// column blocks bc >= 2*bi of the nc = ceil(N/32) column blocks that hold a
+// column below N.
 __host__ __device__ inline long long tiles_of(int N) {
-    const long long nb = (N + TILE - 1) / TILE, nc = 2 * nb;
+    const long long nb = (N + TILE - 1) / TILE, nc = (N + TCOL - 1) / TCOL;
     return nb * nc - nb * (nb - 1);
 }
 // Tiles of 64 x 64 (FP32 scan) with row block <= column block.

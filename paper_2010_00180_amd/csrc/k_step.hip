@@ -954,7 +954,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const int b = uniform_int(find_instance(lay.item_prefix, lay.B, item));
         const long long r = item - lay.item_prefix[b];
         const int N = lay.N[b], Np = lay.Npad[b];
-        const int nc = 2 * (Np / TILE);
+        const int nc = (N + TCOL - 1) / TCOL;   // column blocks holding a column below N
         const long long T = tiles_of(N);
         const int c = (int)(r / T);
         int t = (int)(r % T);
