@@ -1765,8 +1765,15 @@ __global__ __launch_bounds__(256) void k_fupdate(Layout lay, const double* __res
 {
     if (step_halted(lay)) return;   // a later step of a multi-step graph after a halt
     const int groups = (lay.M + 3) / 4;
-    const int s = (int)(blockIdx.x / groups);
-    const int m = (int)(blockIdx.x % groups) * 4 + (threadIdx.x >> 6);
+    // XCD x (blocks x, x + 8, ...) takes the x-th contiguous eighth of the
+    // (search, group) blocks, so that the states of an instance meet in one
+    // XCD's L2 and share the coupling rows they read
+    // (the grid is a multiple of 8 blocks, at least S * groups)
+    const unsigned per = gridDim.x / 8;
+    const unsigned lb = (blockIdx.x % 8) * per + blockIdx.x / 8;   // logical block
+    if (lb >= (unsigned)lay.S * (unsigned)groups) return;
+    const int s = (int)(lb / groups);
+    const int m = (int)(lb % groups) * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (m >= lay.nm_count[s]) return;
     const int b = s / lay.L;
@@ -2061,7 +2068,8 @@ hipError_t launch_merge(const Layout& lay, hipStream_t st)
 
 hipError_t launch_fupdate(const Layout& lay, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_fupdate, dim3(lay.S * ((lay.M + 3) / 4)), dim3(256), 0, st, lay, lay.J4);
+    const unsigned blocks = (unsigned)lay.S * ((lay.M + 3) / 4);
+    hipLaunchKernelGGL(k_fupdate, dim3((blocks + 7) / 8 * 8), dim3(256), 0, st, lay, lay.J4);
     return hipGetLastError();
 }
 
