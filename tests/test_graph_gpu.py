@@ -72,6 +72,27 @@ def test_graph_with_full_buffers(form, flags):
     assert st["retries"] > 0
 
 
+@pytest.mark.parametrize("scorer", [binding.SCORER_FIELDS, binding.SCORER_NETWORK])
+def test_learned_form_in_graphs_of_k_steps(scorer):
+    """The learned form's ranked and full steps switch on the device, so a
+    graph of several steps holds both kinds."""
+    w = wl.custom([90, 150], L=3, M=30, config=76)
+    params = wl.network_params(5).astype(np.float32)
+    runs = []
+    for kw in ({}, {"persistent": 1, "graph_steps": 8}):
+        s = binding.IsingSearch.from_workload(w, form=binding.FORM_LEARNED, **kw)
+        s.set_scorer(scorer, params if scorer == binding.SCORER_NETWORK else None, seed=3)
+        it = s.run()
+        runs.append((it, [s.get_search(k) for k in range(s.B * s.L)], s.stats()))
+        s.destroy()
+    (ia, sa, sta), (ig, sg, stg) = runs
+    assert ia == ig
+    for k, (a, g) in enumerate(zip(sa, sg)):
+        assert all(np.array_equal(x, y) for x, y in zip(a, g)), f"search {k}"
+    assert sta["steps"] == stg["steps"] and sta["fallbacks"] == stg["fallbacks"]
+    assert sta["scored_pairs"] == stg["scored_pairs"]
+
+
 def test_graph_respects_the_step_cap():
     w = wl.custom([150, 250], L=2, M=50, config=73)
     for cap in (3, 13, 20):
