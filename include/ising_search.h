@@ -50,7 +50,7 @@ typedef enum {
 } ising_status_t;
 
 typedef enum {
-    ISING_FORM_PLAIN = 0,      /* FP64 local fields, FP64 energy-change scan */
+    ISING_FORM_PLAIN = 0,      /* exact local fields, FP64 energy-change scan */
     ISING_FORM_SPLIT_BF16 = 1, /* initial local fields from J = hi + lo (bf16) on MFMA with FP32
                                   accumulation, FP32 scan with a proven error slack, FP64 re-score */
     ISING_FORM_LEARNED = 2     /* pair flips ranked by a small network; only the best K per state are

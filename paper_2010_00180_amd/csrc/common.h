@@ -4,7 +4,8 @@
 //          (zero in the padding); 4*J is exact, it is the pair term of the
 //          energy change.
 //   h      per instance: Npad[b] FP64.
-//   pool   per search s: 2M slots; slot q holds bits[Wmax], E, zob, F[Npmax].
+//   pool   per search s: 2M slots; slot q holds bits[Wmax], E, zob, F[Npmax]
+//          (F exact: 32-bit integers of the instance's grid, or FP64).
 //          A new kept state always takes a slot that the current kept set
 //          does not use, so parents stay readable while children are written.
 //   kept   per search: up to M slot ids sorted by (E, psi).
