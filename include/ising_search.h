@@ -87,8 +87,8 @@ enum {
  * the step's cut T only if both of its sites satisfy
  * a_i + min_k a_k - max_k |4J_ik| <= T.  A state with at most 256 such sites has
  * exactly the pairs among them evaluated (FP64, the same arithmetic as the
- * scan) by the preparation kernel and leaves the scan; the others are scanned
- * in full.  The kept sets are identical with and without the flag (every value
+ * scan) by a kernel of its own before the preparation and leaves the scan; the
+ * others are prepared and scanned in full.  The kept sets are identical with and without the flag (every value
  * involved is exact on the 2^-24 grid); pair_evals then counts the pairs
  * actually evaluated and bounded_states the states resolved this way.
  */
