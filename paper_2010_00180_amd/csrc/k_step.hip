@@ -246,6 +246,7 @@ constexpr int NPILOT = 4;                    // pilots of a ranking step
 constexpr int PRANK = 512;                   // singles per pilot of a ranking step
 constexpr int NPIL = 32;                     // pilots of a full step
 constexpr int PKW = 10;                      // sites per pilot of a full step (at least)
+constexpr int PIL_BLOCKS = 10;               // 64-site blocks of a pilot's fields loaded in one round
 constexpr int PCW = PKW * (PKW + 1) / 2;     // candidates per pilot of a full step
 constexpr int POOL = NPILOT * PRANK;         // candidate pool, a power of 2
 static_assert(NPIL * PCW <= POOL, "the candidate pool holds either kind of step");
@@ -420,11 +421,11 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
             const uint64_t xw = lane < W ? xp[lane] : 0ull;
             double bu = INFINITY, bd = INFINITY;
             int iu = 0x7FFFFFFF, id = 0x7FFFFFFF;
-            for (int i0 = 0; i0 < N; i0 += 512) {
-                double f[8];
+            for (int i0 = 0; i0 < N; i0 += 64 * PIL_BLOCKS) {
+                double f[PIL_BLOCKS];
                 Fp.gather(f, [&](int r) { return min(i0 + 64 * r, Np - 64) + lane; });
 #pragma unroll
-                for (int r = 0; r < 8; ++r) {
+                for (int r = 0; r < PIL_BLOCKS; ++r) {
                     const int ib = i0 + 64 * r, i = ib + lane;
                     if (ib < N) {
                         const bool neg = __builtin_amdgcn_inverse_ballot_w64(word_of_lane(xw, ib >> 6));
@@ -482,18 +483,18 @@ __global__ __launch_bounds__(256) void k_frontier(Layout lay, const double* __re
             const uint64_t* xp = lay.bits + (q0 + pslot[p]) * lay.Wmax;
             const FieldRow Fp = field_row(lay, q0 + pslot[p], b);
             const double Ep = lay.E[q0 + pslot[p]];
-            // the lane's lightest site (the first of equals): rounds of 8 blocks
+            // the lane's lightest site (the first of equals): rounds of PIL_BLOCKS blocks
             // of 64 sites whose loads are issued together (blocks past Np load
             // the last block again, unused); the word of block k, held by lane
             // k, is the lane mask of the flipped spins
             const uint64_t xw = lane < W ? xp[lane] : 0ull;
             double best = INFINITY;
             int bi = 0x7FFFFFFF;
-            for (int i0 = 0; i0 < N; i0 += 512) {
-                double f[8];
+            for (int i0 = 0; i0 < N; i0 += 64 * PIL_BLOCKS) {
+                double f[PIL_BLOCKS];
                 Fp.gather(f, [&](int r) { return min(i0 + 64 * r, Np - 64) + lane; });
 #pragma unroll
-                for (int r = 0; r < 8; ++r) {
+                for (int r = 0; r < PIL_BLOCKS; ++r) {
                     const int ib = i0 + 64 * r, i = ib + lane;
                     if (ib < N) {
                         const bool neg = __builtin_amdgcn_inverse_ballot_w64(word_of_lane(xw, ib >> 6));
