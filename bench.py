@@ -732,6 +732,10 @@ def main():
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample")
         cpu = cpu_baseline(w, args.cpu_seconds, args.cpu_single_seconds)
+        # the headline rate against the oracle's, both in pair-flip evaluations/s
+        cpu["gpu_over_cpu"] = head["value"] / cpu["value"] if cpu["value"] else None
+        if cpu.get("single_core_value"):
+            cpu["gpu_over_single_core"] = head["value"] / cpu["single_core_value"]
 
     roof = dict(head["roofline"])
     digest = source_digest(roof["kernel"]) if roof["kernel"] in KERNEL_SOURCE else None
