@@ -1989,15 +1989,19 @@ extern "C" int ising_bestfirst(int32_t n_inst, const int32_t* N, const double* c
     const int nchild = (h1 == H1_EXCHANGE ? 0 : nmax) + (h1 == H1_SINGLES ? 0 : nmax * (nmax - 1) / 2);
     int C = 1;
     while (C < std::max(nchild, K1)) C <<= 1;
-    const size_t lds = bestfirst_lds_bytes(K1, C);
-    if (lds > BFS_LDS_MAX)
-        return fail(ISING_ERR_INVALID_ARG, "a list of %d entries with N=%d needs %zu bytes of LDS (at most %zu)", K1,
-                    nmax, lds, BFS_LDS_MAX);
+    // the lists in LDS when they fit, else in global memory per block
+    const size_t need = bestfirst_lds_bytes(K1, C);
+    const bool in_lds = need <= BFS_LDS_MAX;
+    const size_t lds = in_lds ? need : 0;
+    const size_t ws_stride = in_lds ? 0 : (need + 255) / 256 * 256;
     int rc = have_device();
     if (rc != ISING_OK) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    hipError_t e = bestfirst_set_lds(lds);
-    if (e != hipSuccess) return fail(ISING_ERR_HIP, "the best-first kernels cannot use %zu bytes of LDS", lds);
+    hipError_t e = hipSuccess;
+    if (in_lds) {
+        e = bestfirst_set_lds(lds);
+        if (e != hipSuccess) return fail(ISING_ERR_HIP, "the best-first kernels cannot use %zu bytes of LDS", lds);
+    }
 
     const size_t S = (size_t)n_inst * L;
     std::vector<long long> joff(n_inst);
@@ -2017,6 +2021,8 @@ extern "C" int ising_bestfirst(int32_t n_inst, const int32_t* N, const double* c
         (rc = buf.get(&dE, S * K1)) || (rc = buf.get(&dused, S * K1)) || (rc = buf.get(&dborn, S * K1)) ||
         (rc = buf.get(&dexp, S)) || (rc = buf.get(&dmpsi, (size_t)n_inst * K1)) || (rc = buf.get(&dmE, (size_t)n_inst * K1)))
         return rc;
+    unsigned char* dws = nullptr;   // one region per search block (the merge blocks reuse the first ones)
+    if (!in_lds && (rc = buf.get(&dws, S * ws_stride))) return rc;
     {
         std::vector<double> Jh((size_t)jtot), hh((size_t)n_inst * 64, 0.0);
         std::vector<uint64_t> xh(S);
@@ -2050,6 +2056,8 @@ extern "C" int ising_bestfirst(int32_t n_inst, const int32_t* N, const double* c
     a.out_expanded = dexp;
     a.merged_psi = dmpsi;
     a.merged_E = dmE;
+    a.ws = dws;
+    a.ws_stride = ws_stride;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (kernel_ms) {
         HIP_TRY(hipEventCreate(&e0));

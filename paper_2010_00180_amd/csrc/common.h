@@ -506,7 +506,7 @@ hipError_t launch_brute_sort(const BruteArgs& a, int K, uint64_t* out_bits, doub
 
 // ------------------------------------------------------------------ best-first search (k_bestfirst.hip)
 constexpr int BFS_NMAX = 64;       // one word per state
-constexpr int BFS_K1MAX = 2048;    // list entries (K + 1) at most
+constexpr int BFS_K1MAX = 1 << 20; // list entries (K + 1) at most (lists past the LDS go to global memory)
 constexpr size_t BFS_LDS_MAX = 160 * 1024;
 
 struct BestFirstArgs {
@@ -523,6 +523,10 @@ struct BestFirstArgs {
     int* out_expanded;         // [B*L] iterations that expanded a state
     uint64_t* merged_psi;      // [B][K1] Alg. 4 result
     double* merged_E;
+    // lists too long for LDS: each block's lists, hash and offered entries in
+    // global memory, ws_stride bytes per block (null: in LDS)
+    unsigned char* ws;
+    size_t ws_stride;
 };
 
 size_t bestfirst_lds_bytes(int K1, int C);

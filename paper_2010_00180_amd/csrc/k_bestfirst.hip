@@ -2,7 +2,9 @@
 // search with the list update of Alg. 2, and the merge of Alg. 4.
 //
 // One block per search; the list of K + 1 entries (state, energy, expanded
-// flag, arrival iteration) lives in LDS in energy order, entries of equal
+// flag, arrival iteration) lives in LDS (in global memory, per block, when
+// it does not fit: the same code through the same pointers) in energy order,
+// entries of equal
 // energy in order of arrival, placeholders (E = +inf) at the end.  An
 // iteration expands the first entry that has not been expanded: its children
 // (single flips of sites 0 .. N-1, then pair flips (0,1), (0,2), ..; one of the
@@ -192,7 +194,7 @@ __global__ __launch_bounds__(256) void k_bf_search(BestFirstArgs a)
     const int K1 = a.K1;
     int HS = 1;
     while (HS < 2 * K1) HS <<= 1;
-    const BfLds s = bf_carve(bf_dyn, K1, HS, a.C);
+    const BfLds s = bf_carve(a.ws ? a.ws + (size_t)blockIdx.x * a.ws_stride : bf_dyn, K1, HS, a.C);
     const double* __restrict__ J = a.J + a.joff[b];
     const double* __restrict__ h = a.h + (size_t)b * 64;
     const int h1 = a.h1;
@@ -331,7 +333,7 @@ __global__ __launch_bounds__(256) void k_bf_merge(BestFirstArgs a)
     const int K1 = a.K1;
     int HS = 1;
     while (HS < 2 * K1) HS <<= 1;
-    const BfLds s = bf_carve(bf_dyn, K1, HS, a.C);
+    const BfLds s = bf_carve(a.ws ? a.ws + (size_t)blockIdx.x * a.ws_stride : bf_dyn, K1, HS, a.C);
     const size_t o0 = (size_t)b * a.L * K1;
     for (int k = threadIdx.x; k < K1; k += blockDim.x) {
         s.psi[0][k] = a.out_psi[o0 + k];

@@ -101,11 +101,22 @@ def test_other_h1(flags):
     check(insts, 60, 25, f"h1 flags={flags}", flags=flags)
 
 
-def test_rejects_lists_that_do_not_fit():
-    inst = wl.make_instance(64, 8800, 1, "sk")
+@pytest.mark.parametrize("N,K,I,dist,L", [(64, 2047, 5, "sk", 2), (20, 2110, 2110, "uniform", 1),
+                                         (16, 2740, 2740, "uniform", 1), (14, 3000, 200, "pmj", 2)])
+def test_lists_past_the_lds(N, K, I, dist, L):
+    """Lists too long for the 160 KB of LDS live in device memory, one region
+    per search: K = 10 K0 at N = 20 is the largest list of Sec. IV at that
+    size; pmj keeps exact ties in the long list."""
+    insts = [wl.make_instance(N, 8900 + N + k, L, dist) for k in range(2)]
+    x0s = [[0]] * 2 if L == 1 else None
+    check(insts, K, I, f"global lists N={N} K={K}", x0s=x0s)
+
+
+def test_rejects_what_the_kernels_cannot_take():
+    big = wl.make_instance(65, 8801, 1, "sk")
     with pytest.raises(binding.IsingError):
-        binding.bestfirst([inst.J], [inst.h], [inst.init_bits[:, 0]], 2047, 5)
-    assert "LDS" in binding.last_error()
-    with pytest.raises(binding.IsingError):
-        big = wl.make_instance(65, 8801, 1, "sk")
         binding.bestfirst([big.J], [big.h], [[0]], 10, 5)
+    inst = wl.make_instance(12, 8802, 1, "sk")
+    with pytest.raises(binding.IsingError):
+        binding.bestfirst([inst.J], [inst.h], [[0]], 1 << 20, 5)
+    assert "K=" in binding.last_error()
