@@ -1987,21 +1987,17 @@ extern "C" int ising_bestfirst(int32_t n_inst, const int32_t* N, const double* c
     }
     const int K1 = K + 1;
     const int nchild = (h1 == H1_EXCHANGE ? 0 : nmax) + (h1 == H1_SINGLES ? 0 : nmax * (nmax - 1) / 2);
-    int C = 1;
-    while (C < std::max(nchild, K1)) C <<= 1;
+    int Cs = 1;
+    while (Cs < nchild) Cs <<= 1;
     // the lists in LDS when they fit, else in global memory per block
-    const size_t need = bestfirst_lds_bytes(K1, C);
-    const bool in_lds = need <= BFS_LDS_MAX;
-    const size_t lds = in_lds ? need : 0;
-    const size_t ws_stride = in_lds ? 0 : (need + 255) / 256 * 256;
+    const BestFirstPlan plan = bestfirst_plan(K1, Cs);
     int rc = have_device();
     if (rc != ISING_OK) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    hipError_t e = hipSuccess;
-    if (in_lds) {
-        e = bestfirst_set_lds(lds);
-        if (e != hipSuccess) return fail(ISING_ERR_HIP, "the best-first kernels cannot use %zu bytes of LDS", lds);
-    }
+    hipError_t e = bestfirst_set_lds(plan);
+    if (e != hipSuccess)
+        return fail(ISING_ERR_HIP, "the best-first kernels cannot use %zu and %zu bytes of LDS", plan.lds_search,
+                    plan.lds_merge);
 
     const size_t S = (size_t)n_inst * L;
     std::vector<long long> joff(n_inst);
@@ -2022,7 +2018,7 @@ extern "C" int ising_bestfirst(int32_t n_inst, const int32_t* N, const double* c
         (rc = buf.get(&dexp, S)) || (rc = buf.get(&dmpsi, (size_t)n_inst * K1)) || (rc = buf.get(&dmE, (size_t)n_inst * K1)))
         return rc;
     unsigned char* dws = nullptr;   // one region per search block (the merge blocks reuse the first ones)
-    if (!in_lds && (rc = buf.get(&dws, S * ws_stride))) return rc;
+    if (plan.ws_stride && (rc = buf.get(&dws, S * plan.ws_stride))) return rc;
     {
         std::vector<double> Jh((size_t)jtot), hh((size_t)n_inst * 64, 0.0);
         std::vector<uint64_t> xh(S);
@@ -2042,7 +2038,7 @@ extern "C" int ising_bestfirst(int32_t n_inst, const int32_t* N, const double* c
     a.L = L;
     a.K1 = K1;
     a.I = I;
-    a.C = C;
+    a.Cs = Cs;
     a.h1 = h1;
     a.N = dN;
     a.joff = djoff;
@@ -2056,8 +2052,10 @@ extern "C" int ising_bestfirst(int32_t n_inst, const int32_t* N, const double* c
     a.out_expanded = dexp;
     a.merged_psi = dmpsi;
     a.merged_E = dmE;
+    a.lists_in_lds = plan.lists_in_lds;
+    a.merge_in_lds = plan.merge_in_lds;
     a.ws = dws;
-    a.ws_stride = ws_stride;
+    a.ws_stride = plan.ws_stride;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (kernel_ms) {
         HIP_TRY(hipEventCreate(&e0));
@@ -2067,7 +2065,7 @@ extern "C" int ising_bestfirst(int32_t n_inst, const int32_t* N, const double* c
         }
         e = hipEventRecord(e0, st);
     }
-    if (e == hipSuccess) e = launch_bestfirst(a, n_inst, lds, st);
+    if (e == hipSuccess) e = launch_bestfirst(a, n_inst, plan, st);
     if (e == hipSuccess && kernel_ms) e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e == hipSuccess && kernel_ms) *kernel_ms = (float)elapsed_ms(e0, e1);

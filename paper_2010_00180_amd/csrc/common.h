@@ -510,7 +510,8 @@ constexpr int BFS_K1MAX = 1 << 20; // list entries (K + 1) at most (lists past t
 constexpr size_t BFS_LDS_MAX = 160 * 1024;
 
 struct BestFirstArgs {
-    int L, K1, I, C, h1;       // searches per instance, list entries, iterations, offered-entry room, H1 mode
+    int L, K1, I, Cs, h1;      // searches per instance, list entries, iterations, offered-entry room of a
+                               // search (a power of two, at least its children), H1 mode
     const int* N;              // [B]
     const long long* joff;     // [B] offset of instance b's N*N couplings in J
     const double* J;           // J_ij, row-major per instance
@@ -523,14 +524,21 @@ struct BestFirstArgs {
     int* out_expanded;         // [B*L] iterations that expanded a state
     uint64_t* merged_psi;      // [B][K1] Alg. 4 result
     double* merged_E;
-    // lists too long for LDS: each block's lists, hash and offered entries in
-    // global memory, ws_stride bytes per block (null: in LDS)
+    // what does not fit in LDS goes to global memory, ws_stride bytes per
+    // block: a search's lists and hash, or all of a merge block's arrays
+    int lists_in_lds, merge_in_lds;
     unsigned char* ws;
     size_t ws_stride;
 };
 
-size_t bestfirst_lds_bytes(int K1, int C);
-hipError_t bestfirst_set_lds(size_t bytes);
-hipError_t launch_bestfirst(const BestFirstArgs& a, int n_inst, size_t lds, hipStream_t st);
+// dynamic LDS of the two kernels and the global bytes per block (0: none)
+struct BestFirstPlan {
+    size_t lds_search, lds_merge, ws_stride;
+    int lists_in_lds, merge_in_lds;
+};
+
+BestFirstPlan bestfirst_plan(int K1, int Cs);
+hipError_t bestfirst_set_lds(const BestFirstPlan& p);
+hipError_t launch_bestfirst(const BestFirstArgs& a, int n_inst, const BestFirstPlan& p, hipStream_t st);
 
 }  // namespace qi

@@ -87,6 +87,16 @@ def test_one_word_limit(N):
     check(insts, 200, 8, f"N={N}")
 
 
+@pytest.mark.parametrize("flags", [0, binding.FLAG_SINGLE_FLIPS])
+def test_states_with_every_bit_set(flags):
+    """At N = 64 the states 2^64 - 1 and 2^64 - 2 (every spin down, and every
+    spin but the first) are ordinary states of the search; the kernels' hash
+    of the list keeps them apart from its slot markers."""
+    insts = [wl.make_instance(64, 8550 + k, 2, "sk") for k in range(2)]
+    top = (1 << 64) - 1
+    check(insts, 300, 40, f"all-down starts flags={flags}", flags=flags, x0s=[[top, top - 1], [top - 1, top - 3]])
+
+
 def test_uneven_sizes_one_call():
     insts = [wl.make_instance(n, 8600 + n, 3, "uniform") for n in (9, 30, 17, 30)]
     check(insts, 120, 15, "uneven")
