@@ -341,8 +341,7 @@ def c1_shape_tts(binding, torch, workloads, n_inst=120):
     wall = time.perf_counter() - t0
     s.destroy()
     p1 = float(np.mean([gE[0] == eE[0] for (gb, gE), (eb, eE) in zip(res, exact)]))
-    r = float(np.mean([np.mean([int(x) in {int(y) for y in gb[:, 0]} for x in eb[:, 0]])
-                       for (gb, gE), (eb, eE) in zip(res, exact)]))
+    r = float(np.mean([np.isin(eb[:, 0], gb[:, 0]).mean() for (gb, gE), (eb, eE) in zip(res, exact)]))
     t = wall / n_inst
     return {"instances": n_inst, "N": 24, "M": 8, "L": 4, "form": "plain",
             "E_ref": "exact: the GPU enumeration of all 2^24 states", "p1": p1, "r_of_8_lowest": r,
@@ -528,25 +527,30 @@ def bestfirst_studies(binding, torch, workloads, sizes):
     [-1/2, 1/2]; p1 and r against the GPU enumeration's 120 lowest states."""
     import numpy as np
     out = {"per_N": {}, "note": "single: (L, phi_1) = (1, 0), I = K = a K0; multi: L = N random initial "
-                                "states, K = K0, I = a N; K0 = N(N+1)/2 + 1; r = fraction of the 120 lowest "
-                                "states found; times are GPU kernel time per instance"}
+                                "states, K = K0, I = a N; multiK (largest N only): L = N, K = a K0, I = a N; "
+                                "K0 = N(N+1)/2 + 1; r = fraction of the 120 lowest states found; times are GPU "
+                                "kernel time per instance"}
     for N in sizes:
         insts = [workloads.make_instance(N, workloads.seed_for(7, 1000 * N + k), N, "uniform") for k in range(120)]
         Js, hs = [i.J for i in insts], [i.h for i in insts]
         exact = binding.brute_lowest(Js, hs, 120)
+        log(f"[bestfirst] N={N}: the 120 lowest states of 120 instances enumerated")
         K0 = N * (N + 1) // 2 + 1
         rows = {}
-        cfgs = [("single", a, 1, a * K0, a * K0) for a in (1, 2, 3, 10) if a * K0 + 1 <= 2048]
+        cfgs = [("single", a, 1, a * K0, a * K0) for a in (1, 2, 3, 10, 100)]
         cfgs += [("multi", a, N, K0, max(1, int(round(a * N)))) for a in (0.1, 0.2, 0.3, 0.5, 1.0)]
+        if N == max(sizes):
+            cfgs += [("multiK", a, N, a * K0, a * N) for a in (2, 3, 10, 100)]
         for kind, a, L, K, I in cfgs:
             x0s = [[0] for _ in insts] if L == 1 else [i.init_bits[:L, 0] for i in insts]
             res = binding.bestfirst(Js, hs, x0s, K, I)
             p1 = float(np.mean([res["merged"][b][1][0] == exact[b][1][0] for b in range(120)]))
-            r = float(np.mean([np.mean([int(x) in {int(y) for y in res["merged"][b][0][:, 0]}
-                                        for x in exact[b][0][:, 0]]) for b in range(120)]))
+            r = float(np.mean([np.isin(exact[b][0][:, 0], res["merged"][b][0][:, 0]).mean() for b in range(120)]))
             t = res["kernel_ms"] / 1e3 / 120
             rows[f"{kind}_a{a}"] = {"L": L, "K": K, "I": I, "LI": L * I, "p1": p1, "r": r,
                                     "t_per_instance_s": t, "tts_s": tts_of(p1, t)}
+            log(f"[bestfirst] N={N} {kind} a={a}: K={K} I={I} L={L} p1={p1:.3f} r={r:.3f} "
+                f"{res['kernel_ms']:.1f} ms for 120 instances")
         out["per_N"][N] = rows
     return out
 

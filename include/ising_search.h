@@ -429,10 +429,10 @@ int ising_brute_lowest(int32_t n_inst, const int32_t *N, const double *const *J,
  *   L                 searches per instance; init_bits[b] holds L words
  *   K, I              list of K + 1 entries (K + 1 <= 2^20), I >= 0 iterations;
  *                     a search keeps its list, the list's double buffer and
- *                     the offered children in LDS when they fit in 160 KB,
- *                     else in device memory (about 21 (K+1) + 22 C bytes per
- *                     search, C the power of two at least max(K+1, children);
- *                     the same result, more slowly)
+ *                     the hash of its states in LDS when they fit beside the
+ *                     offered children in 160 KB, else in device memory
+ *                     (about 58 (K+1) bytes per search, 78 (K+1) per instance
+ *                     for the merge; the same result, more slowly)
  *   merged_bits/E     caller buffers of n_inst*(K+1): instance b's merged list
  *                     at b*(K+1), merged_count[b] real entries, in list order
  *   search_*          NULL, or caller buffers of n_inst*L*(K+1) (count: n_inst*L)
