@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "../../include/ising_search.h"
+#include "bestfirst.h"
 #include "common.h"
 
 using namespace qi;

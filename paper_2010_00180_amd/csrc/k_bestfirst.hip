@@ -23,7 +23,7 @@
 //
 // The merge of Alg. 4 is the same update with the later searches' lists, in
 // their own order, as the offered entries.
-#include "common.h"
+#include "bestfirst.h"
 
 namespace qi {
 
