@@ -111,15 +111,21 @@ def test_other_h1(flags):
     check(insts, 60, 25, f"h1 flags={flags}", flags=flags)
 
 
-@pytest.mark.parametrize("N,K,I,dist,L", [(64, 2047, 5, "sk", 2), (20, 2110, 2110, "uniform", 1),
-                                         (16, 2740, 2740, "uniform", 1), (14, 3000, 200, "pmj", 2)])
-def test_lists_past_the_lds(N, K, I, dist, L):
-    """Lists too long for the 160 KB of LDS live in device memory, one region
-    per search: K = 10 K0 at N = 20 is the largest list of Sec. IV at that
-    size; pmj keeps exact ties in the long list."""
-    insts = [wl.make_instance(N, 8900 + N + k, L, dist) for k in range(2)]
-    x0s = [[0]] * 2 if L == 1 else None
-    check(insts, K, I, f"global lists N={N} K={K}", x0s=x0s)
+@pytest.mark.parametrize("N,K,I,dist,L,n_inst", [
+    (64, 2047, 5, "sk", 2, 2),             # search lists in device memory, merge in LDS
+    (20, 2110, 2110, "uniform", 1, 2),     # K = 10 K0 at N = 20: search in LDS, merge in device memory
+    (20, 2110, 60, "uniform", 3, 2),       # the same split, with three lists merged
+    (16, 2740, 2740, "uniform", 1, 2),
+    (14, 3000, 200, "pmj", 2, 2),          # both in device memory; exact ties in the long list
+    (24, 3010, 3010, "uniform", 1, 1),     # K = 10 K0 at N = 24: both in device memory
+])
+def test_lists_past_the_lds(N, K, I, dist, L, n_inst):
+    """Lists that do not fit the 160 KB of LDS beside a kernel's other arrays
+    live in device memory, one region per block; each kernel decides on its
+    own, so the search and the merge may differ."""
+    insts = [wl.make_instance(N, 8900 + N + k, L, dist) for k in range(n_inst)]
+    x0s = [[0]] * n_inst if (L == 1 and dist == "uniform" and I == K) else None
+    check(insts, K, I, f"long lists N={N} K={K} L={L}", x0s=x0s)
 
 
 def test_rejects_what_the_kernels_cannot_take():
