@@ -118,6 +118,7 @@ def test_other_h1(flags):
     (16, 2740, 2740, "uniform", 1, 2),
     (14, 3000, 200, "pmj", 2, 2),          # both in device memory; exact ties in the long list
     (24, 3010, 3010, "uniform", 1, 1),     # K = 10 K0 at N = 24: both in device memory
+    (12, 5000, 5000, "uniform", 1, 1),     # a list longer than the 4096 states: every state found and expanded
 ])
 def test_lists_past_the_lds(N, K, I, dist, L, n_inst):
     """Lists that do not fit the 160 KB of LDS beside a kernel's other arrays
