@@ -426,7 +426,8 @@ int ising_brute_lowest(int32_t n_inst, const int32_t *N, const double *const *J,
  * spins give the parent back and are skipped).
  *
  *   n_inst, N, J, h   as for ising_search_init, with 1 <= N[b] <= 64
- *   L                 searches per instance; init_bits[b] holds L words
+ *   L                 searches per instance, n_inst * L <= 2^24; init_bits[b]
+ *                     holds L words (no bits at positions >= N[b])
  *   K, I              list of K + 1 entries (K + 1 <= 2^20), I >= 0 iterations;
  *                     a search keeps its list, the list's double buffer and
  *                     the hash of its states in LDS when they fit beside the
